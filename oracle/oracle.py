@@ -1,0 +1,167 @@
+"""ctypes front end of the plain C oracle (wt_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use this module; the GPU library never does.  It shares no
+code with the library: it loads its own shared object built from
+``wt_oracle.c`` with gcc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "wt_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+RANK_BLOCK_BITS = 512
+SEL_SAMPLE = 4096
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def compile_oracle(out_path: str = LIB, mutant: int | None = None) -> str:
+    """Compile wt_oracle.c with gcc into ``out_path`` (optionally a planted mutant)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", out_path, SRC]
+    if mutant is not None:
+        cmd.insert(1, f"-DORACLE_MUTANT={int(mutant)}")
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
+def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
+    lib.oracle_levels.restype = ctypes.c_uint32
+    lib.oracle_levels.argtypes = [ctypes.c_uint64]
+    lib.oracle_build.restype = ctypes.c_int
+    lib.oracle_build.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                 _u64p, _u64p]
+    lib.oracle_rank_select.restype = ctypes.c_int
+    lib.oracle_rank_select.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint32, _u64p, _u64p, _u64p, _u64p]
+    lib.oracle_access_naive.restype = ctypes.c_uint64
+    lib.oracle_access_naive.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64]
+    lib.oracle_rank_naive.restype = ctypes.c_uint64
+    lib.oracle_rank_naive.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint64]
+    lib.oracle_select_naive.restype = ctypes.c_int64
+    lib.oracle_select_naive.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint64]
+    for name in ("oracle_access_tree",):
+        getattr(lib, name).restype = ctypes.c_uint64
+        getattr(lib, name).argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.oracle_rank_tree.restype = ctypes.c_uint64
+    lib.oracle_rank_tree.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint64]
+    lib.oracle_select_tree.restype = ctypes.c_int64
+    lib.oracle_select_tree.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_uint64]
+    return lib
+
+
+_LIBS: dict[str, ctypes.CDLL] = {}
+
+
+def load(path: str = LIB) -> ctypes.CDLL:
+    """Load (compiling first if needed) the oracle shared object at ``path``."""
+    if path not in _LIBS:
+        if path == LIB and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
+            compile_oracle(LIB)
+        _LIBS[path] = _declare(ctypes.CDLL(path))
+    return _LIBS[path]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_u64p)
+
+
+def levels(sigma: int) -> int:
+    return int(load().oracle_levels(sigma))
+
+
+def sym_bytes_of(S: np.ndarray) -> int:
+    return {np.dtype(np.uint8): 1, np.dtype(np.uint16): 2, np.dtype(np.uint32): 4}[S.dtype]
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """Build bits and C.  Returns {'L', 'W', 'bits' (L, W) uint64, 'C' (sigma+1,) uint64}."""
+    lib = load(lib_path)
+    S = np.ascontiguousarray(S)
+    n = int(S.shape[0])
+    L = int(lib.oracle_levels(sigma))
+    W = (n + 63) // 64
+    bits = np.zeros(max(L * W, 1), dtype=np.uint64)
+    C = np.zeros(sigma + 1, dtype=np.uint64)
+    rc = lib.oracle_build(S.ctypes.data_as(ctypes.c_void_p), n, sigma, sym_bytes_of(S), _ptr(bits), _ptr(C))
+    if rc != 0:
+        raise OracleError(f"oracle_build returned {rc}")
+    return {"L": L, "W": W, "n": n, "sigma": sigma, "bits": bits[: L * W].reshape(L, W), "C": C}
+
+
+def rank_select(bits: np.ndarray, n: int, L: int, lib_path: str = LIB) -> dict:
+    """Directories over (L, W) level bits (see oracle_rank_select for the format)."""
+    lib = load(lib_path)
+    W = (n + 63) // 64
+    flat = np.ascontiguousarray(bits, dtype=np.uint64).reshape(-1)
+    if flat.size == 0:
+        flat = np.zeros(1, dtype=np.uint64)
+    rank_len = (n + RANK_BLOCK_BITS - 1) // RANK_BLOCK_BITS + 1
+    cap = (n + SEL_SAMPLE - 1) // SEL_SAMPLE + 1
+    rank = np.zeros(max(L * rank_len, 1), dtype=np.uint64)
+    sel1 = np.zeros(max(L * cap, 1), dtype=np.uint64)
+    sel0 = np.zeros(max(L * cap, 1), dtype=np.uint64)
+    counts = np.zeros(max(2 * L, 1), dtype=np.uint64)
+    lib.oracle_rank_select(_ptr(flat), n, L, _ptr(rank), _ptr(sel1), _ptr(sel0), _ptr(counts))
+    return {
+        "rank": rank[: L * rank_len].reshape(L, rank_len),
+        "sel1": sel1[: L * cap].reshape(L, cap),
+        "sel0": sel0[: L * cap].reshape(L, cap),
+        "sel_counts": counts[: 2 * L],
+    }
+
+
+def build_all(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    t = build(S, sigma, lib_path)
+    t.update(rank_select(t["bits"], t["n"], t["L"], lib_path))
+    return t
+
+
+# ---- queries ---------------------------------------------------------------
+
+def access_naive(S: np.ndarray, i: int) -> int:
+    return int(load().oracle_access_naive(S.ctypes.data_as(ctypes.c_void_p), sym_bytes_of(S), i))
+
+
+def rank_naive(S: np.ndarray, c: int, i: int) -> int:
+    return int(load().oracle_rank_naive(S.ctypes.data_as(ctypes.c_void_p), sym_bytes_of(S), S.shape[0], c, i))
+
+
+def select_naive(S: np.ndarray, c: int, k: int) -> int:
+    return int(load().oracle_select_naive(S.ctypes.data_as(ctypes.c_void_p), sym_bytes_of(S), S.shape[0], c, k))
+
+
+def _tree_args(t: dict):
+    bits = np.ascontiguousarray(t["bits"], dtype=np.uint64).reshape(-1)
+    if bits.size == 0:
+        bits = np.zeros(1, dtype=np.uint64)
+    return bits, np.ascontiguousarray(t["C"], dtype=np.uint64)
+
+
+def access_tree(t: dict, i: int, lib_path: str = LIB) -> int:
+    bits, C = _tree_args(t)
+    return int(load(lib_path).oracle_access_tree(_ptr(bits), _ptr(C), t["n"], t["sigma"], i))
+
+
+def rank_tree(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
+    bits, C = _tree_args(t)
+    return int(load(lib_path).oracle_rank_tree(_ptr(bits), _ptr(C), t["n"], t["sigma"], c, i))
+
+
+def select_tree(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
+    bits, C = _tree_args(t)
+    return int(load(lib_path).oracle_select_tree(_ptr(bits), _ptr(C), t["n"], t["sigma"], c, k))

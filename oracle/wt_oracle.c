@@ -1,0 +1,416 @@
+/*
+ * wt_oracle.c -- plain, slow, sequential reference for wavelet-tree
+ * construction (Shun, "Parallel Wavelet Tree Construction").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the HIP library, and the library never calls it.
+ *
+ * Everything here is integer arithmetic and single-threaded.  No blocking,
+ * fusion or reordering beyond what the paper states.
+ *
+ * Pins (what this file is checked against, in the CPU test suite):
+ *   - bits: the sortWT closed form (Fig. 2): level l is S stably sorted by
+ *     its top l bits, brute-forced in Python over every tiny input;
+ *   - popcount per level equals the count of symbols with that bit set;
+ *   - C against a histogram computed by numpy;
+ *   - directories against a naive Python popcount / scan;
+ *   - tree-walking access/rank/select against naive counting over S;
+ *   - hand-derived fixtures under tests/golden/;
+ *   - planted mutants of this file (ORACLE_MUTANT) must fail those pins.
+ *
+ * Readings where the paper is silent are listed next to the code below.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_SYMBOL (-2)
+#define OR_ERR_NOMEM (-6)
+
+/* Directory constants of the oracle's reading (the paper fixes none, see
+ * "Parallel Construction of Rank/Select Structures": Jacobson blocks and
+ * Clark samples are sized asymptotically).  One absolute count per 512
+ * bits, one sample per 4096 ones and per 4096 zeros. */
+#define OR_RANK_BLOCK_BITS 512u
+#define OR_SEL_SAMPLE 4096u
+
+/* Read symbol i of a packed little-endian array of sym_bytes-wide symbols. */
+static uint64_t sym_at(const void *S, int sym_bytes, uint64_t i)
+{
+    if (sym_bytes == 1)
+        return ((const uint8_t *)S)[i];
+    if (sym_bytes == 2)
+        return ((const uint16_t *)S)[i];
+    return ((const uint32_t *)S)[i];
+}
+
+/* L = ceil(log2 sigma), computed with integers (Preliminaries: the root
+ * represents [0, 2^ceil(log sigma) - 1]).  sigma = 1 gives L = 0: the
+ * levelWT loop over levels runs zero times (reading: no bitmaps at all). */
+uint32_t oracle_levels(uint64_t sigma)
+{
+    uint32_t L = 0;
+    while (L < 64 && (((uint64_t)1) << L) < sigma)
+        L++;
+    return L;
+}
+
+static void set_bit(uint64_t *words, uint64_t pos)
+{
+    /* Reading of the word layout (the paper only says "bit arithmetic"):
+     * position i lives in word i/64 at bit i%64. */
+    words[pos / 64] |= ((uint64_t)1) << (pos % 64);
+}
+
+static int get_bit(const uint64_t *words, uint64_t pos)
+{
+    return (int)((words[pos / 64] >> (pos % 64)) & 1u);
+}
+
+/* One entry of the node array A of Fig. 1: (start, len, id, range), plus
+ * the smallest symbol of the node's range, lo, which Fig. 1 carries
+ * implicitly through id. */
+typedef struct {
+    uint64_t start, len, id, range, lo;
+} or_node;
+
+/*
+ * Level-by-level construction (levelWT of Fig. 1, run sequentially, i.e.
+ * the serialWT order of the Experiments section).
+ *
+ * S: n symbols of sym_bytes each.  Outputs:
+ *   bits: L*W words, W = ceil(n/64); level l occupies words [l*W, (l+1)*W)
+ *         (the levelwise representation of the Experiments section);
+ *   C:    sigma+1 entries, C[c] = number of symbols < c.  The nodes of level
+ *         l are determined by C (the node holding symbols [a, b] occupies
+ *         positions [C[a], C[b+1]) of every level bitmap it appears in).
+ *
+ * Returns OR_ERR_SYMBOL if some S[i] >= sigma (the paper assumes symbols lie
+ * in [0, sigma); the oracle's reading is to reject other input).
+ */
+int oracle_build(const void *S, uint64_t n, uint64_t sigma, int sym_bytes,
+                 uint64_t *bits, uint64_t *C)
+{
+    if (sigma == 0 || (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4))
+        return OR_ERR_ARG;
+    if (sym_bytes < 4 && sigma > (((uint64_t)1) << (8 * sym_bytes)))
+        return OR_ERR_ARG;
+    if (sym_bytes == 4 && sigma > (((uint64_t)1) << 32))
+        return OR_ERR_ARG;
+
+    for (uint64_t i = 0; i < n; i++)
+        if (sym_at(S, sym_bytes, i) >= sigma)
+            return OR_ERR_SYMBOL;
+
+    /* C[c] = #{i : S[i] < c}: counts, then running sums. */
+    memset(C, 0, (size_t)(sigma + 1) * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; i++)
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 4
+        /* planted mistake: C[c] counts symbols <= c */
+        C[sym_at(S, sym_bytes, i)] += 1;
+#else
+        C[sym_at(S, sym_bytes, i) + 1] += 1;
+#endif
+    for (uint64_t c = 1; c <= sigma; c++)
+        C[c] += C[c - 1];
+
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64;
+    if (L == 0)
+        return OR_OK;
+    memset(bits, 0, (size_t)(L * W) * sizeof(uint64_t));
+    if (n == 0)
+        return OR_OK;
+
+    /* S and S' of Fig. 1, widened to 64 bits. */
+    uint64_t *cur = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    uint64_t *nxt = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    /* X of Fig. 1 (per-node prefix sums of the "left" flags). */
+    uint64_t *X = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    /* A and A' hold at most min(n, 2^l) non-empty nodes. */
+    uint64_t amax = n < (((uint64_t)1) << (L < 40 ? L : 40)) ? n : (((uint64_t)1) << (L < 40 ? L : 40));
+    or_node *A = (or_node *)malloc((size_t)(amax + 1) * sizeof(or_node));
+    or_node *A2 = (or_node *)malloc((size_t)(2 * amax + 2) * sizeof(or_node));
+    if (!cur || !nxt || !X || !A || !A2) {
+        free(cur); free(nxt); free(X); free(A); free(A2);
+        return OR_ERR_NOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++)
+        cur[i] = sym_at(S, sym_bytes, i);
+
+    /* A = {(0, n, 0, 2^L)}: the root covers every position and the symbol
+     * range [0, 2^L - 1]. */
+    uint64_t na = 1;
+    A[0].start = 0;
+    A[0].len = n;
+    A[0].id = 0;
+    A[0].range = ((uint64_t)1) << L;
+    A[0].lo = 0;
+
+    for (uint32_t l = 0; l < L; l++) {
+        uint64_t *B = bits + (uint64_t)l * W;
+        uint64_t na2 = 0;
+        for (uint64_t j = 0; j < na; j++) {
+            const or_node *v = &A[j];
+            /* A node of range [a, b] marks a symbol 0 when it lies in
+             * [a, (a+b+1)/2 - 1] and 1 otherwise (Preliminaries). */
+            uint64_t a = v->lo, b = v->lo + v->range - 1;
+            uint64_t mid = (a + b + 1) / 2;
+            /* Bits of this node (the loops of Fig. 1 that set B). */
+            for (uint64_t i = 0; i < v->len; i++) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 1
+                /* planted mistake: off-by-one midpoint */
+                if (cur[v->start + i] > mid)
+#else
+                if (cur[v->start + i] >= mid)
+#endif
+                    set_bit(B, v->start + i);
+            }
+            if (v->range <= 2)
+                continue; /* no children: the recursion stops at range <= 2 */
+
+            /* X[i] = 1 for symbols going left; exclusive prefix sum gives
+             * their offsets, X_s is the total (Fig. 1). */
+            uint64_t Xs = 0;
+            for (uint64_t i = 0; i < v->len; i++) {
+                uint64_t left = cur[v->start + i] < mid ? 1u : 0u;
+                X[i] = Xs;
+                Xs += left;
+            }
+            for (uint64_t i = 0; i < v->len; i++) {
+                uint64_t s = cur[v->start + i];
+                if (s >= mid) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 2
+                    /* planted mistake: right child written in reverse */
+                    nxt[v->start + v->len - 1 - (i - X[i])] = s;
+#else
+                    nxt[v->start + Xs + i - X[i]] = s;
+#endif
+                } else {
+                    nxt[v->start + X[i]] = s;
+                }
+            }
+            /* Children, ids 2*id+1 and 2*id+2, each of half the range;
+             * empty children are dropped (the filter of Fig. 1). */
+            if (Xs > 0) {
+                or_node *c = &A2[na2++];
+                c->start = v->start;
+                c->len = Xs;
+                c->id = 2 * v->id + 1;
+                c->range = v->range / 2;
+                c->lo = a;
+            }
+            if (v->len - Xs > 0) {
+                or_node *c = &A2[na2++];
+                c->start = v->start + Xs;
+                c->len = v->len - Xs;
+                c->id = 2 * v->id + 2;
+                c->range = v->range / 2;
+                c->lo = mid;
+            }
+        }
+        if (l + 1 < L) {
+            /* swap(S, S') and A <- filtered A' */
+            uint64_t *t = cur;
+            cur = nxt;
+            nxt = t;
+            memcpy(A, A2, (size_t)na2 * sizeof(or_node));
+            na = na2;
+        }
+    }
+    free(cur); free(nxt); free(X); free(A); free(A2);
+    return OR_OK;
+}
+
+/*
+ * Rank/select directories over each level bitmap (section "Parallel
+ * Construction of Rank/Select Structures", in a practical fixed-constant
+ * reading):
+ *   rank[l][j] = number of 1s of B_l in positions [0, min(512 j, n)),
+ *                j = 0 .. ceil(n/512)                      (rank_len entries)
+ *   sel1[l][t] = position of the 1 whose 0-based ordinal is 4096 t,
+ *                t < ceil(ones_l / 4096); the remaining entries up to
+ *                sel_cap = ceil(n/4096) + 1 hold n.  sel0 likewise for 0s.
+ *   sel_counts[l] = ceil(ones_l/4096), sel_counts[L + l] = ceil(zeros_l/4096).
+ */
+int oracle_rank_select(const uint64_t *bits, uint64_t n, uint32_t L,
+                       uint64_t *rank, uint64_t *sel1, uint64_t *sel0,
+                       uint64_t *sel_counts)
+{
+    uint64_t W = (n + 63) / 64;
+    uint64_t rank_len = (n + OR_RANK_BLOCK_BITS - 1) / OR_RANK_BLOCK_BITS + 1;
+    uint64_t cap = (n + OR_SEL_SAMPLE - 1) / OR_SEL_SAMPLE + 1;
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        uint64_t *R = rank + (uint64_t)l * rank_len;
+        uint64_t *P1 = sel1 + (uint64_t)l * cap;
+        uint64_t *P0 = sel0 + (uint64_t)l * cap;
+        uint64_t ones = 0, zeros = 0, t1 = 0, t0 = 0;
+        for (uint64_t t = 0; t < cap; t++) {
+            P1[t] = n;
+            P0[t] = n;
+        }
+        for (uint64_t i = 0; i < n; i++) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 3
+            /* planted mistake: block count includes the bit at the boundary */
+            if (i % OR_RANK_BLOCK_BITS == 0)
+                R[i / OR_RANK_BLOCK_BITS] = ones + (uint64_t)get_bit(B, i);
+#else
+            if (i % OR_RANK_BLOCK_BITS == 0)
+                R[i / OR_RANK_BLOCK_BITS] = ones;
+#endif
+            if (get_bit(B, i)) {
+                if (ones % OR_SEL_SAMPLE == 0)
+                    P1[t1++] = i;
+                ones++;
+            } else {
+                if (zeros % OR_SEL_SAMPLE == 0)
+                    P0[t0++] = i;
+                zeros++;
+            }
+        }
+        R[rank_len - 1] = ones;
+        sel_counts[l] = t1;
+        sel_counts[L + l] = t0;
+    }
+    return OR_OK;
+}
+
+/* ---- queries (Preliminaries) -------------------------------------------
+ * Naive versions over S itself.  Reading of the conventions:
+ *   access(i) = S[i];
+ *   rank(c, i) = number of c in S[0, i)  (the paper counts 0..i inclusive,
+ *                so the paper's rank_c(S, i) is rank(c, i + 1) here);
+ *   select(c, k) = position of the k-th c, k >= 1; -1 when there is none.
+ */
+uint64_t oracle_access_naive(const void *S, int sym_bytes, uint64_t i)
+{
+    return sym_at(S, sym_bytes, i);
+}
+
+uint64_t oracle_rank_naive(const void *S, int sym_bytes, uint64_t n, uint64_t c, uint64_t i)
+{
+    uint64_t r = 0;
+    if (i > n)
+        i = n;
+    for (uint64_t j = 0; j < i; j++)
+        r += sym_at(S, sym_bytes, j) == c;
+    return r;
+}
+
+int64_t oracle_select_naive(const void *S, int sym_bytes, uint64_t n, uint64_t c, uint64_t k)
+{
+    uint64_t seen = 0;
+    if (k == 0)
+        return -1;
+    for (uint64_t j = 0; j < n; j++)
+        if (sym_at(S, sym_bytes, j) == c && ++seen == k)
+            return (int64_t)j;
+    return -1;
+}
+
+/* Tree-walking queries over the oracle's own bits and C, counting bits one
+ * at a time (no directories), so that they test the tree itself. */
+static uint64_t count_ones(const uint64_t *B, uint64_t from, uint64_t to)
+{
+    uint64_t r = 0;
+    for (uint64_t i = from; i < to; i++)
+        r += (uint64_t)get_bit(B, i);
+    return r;
+}
+
+/* Position of the node that holds the symbol range starting at lo. */
+static uint64_t node_start(const uint64_t *C, uint64_t sigma, uint64_t lo)
+{
+    return C[lo < sigma ? lo : sigma];
+}
+
+uint64_t oracle_access_tree(const uint64_t *bits, const uint64_t *C, uint64_t n,
+                            uint64_t sigma, uint64_t i)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64;
+    uint64_t lo = 0, range = ((uint64_t)1) << L, j = i;
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        uint64_t a = node_start(C, sigma, lo);
+        uint64_t half = range / 2;
+        uint64_t ones_before = count_ones(B, a, j);
+        if (get_bit(B, j)) {
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 5
+            /* planted mistake: right child placed at the parent's start */
+            uint64_t child = node_start(C, sigma, lo);
+#else
+            uint64_t child = node_start(C, sigma, lo + half);
+#endif
+            j = child + ones_before;
+            lo += half;
+        } else {
+            j = a + (j - a - ones_before);
+        }
+        range = half;
+    }
+    return lo;
+}
+
+uint64_t oracle_rank_tree(const uint64_t *bits, const uint64_t *C, uint64_t n,
+                          uint64_t sigma, uint64_t c, uint64_t i)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64;
+    uint64_t lo = 0, range = ((uint64_t)1) << L, r;
+    if (c >= sigma)
+        return 0;
+    if (i > n)
+        i = n;
+    r = i; /* elements of the current node that precede the query position */
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        uint64_t a = node_start(C, sigma, lo);
+        uint64_t half = range / 2;
+        uint64_t ones_before = count_ones(B, a, a + r);
+        if (c >= lo + half) {
+            r = ones_before;
+            lo += half;
+        } else {
+            r = r - ones_before;
+        }
+        range = half;
+    }
+    return r;
+}
+
+/* Position of the bit equal to b with 0-based ordinal o among positions
+ * [a, n) of B, by a plain scan. */
+static uint64_t scan_select(const uint64_t *B, uint64_t a, uint64_t n, int b, uint64_t o)
+{
+    for (uint64_t i = a; i < n; i++)
+        if (get_bit(B, i) == b && o-- == 0)
+            return i;
+    return n;
+}
+
+int64_t oracle_select_tree(const uint64_t *bits, const uint64_t *C, uint64_t n,
+                           uint64_t sigma, uint64_t c, uint64_t k)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64;
+    if (c >= sigma || k == 0 || k > C[c + 1] - C[c])
+        return -1;
+    /* Ascend from the leaf of c: r is the 0-based index inside the child. */
+    uint64_t r = k - 1;
+    for (uint32_t d = L; d-- > 0;) {
+        const uint64_t *B = bits + (uint64_t)d * W;
+        uint64_t range = ((uint64_t)1) << (L - d);
+        uint64_t lo = (c / range) * range;
+        uint64_t a = node_start(C, sigma, lo);
+        int b = c >= lo + range / 2;
+        uint64_t j = scan_select(B, a, n, b, r);
+        r = j - a;
+    }
+    return (int64_t)r;
+}

@@ -1,0 +1,157 @@
+"""Seeded synthetic workloads.
+
+This module only draws random symbols; it holds none of the wavelet-tree
+arithmetic.  It serves the tests, the smoke check and the benchmark alike.
+
+Workloads (the paper's real corpora are not available; these stand in for the
+shapes of its inputs -- text with alphabets up to 256, random inputs with
+sigma = 2^k, and a document-id array with a large alphabet):
+
+  1  uniform:       n = 2^20 uint8, sigma = 256, i.i.d. uniform
+  2  text-like:     n = 2^28 uint8, sigma = 256; runs whose symbol follows
+                    Zipf(1.1) over a seeded permutation of the byte alphabet
+                    and whose length is geometric with mean 4
+  3  large-alpha:   n = 2^27 uint32, sigma in {2^16, 2^20}; the first half
+                    uniform, the second half Zipf(1.0) over a seeded
+                    permutation of [0, sigma) (concatenated in one input)
+  4  batch:         4096 sequences, n = floor(2^U), U ~ U[10, 20], sigma drawn
+                    from {4, 256, 2^16} (uint8, uint8, uint16), uniform symbols
+  5  serving:       Poisson arrivals (mean gap 0.5 ms), n = floor(2^U) with
+                    U ~ U[12, 26], sigma = floor(2^U) with U ~ U[2, 20],
+                    narrowest symbol width, Zipf(1.1) symbols over a seeded
+                    permutation of [0, sigma)
+
+Seeds are 1407 * 1000 + workload id (plus a sequence index for 4 and 5).
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass
+
+import numpy as np
+
+SEED_BASE = 1407 * 1000
+
+
+def rng_for(workload: int, index: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + workload + index))
+
+
+def sha256(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).view(np.uint8)).hexdigest()
+
+
+def dtype_for_sigma(sigma: int):
+    if sigma <= 1 << 8:
+        return np.uint8
+    if sigma <= 1 << 16:
+        return np.uint16
+    return np.uint32
+
+
+def zipf_symbols(rng: np.random.Generator, count: int, ranks: int, s: float,
+                 perm: np.ndarray, dtype, chunk: int = 1 << 24) -> np.ndarray:
+    """``count`` draws from a truncated Zipf(s) over ``ranks`` ranks (P(r) ~ r^-s,
+    r = 1..ranks), mapped to symbols through ``perm`` (inverse-CDF sampling)."""
+    w = np.arange(1, ranks + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    out = np.empty(count, dtype=dtype)
+    for lo in range(0, count, chunk):
+        hi = min(count, lo + chunk)
+        u = rng.random(hi - lo)
+        r = np.searchsorted(cdf, u, side="right")
+        np.minimum(r, ranks - 1, out=r)
+        out[lo:hi] = perm[r]
+    return out
+
+
+def uniform(n: int = 1 << 20, sigma: int = 256, seed_workload: int = 1, index: int = 0,
+            dtype=None) -> np.ndarray:
+    rng = rng_for(seed_workload, index)
+    dt = dtype or dtype_for_sigma(sigma)
+    return rng.integers(0, sigma, n, dtype=np.uint64).astype(dt)
+
+
+def text_like(n: int = 1 << 28, sigma: int = 256, s: float = 1.1, mean_run: float = 4.0,
+              index: int = 0) -> np.ndarray:
+    """Runs of repeated symbols: symbol ~ Zipf(s) over a permuted alphabet,
+    run length ~ Geometric(1/mean_run) (support >= 1)."""
+    rng = rng_for(2, index)
+    perm = rng.permutation(sigma).astype(np.uint64)
+    dt = dtype_for_sigma(sigma)
+    out = np.empty(n, dtype=dt)
+    filled = 0
+    while filled < n:
+        runs = max(1024, int((n - filled) / mean_run * 1.05) + 1024)
+        runs = min(runs, 1 << 24)
+        syms = zipf_symbols(rng, runs, sigma, s, perm, dt)
+        lens = rng.geometric(1.0 / mean_run, runs)
+        piece = np.repeat(syms, lens)
+        take = min(n - filled, piece.shape[0])
+        out[filled:filled + take] = piece[:take]
+        filled += take
+    return out
+
+
+def large_alphabet(n: int = 1 << 27, sigma: int = 1 << 20, index: int = 0) -> np.ndarray:
+    """First half uniform over [0, sigma), second half Zipf(1.0) over a permuted [0, sigma)."""
+    rng = rng_for(3, index)
+    half = n // 2
+    a = rng.integers(0, sigma, half, dtype=np.uint64).astype(np.uint32)
+    perm = rng.permutation(sigma).astype(np.uint32)
+    b = zipf_symbols(rng, n - half, sigma, 1.0, perm, np.uint32)
+    return np.concatenate([a, b])
+
+
+@dataclass
+class BatchSeq:
+    S: np.ndarray
+    sigma: int
+
+
+def batch(count: int = 4096, lo_exp: float = 10.0, hi_exp: float = 20.0,
+          sigmas=(4, 256, 1 << 16), index: int = 0) -> list[BatchSeq]:
+    rng = rng_for(4, index)
+    out = []
+    for _ in range(count):
+        n = int(np.floor(2.0 ** rng.uniform(lo_exp, hi_exp)))
+        sigma = int(sigmas[rng.integers(0, len(sigmas))])
+        S = rng.integers(0, sigma, n, dtype=np.uint64).astype(dtype_for_sigma(sigma))
+        out.append(BatchSeq(S, sigma))
+    return out
+
+
+@dataclass
+class Request:
+    arrival_s: float
+    S: np.ndarray
+    sigma: int
+
+
+def serving_requests(count: int, mean_gap_s: float = 0.5e-3, n_exp=(12.0, 26.0),
+                     sigma_exp=(2.0, 20.0), s: float = 1.1, index: int = 0) -> list[Request]:
+    rng = rng_for(5, index)
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += float(rng.exponential(mean_gap_s))
+        n = int(np.floor(2.0 ** rng.uniform(*n_exp)))
+        sigma = max(1, int(np.floor(2.0 ** rng.uniform(*sigma_exp))))
+        perm = rng.permutation(sigma).astype(np.uint64)
+        S = zipf_symbols(rng, n, sigma, s, perm, dtype_for_sigma(sigma))
+        out.append(Request(t, S, sigma))
+    return out
+
+
+def workload(cfg: str, n: int | None = None):
+    """(S, sigma) for a named single-build workload; ``n`` overrides the length."""
+    if cfg == "uniform256":
+        return uniform(n or (1 << 20), 256), 256
+    if cfg == "text256":
+        return text_like(n or (1 << 28)), 256
+    if cfg == "alpha16":
+        return large_alphabet(n or (1 << 27), 1 << 16), 1 << 16
+    if cfg == "alpha20":
+        return large_alphabet(n or (1 << 27), 1 << 20), 1 << 20
+    raise KeyError(cfg)

@@ -1,0 +1,180 @@
+"""CPU tests that pin the oracle to facts other than itself (no GPU needed)."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import pins
+from oracle import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "handworked.json")
+
+
+def _tree_with_dirs(S, sigma, lib_path=oracle.LIB):
+    return oracle.build_all(np.asarray(S), sigma, lib_path)
+
+
+def _dtype(sigma):
+    return np.uint8 if sigma <= 256 else (np.uint16 if sigma <= 65536 else np.uint32)
+
+
+def query_failures(t, S, sigma, lib_path=oracle.LIB):
+    """Exhaustive tree-walk queries against naive counting over S."""
+    n = S.shape[0]
+    for i in range(n):
+        if oracle.access_tree(t, i, lib_path) != int(S[i]):
+            return ["access_tree"]
+    for c in range(sigma + 1):
+        for i in range(n + 1):
+            if oracle.rank_tree(t, c, i, lib_path) != pins.naive_rank(S, c, i):
+                return ["rank_tree"]
+        if c < sigma:
+            for k in range(n + 2):
+                if oracle.select_tree(t, c, k, lib_path) != pins.naive_select(S, c, k):
+                    return ["select_tree"]
+    return []
+
+
+def test_golden_handworked():
+    doc = json.load(open(GOLDEN))
+    for case in doc["cases"]:
+        sigma = case["sigma"]
+        S = np.asarray(case["S"], dtype=_dtype(sigma))
+        t = _tree_with_dirs(S, sigma)
+        assert t["L"] == len(case["levels"]), case["name"]
+        for l, row in enumerate(case["levels"]):
+            assert list(pins.unpack(t["bits"][l], len(S))) == row, (case["name"], l)
+            assert [int(w) for w in t["bits"][l]] == case["words"][l], (case["name"], l)
+        assert [int(x) for x in t["C"]] == case["C"], case["name"]
+        for c, i, want in case["rank"]:
+            assert oracle.rank_tree(t, c, i) == want, (case["name"], c, i)
+            assert oracle.rank_naive(S, c, i) == want
+        for c, k, want in case["select"]:
+            assert oracle.select_tree(t, c, k) == want, (case["name"], c, k)
+            assert oracle.select_naive(S, c, k) == want
+        for i, s in enumerate(case["S"]):
+            assert oracle.access_tree(t, i) == s
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 3, 4, 5])
+def test_exhaustive_tiny(sigma):
+    """Every sequence of length <= 5 (<= 4 for the query sweep) over [0, sigma)."""
+    for n in range(0, 6):
+        for tup in itertools.product(range(sigma), repeat=n):
+            S = np.asarray(tup, dtype=np.uint8)
+            t = _tree_with_dirs(S, sigma)
+            exp = pins.sortwt_levels_py(list(tup), sigma)
+            fails = pins.check_tree(t, S, sigma, exp)
+            assert not fails, (tup, fails)
+            if n <= 4:
+                assert not query_failures(t, S, sigma), tup
+
+
+@pytest.mark.parametrize("sigma", [6, 7, 8, 9, 16, 17])
+def test_exhaustive_short_wider_alphabets(sigma):
+    for n in range(0, 4):
+        for tup in itertools.product(range(sigma), repeat=n):
+            S = np.asarray(tup, dtype=np.uint8)
+            t = _tree_with_dirs(S, sigma)
+            assert not pins.check_tree(t, S, sigma, pins.sortwt_levels_py(list(tup), sigma)), tup
+
+
+@pytest.mark.parametrize("n,sigma,seed", [
+    (1000, 3, 1), (4095, 146, 2), (4097, 256, 3), (10000, 256, 4), (513, 1 << 16, 5),
+    (10000, 1 << 16, 6), (9000, (1 << 20) - 3, 7), (8193, 1 << 20, 8), (20000, 5, 9), (70000, 2, 10),
+])
+def test_random_medium(n, sigma, seed):
+    rng = np.random.default_rng(seed)
+    S = rng.integers(0, sigma, n).astype(_dtype(sigma))
+    t = _tree_with_dirs(S, sigma)
+    assert not pins.check_tree(t, S, sigma)
+
+
+def test_random_medium_skewed_and_queries():
+    rng = np.random.default_rng(11)
+    sigma = 200
+    S = np.minimum(rng.zipf(1.3, 3000) - 1, sigma - 1).astype(np.uint8)
+    t = _tree_with_dirs(S, sigma)
+    assert not pins.check_tree(t, S, sigma)
+    for i in rng.integers(0, S.size, 50):
+        assert oracle.access_tree(t, int(i)) == int(S[i])
+    for _ in range(50):
+        c, i = int(rng.integers(0, sigma + 3)), int(rng.integers(0, S.size + 2))
+        assert oracle.rank_tree(t, c, i) == pins.naive_rank(S, c, i)
+        k = int(rng.integers(0, 40))
+        if c < sigma:
+            assert oracle.select_tree(t, c, k) == pins.naive_select(S, c, k)
+
+
+def test_special_cases():
+    rng = np.random.default_rng(12)
+    # sigma = 2: B_0 is S itself.
+    S = rng.integers(0, 2, 777).astype(np.uint8)
+    t = oracle.build(S, 2)
+    assert np.array_equal(pins.unpack(t["bits"][0], S.size), S)
+    # Constant input c: every level is the constant bit of c.
+    for c, sigma in [(0, 256), (255, 256), (77, 100), (4, 5)]:
+        S = np.full(1000, c, dtype=np.uint8)
+        t = oracle.build(S, sigma)
+        L = pins.levels(sigma)
+        for l in range(L):
+            assert set(pins.unpack(t["bits"][l], S.size)) == {(c >> (L - 1 - l)) & 1}
+    # Sorted input: every S_l equals S, so B_l[i] is bit L-1-l of S[i].
+    S = np.sort(rng.integers(0, 1000, 3000)).astype(np.uint16)
+    t = oracle.build(S, 1000)
+    for l in range(t["L"]):
+        assert np.array_equal(pins.unpack(t["bits"][l], S.size), (S >> (t["L"] - 1 - l)) & 1)
+    # sigma = 1: no levels at all.
+    t = oracle.build(np.zeros(10, dtype=np.uint8), 1)
+    assert t["L"] == 0 and t["bits"].size == 0 and list(t["C"]) == [0, 10]
+    # n = 0.
+    t = oracle.build_all(np.zeros(0, dtype=np.uint8), 256)
+    assert t["bits"].size == 0 and not t["C"].any()
+    assert t["rank"].shape == (8, 1) and not t["rank"].any()
+    assert t["sel1"].shape == (8, 1) and not t["sel1"].any() and not t["sel_counts"].any()
+
+
+def test_levels_integer():
+    assert [pins.levels(s) for s in (1, 2, 3, 4, 5, 255, 256, 257)] == [0, 1, 2, 2, 3, 8, 8, 9]
+    for s in (1, 2, 3, 4, 5, 255, 256, 257, (1 << 20) - 1, 1 << 20, (1 << 20) + 1, 1 << 31, (1 << 31) + 1,
+              1 << 32):
+        assert oracle.levels(s) == pins.levels(s)
+
+
+def test_error_paths():
+    with pytest.raises(oracle.OracleError):
+        oracle.build(np.asarray([0, 1, 5], dtype=np.uint8), 5)
+    with pytest.raises(oracle.OracleError):
+        oracle.build(np.asarray([0], dtype=np.uint8), 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.build(np.asarray([0], dtype=np.uint8), 257)
+
+
+def _pin_failures(lib_path):
+    """Run every pin on a few inputs through the oracle built at lib_path."""
+    fails = set()
+    rng = np.random.default_rng(13)
+    cases = [(np.asarray(c, dtype=np.uint8), s) for c, s in [
+        ([3, 1, 0, 2, 3, 0, 1, 2], 4), ([4, 0, 3, 1, 4, 2], 5)]]
+    cases.append((rng.integers(0, 256, 5000).astype(np.uint8), 256))
+    cases.append((rng.integers(0, 13, 700).astype(np.uint8), 13))
+    for S, sigma in cases:
+        try:
+            t = _tree_with_dirs(S, sigma, lib_path)
+        except oracle.OracleError:
+            fails.add("error")
+            continue
+        fails.update(pins.check_tree(t, S, sigma))
+        if S.size <= 8:
+            fails.update(query_failures(t, S, sigma, lib_path))
+    return fails
+
+
+def test_pins_catch_planted_mutants(tmp_path):
+    assert _pin_failures(oracle.LIB) == set()
+    for m in (1, 2, 3, 4, 5):
+        path = str(tmp_path / f"liboracle_m{m}.so")
+        oracle.compile_oracle(path, mutant=m)
+        assert _pin_failures(path), f"mutant {m} passed every pin"
