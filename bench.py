@@ -1,0 +1,179 @@
+"""Benchmark: one step = one full wt_build (validation + histogram + C +
+node tables + every level pass with rank/select directories) of a synthetic
+sequence already resident in HBM.
+
+Prints ONE JSON line.  Default workload: text-like n = 2^28 uint8, sigma = 256
+(Zipf(1.1) symbols over a permuted byte alphabet, geometric runs of mean 4).
+
+  python bench.py [--steps K] [--warmup W] [--workload text256|uniform256|alpha16|alpha20]
+                  [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "symbols*levels/s and % HBM peak; batched vs per-seq builds, bit-exact"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_pass.json")
+LEVEL_PASS_SOURCES = [os.path.join(ROOT, "paper_1407_8142_amd", "csrc", f) for f in ("wt_build.hip", "wt_device.hpp")]
+
+WORKLOADS = {
+    "text256": ("text-like: n=2^28 uint8, sigma=256, Zipf(1.1) over a permuted byte alphabet, geometric runs "
+                "(mean 4)", 1 << 28),
+    "uniform256": ("uniform: n=2^20 uint8, sigma=256, i.i.d.", 1 << 20),
+    "alpha16": ("large alphabet: n=2^27 uint32, sigma=2^16, half uniform, half Zipf(1.0) word-id-like", 1 << 27),
+    "alpha20": ("large alphabet: n=2^27 uint32, sigma=2^20, half uniform, half Zipf(1.0) word-id-like", 1 << 27),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for p in LEVEL_PASS_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int) -> list[float]:
+    """Algorithmic HBM bytes of each level-pass launch: read the level's
+    sequence, write the next one (not on the last level), write the level
+    bits (n/8), the rank directory (8 B per 512 bits) and select samples
+    (8 B per 4096 ones and per 4096 zeros)."""
+    out = []
+    for l in range(L):
+        rd = in_bytes if l == 0 else mid_bytes
+        wr = mid_bytes if l + 1 < L else 0
+        out.append(n * (rd + wr) + n / 8 + n / 64 + n / 256)
+    return out
+
+
+def traffic_per_launch(workload: str):
+    """Measured HBM bytes per level-pass launch from committed rocprofv3
+    counter runs, or None when absent or taken on different kernel sources."""
+    try:
+        doc = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = doc.get(workload)
+    if not ent or ent.get("source_sha256") != source_sha():
+        return None
+    return ent.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(S, sigma, L, sample_n):
+    from oracle import oracle
+    sub = S[:sample_n].copy()
+    t0 = time.perf_counter()
+    t = oracle.build(sub, sigma)
+    oracle.rank_select(t["bits"], t["n"], t["L"])
+    dt = time.perf_counter() - t0
+    return {"value": sample_n * L / dt, "unit": "symbols*levels/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_n} symbols of the same workload, bits + C + rank/select, single thread, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="text256", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=None, help="override the sequence length")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 27)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1407_8142_amd import inputs, wt
+
+    desc, n_default = WORKLOADS[args.workload]
+    n = args.n or n_default
+    log(f"[bench] generating {args.workload} n={n}")
+    S, sigma = inputs.workload(args.workload, n)
+    L = wt.plan(n, sigma, S.dtype.itemsize).L
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d_seq = wt.to_device(S, dev)
+    tree = wt.WaveletTree.allocate(n, sigma, S.dtype.itemsize, True, dev)
+    stream = torch.cuda.current_stream()
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        tree.build_from(d_seq)
+    torch.cuda.synchronize()
+    if tree.status() != wt.WT_OK:
+        raise SystemExit("input rejected by wt_build")
+    wt.timing_collect()
+
+    log(f"[bench] timing {args.steps} steps")
+    wt.timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        tree.build_from(d_seq)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    wt.timing_enable(False)
+    ms_total = ev0.elapsed_time(ev1)
+    launches = wt.timing_collect()
+    ms_per_step = ms_total / args.steps
+    value = n * L * args.steps / (ms_total / 1e3)
+    log(f"[bench] {ms_per_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step), {value:.3e} sym*lvl/s")
+
+    mid = 1 if L <= 8 else (2 if L <= 16 else 4)
+    per_level = level_pass_bytes(n, L, S.dtype.itemsize, mid)
+    assert len(launches) == L * args.steps, (len(launches), L, args.steps)
+    lp_ms = sum(launches)
+    lp_bytes = sum(per_level) * args.steps
+    avg_launch_ms = lp_ms / len(launches)
+    avg_bytes = lp_bytes / len(launches)
+    achieved = avg_bytes / (avg_launch_ms / 1e3) / 1e9
+    per_level_ms = [sum(launches[l::L]) / args.steps for l in range(L)]
+    log("[bench] level-pass ms per level: " + " ".join(f"{x:.4f}" for x in per_level_ms))
+    traffic = traffic_per_launch(args.workload if n == n_default else "")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "level_pass (all levels)", "avg_launch_ms": round(avg_launch_ms, 5),
+            "algorithmic_bytes_per_launch": round(avg_bytes), "level_pass_share_of_step":
+                round(lp_ms / ms_total, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, n)
+        log(f"[bench] cpu baseline: oracle on {sample} symbols")
+        cpu = cpu_baseline(S, sigma, L, sample)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "symbols*levels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {1: "u8", 2: "u16", 4: "u32"}[S.dtype.itemsize], "data": "synthetic",
+        "config": {"workload": desc if n == n_default else f"{desc} (n overridden to {n})", "n": n,
+                   "sigma": sigma, "levels": L, "sym_bytes": S.dtype.itemsize, "directories": True,
+                   "input_sha256": inputs.sha256(S)[:16]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/*
+ * wt.h -- C ABI of the MI355X (gfx950) wavelet-tree construction library.
+ *
+ * The library builds the levelwise wavelet tree of Shun, "Parallel Wavelet
+ * Tree Construction" (the levelWT algorithm, Fig. 1 of section "Parallel
+ * Wavelet Tree Construction"), plus rank/select directories over every level
+ * bitmap (section "Parallel Construction of Rank/Select Structures"), and
+ * answers access/rank/select queries (defined in section "Preliminaries").
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are device pointers (HIP device memory).  The caller
+ *     owns every buffer; the library never allocates or frees on these paths.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *     asynchronous on that stream; argument errors are returned synchronously.
+ *   - Return value: WT_OK or a negative wt_status code.  Data errors found
+ *     on the device (a symbol >= sigma) are written to a status word in the
+ *     scratch buffer and read back with wt_status_get; outputs are then
+ *     unspecified.
+ *   - Calls on different streams may run concurrently only when they use
+ *     disjoint scratch and output buffers.
+ *
+ * Definitions (L = ceil(log2 sigma), 0 when sigma = 1; k_l = L-1-l)
+ *   - The root covers the symbol range [0, 2^L - 1]; a node of range [a, b]
+ *     marks a symbol 0 iff it is <= (a+b+1)/2 - 1 (Preliminaries).  Level l
+ *     of the levelwise representation is one n-bit bitmap holding the nodes
+ *     of depth l in order; equivalently B_l[i] is bit k_l of the i-th symbol
+ *     of S stably sorted by its top l bits (sortWT, Fig. 2).
+ *   - Bits are LSB-first in 64-bit words: position i is bit i%64 of word
+ *     i/64 of its level; padding bits are 0.  Level l occupies words
+ *     [l*W, (l+1)*W), W = ceil(n/64).
+ *   - Node offsets are exported as C[0..sigma], C[c] = #{i : S[i] < c}.  The
+ *     node p of level l (heap id 2^l - 1 + p, as in Fig. 2) covers positions
+ *     [C[min(p*2^(L-l), sigma)], C[min((p+1)*2^(L-l), sigma)]) of B_l; it is
+ *     empty when that range is.
+ */
+#ifndef WT_H
+#define WT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WT_OK = 0,
+    WT_ERR_ARG = -1,     /* invalid argument (null pointer, bad width, sigma out of range, misalignment) */
+    WT_ERR_SYMBOL = -2,  /* some S[i] >= sigma (reported by wt_status_get) */
+    WT_ERR_SCRATCH = -3, /* scratch buffer smaller than the plan requires */
+    WT_ERR_RANGE = -4,   /* size beyond what the library supports */
+    WT_ERR_HIP = -5,     /* a HIP call or kernel launch failed */
+    WT_ERR_NOMEM = -6    /* host-side allocation failed */
+} wt_status;
+
+/* Directory format constants (a practical reading of Jacobson's rank and
+ * Clark's select: absolute counts per 512 bits, a sample per 4096 ones and
+ * per 4096 zeros; hardware popcount replaces the lookup tables). */
+#define WT_RANK_BLOCK_BITS 512
+#define WT_SELECT_SAMPLE 4096
+
+/* Sizes of every buffer, a pure function of (n, sigma, sym_bytes). */
+typedef struct {
+    uint64_t n, sigma;
+    uint32_t L;               /* levels = ceil(log2 sigma) */
+    uint32_t sym_bytes;       /* input width: 1, 2 or 4 */
+    uint64_t words_per_level; /* W = ceil(n/64) */
+    uint64_t bits_words;      /* L*W            -> uint64 bits[L][W]        */
+    uint64_t C_len;           /* sigma+1        -> uint64 C[sigma+1]        */
+    uint64_t rank_len;        /* ceil(n/512)+1  -> uint64 rank[L][rank_len] */
+    uint64_t sel_cap;         /* ceil(n/4096)+1 -> uint64 sel1/sel0[L][sel_cap] */
+    uint64_t sel_counts_len;  /* 2L             -> uint64 sel_counts[2L]    */
+    uint64_t scratch_bytes;   /* device scratch needed by wt_build          */
+    uint64_t rs_scratch_bytes;/* device scratch needed by wt_build_rank_select */
+} wt_layout;
+
+/* Output buffers of wt_build (device pointers).  bits and C are required
+ * (bits may be NULL when L = 0).  The four directory pointers are either all
+ * NULL (no directories) or all non-NULL (directories emitted by the level
+ * passes themselves). */
+typedef struct {
+    uint64_t *bits;       /* [L][W]                                            */
+    uint64_t *C;          /* [sigma+1]                                         */
+    uint64_t *rank;       /* [L][rank_len]: rank[l][j] = ones of B_l in [0, min(512 j, n)) */
+    uint64_t *sel1;       /* [L][sel_cap]: sel1[l][t] = position of the 1 with 0-based ordinal 4096 t;
+                             entries t >= sel_counts[l] hold n                 */
+    uint64_t *sel0;       /* [L][sel_cap]: the same over the 0s                */
+    uint64_t *sel_counts; /* [2L]: ceil(ones_l/4096) for l < L, then ceil(zeros_l/4096) */
+} wt_outputs;
+
+/* Fill *out with the sizes for (n, sigma, sym_bytes).
+ * Valid: sigma >= 1; sym_bytes in {1, 2, 4}; sigma <= 2^(8*sym_bytes);
+ * n < 2^40.  Returns WT_ERR_ARG / WT_ERR_RANGE otherwise. */
+int wt_plan(uint64_t n, uint64_t sigma, int sym_bytes, wt_layout *out);
+
+/* Build the tree of d_seq[0..n) (levelWT, Fig. 1): C, every level bitmap
+ * and, when requested, the rank/select directories.
+ *   d_seq:   n symbols of sym_bytes each, 16-byte aligned; not modified.
+ *   out:     host struct of device output pointers (see wt_outputs).
+ *   d_scratch: >= wt_plan().scratch_bytes bytes, 256-byte aligned; its
+ *            contents on entry do not matter; it holds the status word
+ *            afterwards (see wt_status_get).
+ * Asynchronous on `stream`. */
+int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes,
+             const wt_outputs *out, void *d_scratch, uint64_t scratch_bytes, void *stream);
+
+/* Build the rank/select directories of existing level bitmaps
+ * d_bits[L][ceil(n/64)] (section "Parallel Construction of Rank/Select
+ * Structures": a prefix sum for rank, prefix sum + filter for select).
+ * Output layout as in wt_outputs.  d_scratch needs
+ * wt_plan().rs_scratch_bytes (or wt_rank_select_scratch_bytes(n, L)). */
+int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t L,
+                         uint64_t *d_rank, uint64_t *d_sel1, uint64_t *d_sel0,
+                         uint64_t *d_sel_counts, void *d_scratch, uint64_t scratch_bytes,
+                         void *stream);
+
+uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L);
+
+/* Wait for `stream`, then return WT_OK or the data error recorded by the
+ * last wt_build that used d_scratch (WT_ERR_SYMBOL). */
+int wt_status_get(const void *d_scratch, void *stream);
+
+/* A built tree: device pointers to the outputs of wt_build (with
+ * directories) plus its sizes. */
+typedef struct {
+    const uint64_t *bits, *C, *rank, *sel1, *sel0, *sel_counts;
+    uint64_t n, sigma;
+    uint32_t L;
+} wt_view;
+
+/* Batched queries (Preliminaries), one result per query, m queries.
+ * wt_access: d_sym[j] = S[d_i[j]]; d_i[j] >= n gives 0xFFFFFFFF.
+ * wt_rank:   d_out[j] = number of c = d_c[j] in S[0, min(d_i[j], n))
+ *            (the paper's inclusive rank_c(S, i) is wt_rank(c, i+1));
+ *            c >= sigma gives 0.
+ * wt_select: d_out[j] = position of the d_k[j]-th (1-based) c = d_c[j] in S,
+ *            or -1 when k = 0, c >= sigma or there are fewer than k.
+ * Queries never fail asynchronously. */
+int wt_access(const wt_view *t, const uint64_t *d_i, uint64_t m, uint32_t *d_sym, void *stream);
+int wt_rank(const wt_view *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t m,
+            uint64_t *d_out, void *stream);
+int wt_select(const wt_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
+              int64_t *d_out, void *stream);
+
+/* Kernel timing for measurement tools.  While enabled, wt_build brackets
+ * every level-pass launch with a pair of HIP events on its stream.
+ * wt_timing_collect waits for the recorded events, writes up to `cap`
+ * durations in milliseconds (launch order) and returns how many launches
+ * were recorded since the previous collect (or a negative wt_status). */
+int wt_timing_enable(int enable);
+int wt_timing_collect(float *ms, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WT_H */

@@ -1,0 +1,775 @@
+// Wavelet-tree construction on gfx950: levelWT (Fig. 1 of "Parallel Wavelet
+// Tree Construction") as one HBM pass per level, plus rank/select directories.
+//
+// Pipeline of wt_build on one stream:
+//   zero_fill      status word, look-back tile states, tickets, C
+//   histogram      counts of every symbol into C[1..sigma] and the symbol check
+//   scan (C)       C[c] = #{S[i] < c}, a device-wide prefix sum
+//   node tables    per level l and node p: D_l[2p] = ones of B_l before node p,
+//                  D_l[2p+1] = zeros of B_l before node p+1 (from C alone)
+//   level_pass x L one kernel per level: bit extraction into B_l (wave
+//                  ballots), zero-count scan with decoupled look-back, stable
+//                  split of every node (Fig. 1 left/right offsets) staged in
+//                  LDS and scattered to S_{l+1}; optionally the directory
+//                  entries of B_l; the last level writes bits only.
+//   dir_finish     per-level directory tails and counts (from the tables)
+//
+// Node offsets come from C rather than from Fig. 1's node list: the node of
+// a symbol at level l is its top l bits (the observation behind sortWT and
+// FEFS), so every node boundary of every level is known once C is known.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/wt.h"
+#include "wt_device.hpp"
+
+namespace wt {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;       // positions per tile
+constexpr int kTileWords = kTile / 64;       // level words per tile (= one wave)
+constexpr int kWaves = kBlock / kWave;
+constexpr int kScanChunk = kBlock * kItems;  // elements per block in the generic scans
+static_assert(kTileWords == kWave, "one wave must own the words of a tile");
+
+constexpr uint32_t kStatusSymbol = 2u;
+
+__host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline uint64_t align_up(uint64_t a, uint64_t b) { return cdiv(a, b) * b; }
+
+// ---------------------------------------------------------------------------
+// zero_fill: clears up to two word ranges.
+__global__ void zero_fill(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb; i += stride) {
+        if (i < na) a[i] = 0;
+        else b[i - na] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// histogram: counts into Cp1[c] = C[c+1] (zeroed).  Each thread reads 16
+// bytes at a time and merges runs of equal symbols before counting, which
+// keeps atomics off the hot symbol of skewed text.  Small alphabets count in
+// LDS (kRep replicas indexed by lane to spread same-address atomics).
+template <typename T>
+__device__ __forceinline__ void hist_flush(uint32_t *s_hist, uint64_t *Cp1, bool lds, uint32_t sym,
+                                           uint32_t cnt) {
+    if (cnt == 0) return;
+    if (lds) atomicAdd(s_hist + sym, cnt);
+    else atomicAdd((unsigned long long *)(Cp1 + sym), (unsigned long long)cnt);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
+                                                    uint64_t *Cp1, uint32_t *status, uint32_t reps) {
+    extern __shared__ uint32_t s_hist_all[];
+    const bool lds = reps > 0;
+    const int tid = threadIdx.x;
+    if (lds) {
+        for (uint64_t i = tid; i < sigma * reps; i += kBlock) s_hist_all[i] = 0;
+        __syncthreads();
+    }
+    uint32_t *s_hist = lds ? s_hist_all + (uint64_t)(tid % reps) * sigma : nullptr;
+    constexpr int V = 16 / sizeof(T);
+    const uint64_t nvec = n / V;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    bool bad = false;
+    uint32_t cur = 0xFFFFFFFFu, cnt = 0;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + tid; v < nvec; v += stride) {
+        union {
+            uint4 q;
+            T e[V];
+        } u;
+        u.q = *(const uint4 *)(S + v * V);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            uint32_t s = (uint32_t)u.e[j];
+            if ((uint64_t)s >= sigma) {
+                bad = true;
+                continue;
+            }
+            if (s != cur) {
+                hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
+                cur = s;
+                cnt = 0;
+            }
+            ++cnt;
+        }
+    }
+    for (uint64_t i = nvec * V + (uint64_t)blockIdx.x * kBlock + tid; i < n; i += stride) {
+        uint32_t s = (uint32_t)S[i];
+        if ((uint64_t)s >= sigma) {
+            bad = true;
+            continue;
+        }
+        if (s != cur) {
+            hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
+            cur = s;
+            cnt = 0;
+        }
+        ++cnt;
+    }
+    hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
+    if (bad) atomicMax(status, kStatusSymbol);
+    if (lds) {
+        __syncthreads();
+        for (uint64_t c = tid; c < sigma; c += kBlock) {
+            uint32_t sum = 0;
+            for (uint32_t r = 0; r < reps; ++r) sum += s_hist_all[(uint64_t)r * sigma + c];
+            if (sum) atomicAdd((unsigned long long *)(Cp1 + c), (unsigned long long)sum);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of kItems values per thread (blocked layout).
+struct BlockScanTmp {
+    uint64_t wave_tot[kWaves];
+};
+
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t (&v)[kItems], BlockScanTmp &tmp, uint64_t &total) {
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    uint64_t own = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) own += v[j];
+    uint64_t inc = wave_incl_scan_u64(own, lane);
+    if (lane == kWave - 1) tmp.wave_tot[wave] = inc;
+    __syncthreads();
+    uint64_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        uint64_t t = tmp.wave_tot[w];
+        if (w < wave) before += t;
+        total += t;
+    }
+    __syncthreads();
+    uint64_t run = before + inc - own;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint64_t x = v[j];
+        v[j] = run;
+        run += x;
+    }
+    return before + inc - own;
+}
+
+// Generic reduce-then-scan over values produced by a functor, cut into
+// chunks of kScanChunk elements; exclusive sums restart at segment heads
+// (the node tables use one segment per level).
+//   F::value(g)            value of element g
+//   F::store(g, excl)      consume the exclusive prefix of element g
+//   F::seg_start(g)        first element of g's segment
+//   F::chunk_seg_first(c)  first chunk of the segment that chunk c continues;
+//                          a segment either starts inside a chunk (and then
+//                          ends inside it too) or starts on a chunk boundary
+template <typename F>
+__global__ __launch_bounds__(kBlock) void scan_reduce(F f, uint64_t count, uint64_t *partials) {
+    __shared__ BlockScanTmp tmp;
+    const uint64_t base = (uint64_t)blockIdx.x * kScanChunk + (uint64_t)threadIdx.x * kItems;
+    uint64_t v[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) v[j] = base + j < count ? f.value(base + j) : 0;
+    uint64_t total;
+    block_excl_scan(v, tmp, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+template <typename F>
+__global__ __launch_bounds__(kBlock) void scan_final(F f, uint64_t count, const uint64_t *partials) {
+    __shared__ BlockScanTmp tmp;
+    __shared__ uint64_t s_ex[kScanChunk];
+    const uint64_t chunk = blockIdx.x;
+    const uint64_t cbase = chunk * kScanChunk;
+    const uint64_t base = cbase + (uint64_t)threadIdx.x * kItems;
+    uint64_t v[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) v[j] = base + j < count ? f.value(base + j) : 0;
+    uint64_t total;
+    block_excl_scan(v, tmp, total);
+    // Exclusive prefix of the chunk inside its segment.
+    uint64_t chunk_off = 0;
+    if (partials) {
+        uint64_t first = f.chunk_seg_first(chunk);
+        chunk_off = partials[chunk] - partials[first];
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) s_ex[threadIdx.x * kItems + j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        uint64_t g = base + j;
+        if (g >= count) continue;
+        uint64_t h = f.seg_start(g);
+        uint64_t ex = h >= cbase ? v[j] - s_ex[h - cbase] : v[j] + chunk_off;
+        f.store(g, ex);
+    }
+}
+
+// C scan: values are counts held in Cp1[c] (= C[c+1]); stores inclusive sums.
+struct CScanOp {
+    uint64_t *Cp1;
+    __device__ uint64_t value(uint64_t g) const { return Cp1[g]; }
+    __device__ void store(uint64_t g, uint64_t ex) const { Cp1[g] = ex + Cp1[g]; }
+    __device__ uint64_t seg_start(uint64_t) const { return 0; }
+    __device__ uint64_t chunk_seg_first(uint64_t) const { return 0; }
+};
+
+// Node tables.  Element g in [1, 2^L) is node p = g - 2^l of level l =
+// floor(log2 g) (heap numbering from 1).  value = ones of B_l inside node p
+// = symbols of its range whose bit k_l is 1 = C[end] - C[middle].
+struct TableOp {
+    const uint64_t *C;
+    uint64_t *D;
+    uint64_t sigma;
+    uint32_t L;
+    __device__ static uint32_t level_of(uint64_t g) { return 63u - (uint32_t)__clzll((long long)g); }
+    __device__ uint64_t Cc(uint64_t x) const { return C[x < sigma ? x : sigma]; }
+    __device__ uint64_t value(uint64_t g) const {
+        if (g == 0) return 0;
+        uint32_t l = level_of(g), k = L - 1 - l;
+        uint64_t p = g - (1ull << l);
+        return Cc((p + 1) << (k + 1)) - Cc(((2 * p + 1) << k));
+    }
+    __device__ void store(uint64_t g, uint64_t ex) const {
+        if (g == 0) return;
+        uint32_t l = level_of(g), k = L - 1 - l;
+        uint64_t p = g - (1ull << l);
+        uint64_t ones = Cc((p + 1) << (k + 1)) - Cc(((2 * p + 1) << k));
+        D[2 * g - 2] = ex;                                  // ones before node p
+        D[2 * g - 1] = Cc((p + 1) << (k + 1)) - (ex + ones);  // zeros before node p+1
+    }
+    __device__ uint64_t seg_start(uint64_t g) const { return g == 0 ? 0 : (1ull << level_of(g)); }
+    __device__ uint64_t chunk_seg_first(uint64_t c) const {
+        // chunks >= 1 hold one level each; a level with several chunks
+        // starts at chunk 2^(l-12) for 4096-element chunks.
+        if (c == 0) return 0;
+        return 1ull << (63u - (uint32_t)__clzll((long long)c));
+    }
+};
+
+// Exclusive scan of chunk partials restarting at chunk_seg_first; single block.
+template <typename F>
+__global__ __launch_bounds__(kBlock) void scan_partials_seg(F f, uint64_t nchunks, uint64_t *partials) {
+    // Partials become "exclusive prefix from the first chunk of the whole
+    // array"; scan_final subtracts partials[first chunk of the segment].
+    __shared__ BlockScanTmp tmp;
+    __shared__ uint64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint64_t c0 = 0; c0 < nchunks; c0 += kScanChunk) {
+        const uint64_t base = c0 + (uint64_t)threadIdx.x * kItems;
+        uint64_t v[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) v[j] = base + j < nchunks ? partials[base + j] : 0;
+        uint64_t total;
+        block_excl_scan(v, tmp, total);
+        uint64_t carry = s_carry;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j)
+            if (base + j < nchunks) partials[base + j] = carry + v[j];
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + total;
+        __syncthreads();
+    }
+    (void)f;
+}
+
+// ---------------------------------------------------------------------------
+// Level pass.
+struct LevelArgs {
+    const void *in;          // S_l (TIN), 16-byte aligned
+    void *out;               // S_{l+1} (TOUT)
+    uint64_t *bits;          // B_l
+    const uint64_t *D;       // D_l: 2^(l+1) entries
+    uint64_t nD;             // 2^(l+1)
+    uint64_t *tile_state;    // ceil(n/kTile) look-back words, zeroed
+    uint32_t *ticket;        // zeroed
+    const uint32_t *status;  // non-zero: input rejected, do nothing
+    uint64_t *rank, *sel1, *sel0;  // directory rows of level l
+    uint64_t n;
+    uint32_t k;              // bit examined at this level: L-1-l
+};
+
+template <typename TIN, typename TOUT, bool SCATTER, bool DIRS>
+__global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
+    constexpr int kStageBytes = kTile * (sizeof(TIN) > sizeof(TOUT) ? sizeof(TIN) : sizeof(TOUT));
+    __shared__ __align__(16) unsigned char s_stage[kStageBytes];
+    __shared__ uint64_t s_words[kTileWords];
+    __shared__ uint32_t s_zpre[kTileWords];
+    __shared__ uint64_t s_Z0;
+    __shared__ uint32_t s_Zt;
+    __shared__ uint32_t s_tile;
+
+    if (*a.status) return;  // uniform across the grid: the input was rejected
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t t0 = tile * kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
+    const uint32_t k = a.k;
+
+    // 1. Coalesced 16-byte loads of the tile into LDS (blocked layout).
+    TIN *stage_in = reinterpret_cast<TIN *>(s_stage);
+    const TIN *in = reinterpret_cast<const TIN *>(a.in) + t0;
+    constexpr int V = 16 / sizeof(TIN);
+    if (len == (uint32_t)kTile) {
+#pragma unroll
+        for (int r = 0; r < kItems / V; ++r) {
+            int e = (r * kBlock + tid) * V;
+            *reinterpret_cast<uint4 *>(stage_in + e) = *reinterpret_cast<const uint4 *>(in + e);
+        }
+    } else {
+        for (uint32_t e = tid; e < len; e += kBlock) stage_in[e] = in[e];
+    }
+    __syncthreads();
+
+    // 2. Striped view: item r of wave w, lane j is position r*kBlock + 64w + j,
+    //    so each ballot is one position-ordered word of B_l (word 4r + w).
+    uint32_t sym[kItems];
+    uint64_t wbits[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        uint32_t e = (uint32_t)(r * kBlock + tid);
+        bool valid = e < len;
+        sym[r] = valid ? (uint32_t)stage_in[e] : 0u;
+        bool bit = valid && ((sym[r] >> k) & 1u);
+        uint64_t vm = __ballot(valid);
+        uint64_t w = __ballot(bit);
+        wbits[r] = w;
+        if (lane == 0) {
+            s_words[r * kWaves + wave] = w;
+            s_zpre[r * kWaves + wave] = (uint32_t)(__popcll(vm) - __popcll(w));
+        }
+    }
+    __syncthreads();
+
+    // 3. Wave 0: scan of the 64 word zero-counts, look-back across tiles,
+    //    bit words to HBM, directory entries.
+    if (wave == 0) {
+        uint32_t zc = s_zpre[lane];
+        uint32_t inc = wave_incl_scan_u32(zc, lane);
+        uint32_t excl = inc - zc;
+        uint32_t Zt = __shfl(inc, kWave - 1, kWave);
+        uint64_t Z0 = lookback_exclusive(a.tile_state, tile, Zt, lane);
+        s_zpre[lane] = excl;
+        if (lane == 0) {
+            s_Z0 = Z0;
+            s_Zt = Zt;
+        }
+        uint64_t word = s_words[lane];
+        if ((uint32_t)lane * 64u < len) a.bits[(t0 >> 6) + lane] = word;
+        if (DIRS) emit_directories(word, excl, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
+    }
+    if (!SCATTER) return;
+    __syncthreads();
+    const uint64_t Z0 = s_Z0;
+    const uint32_t Zt = s_Zt;
+
+    // 4. Stable split of the tile by the level bit into LDS: zeros keep their
+    //    order at [0, Zt), ones at [Zt, len).  Inside each region the
+    //    elements stay grouped by node, and each node's group lands on
+    //    consecutive positions of S_{l+1}.
+    TOUT *stage_out = reinterpret_cast<TOUT *>(s_stage);
+    const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        uint32_t e = (uint32_t)(r * kBlock + tid);
+        if (e < len) {
+            uint64_t w = wbits[r];
+            uint32_t zl = s_zpre[r * kWaves + wave] + (uint32_t)__popcll(~w & lt);
+            uint32_t slot = ((w >> lane) & 1ull) ? Zt + (e - zl) : zl;
+            stage_out[slot] = (TOUT)sym[r];
+        }
+    }
+    __syncthreads();
+
+    // 5. Scatter.  Position s of the split tile holds a zero of node p iff
+    //    s < Zt; its destination is D[2p] + (zeros before it on the level)
+    //    for a zero and D[2p+1] + (ones before it) for a one -- Fig. 1's
+    //    start + X[i] and start + X_s + i - X[i] with the node-relative
+    //    counts rebased to level-wide counts through the tables.
+    TOUT *out = reinterpret_cast<TOUT *>(a.out);
+    const uint64_t O0 = t0 - Z0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        uint32_t s = (uint32_t)(r * kBlock + tid);
+        if (s < len) {
+            TOUT v = stage_out[s];
+            uint64_t q = (uint64_t)((uint32_t)v >> k);
+            if (q < a.nD) {
+                uint64_t dest = a.D[q] + (s < Zt ? Z0 + s : O0 + (s - Zt));
+                if (dest < a.n) out[dest] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Directory tails: for every level, rank[l][last] = ones of the level, the
+// sample counts, and sample entries past the counts set to n.  The level
+// totals come either from the node tables (zeros of a level = D_l's last
+// entry) or from an array of per-level totals.
+__global__ void dir_finish(const uint64_t *D, const uint64_t *zeros_tot, uint64_t n, uint32_t L,
+                           uint64_t *rank, uint64_t rank_len, uint64_t *sel1, uint64_t *sel0, uint64_t cap,
+                           uint64_t *sel_counts) {
+    const uint32_t l = blockIdx.y;
+    uint64_t zeros = zeros_tot ? zeros_tot[l] : D[(1ull << (l + 2)) - 3];
+    uint64_t ones = n - zeros;
+    uint64_t c1 = cdiv(ones, WT_SELECT_SAMPLE), c0 = cdiv(zeros, WT_SELECT_SAMPLE);
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        rank[(uint64_t)l * rank_len + rank_len - 1] = ones;
+        sel_counts[l] = c1;
+        sel_counts[L + l] = c0;
+    }
+    if (t < cap) {
+        if (t >= c1) sel1[(uint64_t)l * cap + t] = n;
+        if (t >= c0) sel0[(uint64_t)l * cap + t] = n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Standalone directories from existing bits: one wave per tile of 64 words
+// of one level (grid.y = level), zero-count look-back per level.
+__global__ __launch_bounds__(kWave) void dir_tiles(const uint64_t *bits, uint64_t n, uint64_t W,
+                                                   uint64_t *state, uint64_t T, uint32_t *tickets,
+                                                   uint64_t *zeros_tot, uint64_t *rank, uint64_t rank_len,
+                                                   uint64_t *sel1, uint64_t *sel0, uint64_t cap) {
+    const uint32_t l = blockIdx.y;
+    const int lane = lane_id();
+    uint32_t tk = 0;
+    if (lane == 0) tk = atomicAdd(tickets + l, 1u);
+    const uint64_t tile = (uint64_t)__shfl(tk, 0, kWave);
+    const uint64_t t0 = tile * kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, n - t0);
+    const uint64_t wi = (t0 >> 6) + lane;
+    const bool has = (uint32_t)lane * 64u < len;
+    const uint64_t word = has ? bits[(uint64_t)l * W + wi] : 0ull;
+    const uint32_t nb = has ? min(64u, len - (uint32_t)lane * 64u) : 0u;
+    const uint32_t zc = nb - (uint32_t)__popcll(word);
+    uint32_t inc = wave_incl_scan_u32(zc, lane);
+    uint32_t excl = inc - zc;
+    uint32_t Zt = __shfl(inc, kWave - 1, kWave);
+    uint64_t Z0 = lookback_exclusive(state + (uint64_t)l * T, tile, Zt, lane);
+    emit_directories(word, excl, Z0, t0, len, Zt, n, rank + (uint64_t)l * rank_len, sel1 + (uint64_t)l * cap,
+                     sel0 + (uint64_t)l * cap, lane);
+    if (tile == T - 1 && lane == 0) zeros_tot[l] = Z0 + Zt;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+struct Plan {
+    uint64_t n, sigma;
+    uint32_t L, in_bytes, mid_bytes;
+    uint64_t W, T, rank_len, cap;
+    uint64_t off_status, off_tickets, off_states, off_D, off_part, off_S0, off_S1, total;
+    uint64_t n_part;
+};
+
+static uint32_t levels_of(uint64_t sigma) {
+    uint32_t L = 0;
+    while (L < 64 && (1ull << L) < sigma) ++L;
+    return L;
+}
+
+static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
+    if (sigma == 0 || (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4)) return WT_ERR_ARG;
+    if (sigma > (1ull << (8 * sym_bytes))) return WT_ERR_ARG;
+    if (n >= (1ull << 40)) return WT_ERR_RANGE;
+    p.n = n;
+    p.sigma = sigma;
+    p.L = levels_of(sigma);
+    if (p.L > 30) return WT_ERR_RANGE;  // dense node tables: 2^(L+1) words
+    p.in_bytes = (uint32_t)sym_bytes;
+    p.mid_bytes = p.L <= 8 ? 1u : (p.L <= 16 ? 2u : 4u);  // width of S_l for l >= 1
+    p.W = cdiv(n, 64);
+    p.T = cdiv(n, kTile);
+    p.rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1;
+    p.cap = cdiv(n, WT_SELECT_SAMPLE) + 1;
+    const uint64_t table_elems = p.L ? (1ull << p.L) : 0;        // node heap indices [0, 2^L)
+    const uint64_t D_len = p.L ? (2ull << p.L) - 2 : 0;          // 2^(l+1) entries per level
+    const uint64_t part_c = cdiv(sigma, kScanChunk);
+    const uint64_t part_t = cdiv(table_elems, kScanChunk);
+    p.n_part = std::max<uint64_t>(std::max<uint64_t>(part_c, part_t), 1);
+    uint64_t o = 0;
+    p.off_status = o;
+    o += 256;
+    p.off_tickets = o;
+    o = align_up(o + 4ull * std::max<uint32_t>(p.L, 1u), 256);
+    p.off_states = o;
+    o = align_up(o + 8ull * p.L * p.T, 256);
+    p.off_D = o;
+    o = align_up(o + 8ull * D_len, 256);
+    p.off_part = o;
+    o = align_up(o + 8ull * p.n_part, 256);
+    p.off_S0 = o;
+    const uint64_t sbytes = p.L >= 2 ? align_up(n * p.mid_bytes, 256) : 0;
+    o += sbytes;
+    p.off_S1 = o;
+    o += p.L >= 3 ? sbytes : 0;
+    p.total = o;
+    return WT_OK;
+}
+
+static bool g_timing = false;
+static std::mutex g_timing_mu;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;  // recorded, not yet collected
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_free;
+
+static int timing_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (!g_free.empty()) {
+        ev = g_free.back();
+        g_free.pop_back();
+    } else {
+        if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) return WT_ERR_HIP;
+    }
+    return hipEventRecord(ev.first, s) == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+static int timing_end(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
+    if (hipEventRecord(ev.second, s) != hipSuccess) return WT_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_events.push_back(ev);
+    return WT_OK;
+}
+
+template <typename TIN, typename TOUT>
+static void launch_level(bool scatter, bool dirs, uint64_t T, hipStream_t s, const LevelArgs &a) {
+    dim3 grid((unsigned)T), block(kBlock);
+    if (scatter) {
+        if (dirs) level_pass<TIN, TOUT, true, true><<<grid, block, 0, s>>>(a);
+        else level_pass<TIN, TOUT, true, false><<<grid, block, 0, s>>>(a);
+    } else {
+        if (dirs) level_pass<TIN, TOUT, false, true><<<grid, block, 0, s>>>(a);
+        else level_pass<TIN, TOUT, false, false><<<grid, block, 0, s>>>(a);
+    }
+}
+
+static void launch_level_any(uint32_t tin, uint32_t tout, bool scatter, bool dirs, uint64_t T, hipStream_t s,
+                             const LevelArgs &a) {
+#define WT_LV(I, O)                                            \
+    if (tin == sizeof(I) && tout == sizeof(O)) {               \
+        launch_level<I, O>(scatter, dirs, T, s, a);            \
+        return;                                                \
+    }
+    WT_LV(uint8_t, uint8_t)
+    WT_LV(uint16_t, uint8_t)
+    WT_LV(uint32_t, uint8_t)
+    WT_LV(uint16_t, uint16_t)
+    WT_LV(uint32_t, uint16_t)
+    WT_LV(uint32_t, uint32_t)
+#undef WT_LV
+}
+
+static int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <typename T>
+static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, hipStream_t s) {
+    uint32_t reps = 0;
+    if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / p.sigma));
+    uint64_t vec = p.n / (16 / sizeof(T));
+    uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(vec, kBlock * 4), (uint64_t)num_cus() * 8));
+    size_t shm = reps ? (size_t)reps * p.sigma * 4 : 0;
+    histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, Cp1, status, reps);
+}
+
+}  // namespace wt
+
+using namespace wt;
+
+extern "C" int wt_plan(uint64_t n, uint64_t sigma, int sym_bytes, wt_layout *out) {
+    if (!out) return WT_ERR_ARG;
+    Plan p;
+    int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    out->n = n;
+    out->sigma = sigma;
+    out->L = p.L;
+    out->sym_bytes = (uint32_t)sym_bytes;
+    out->words_per_level = p.W;
+    out->bits_words = (uint64_t)p.L * p.W;
+    out->C_len = sigma + 1;
+    out->rank_len = p.rank_len;
+    out->sel_cap = p.cap;
+    out->sel_counts_len = 2ull * p.L;
+    out->scratch_bytes = p.total;
+    out->rs_scratch_bytes = wt_rank_select_scratch_bytes(n, p.L);
+    return WT_OK;
+}
+
+extern "C" uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L) {
+    uint64_t T = cdiv(n, kTile);
+    // tickets, per-level zero totals, per-level look-back states
+    return align_up(4ull * std::max<uint32_t>(L, 1u), 256) + align_up(8ull * std::max<uint32_t>(L, 1u), 256) +
+           align_up(8ull * L * T, 256);
+}
+
+extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                        void *d_scratch, uint64_t scratch_bytes, void *stream) {
+    Plan p;
+    int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    if (!out || !out->C || !d_scratch || (n > 0 && !d_seq) || (p.L > 0 && n > 0 && !out->bits)) return WT_ERR_ARG;
+    const bool dirs = out->rank != nullptr;
+    if (dirs != (out->sel1 != nullptr) || dirs != (out->sel0 != nullptr) || dirs != (out->sel_counts != nullptr))
+        return WT_ERR_ARG;
+    if (((uintptr_t)d_seq & 15u) || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    if (scratch_bytes < p.total) return WT_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    uint32_t *status = (uint32_t *)(sc + p.off_status);
+    uint32_t *tickets = (uint32_t *)(sc + p.off_tickets);
+    uint64_t *states = (uint64_t *)(sc + p.off_states);
+    uint64_t *D = (uint64_t *)(sc + p.off_D);
+    uint64_t *part = (uint64_t *)(sc + p.off_part);
+
+    // Zero: status + tickets + states (one contiguous range), and C.
+    {
+        uint64_t na = p.off_D / 8, nb = sigma + 1;
+        uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
+        zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
+    }
+    if (n > 0) {
+        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, s);
+        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, s);
+        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, s);
+        // C: prefix sums of the counts.
+        CScanOp cop{out->C + 1};
+        uint64_t chunks = cdiv(sigma, kScanChunk);
+        if (chunks > 1) {
+            scan_reduce<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+            scan_partials_seg<CScanOp><<<1, kBlock, 0, s>>>(cop, chunks, part);
+            scan_final<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+        } else {
+            scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
+        }
+    }
+    if (p.L > 0) {
+        // Node tables for every level.
+        TableOp top{out->C, D, sigma, p.L};
+        uint64_t count = 1ull << p.L;
+        uint64_t chunks = cdiv(count, kScanChunk);
+        if (chunks > 1) {
+            scan_reduce<TableOp><<<(unsigned)chunks, kBlock, 0, s>>>(top, count, part);
+            scan_partials_seg<TableOp><<<1, kBlock, 0, s>>>(top, chunks, part);
+            scan_final<TableOp><<<(unsigned)chunks, kBlock, 0, s>>>(top, count, part);
+        } else {
+            scan_final<TableOp><<<1, kBlock, 0, s>>>(top, count, nullptr);
+        }
+        if (dirs) {
+            dim3 g((unsigned)cdiv(p.cap, kBlock), p.L);
+            dir_finish<<<g, kBlock, 0, s>>>(D, nullptr, n, p.L, out->rank, p.rank_len, out->sel1, out->sel0, p.cap,
+                                            out->sel_counts);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+    if (n == 0 || p.L == 0) return WT_OK;
+
+    const void *cur = d_seq;
+    uint32_t cur_w = p.in_bytes;
+    for (uint32_t l = 0; l < p.L; ++l) {
+        const bool scatter = l + 1 < p.L;
+        void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+        LevelArgs a;
+        a.in = cur;
+        a.out = scatter ? dst : nullptr;
+        a.bits = out->bits + (uint64_t)l * p.W;
+        a.D = D + ((2ull << l) - 2);
+        a.nD = 2ull << l;
+        a.tile_state = states + (uint64_t)l * p.T;
+        a.ticket = tickets + l;
+        a.status = status;
+        a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
+        a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
+        a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
+        a.n = n;
+        a.k = p.L - 1 - l;
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (g_timing && (rc = timing_begin(s, ev))) return rc;
+        launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, p.T, s, a);
+        if (g_timing && (rc = timing_end(s, ev))) return rc;
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        cur = dst;
+        cur_w = p.mid_bytes;
+    }
+    return WT_OK;
+}
+
+extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t L, uint64_t *d_rank,
+                                    uint64_t *d_sel1, uint64_t *d_sel0, uint64_t *d_sel_counts, void *d_scratch,
+                                    uint64_t scratch_bytes, void *stream) {
+    if (L == 0) return WT_OK;
+    if (L > 30 || n >= (1ull << 40)) return WT_ERR_RANGE;
+    if (!d_rank || !d_sel1 || !d_sel0 || !d_sel_counts || !d_scratch || (n > 0 && !d_bits)) return WT_ERR_ARG;
+    if ((uintptr_t)d_scratch & 255u) return WT_ERR_ARG;
+    if (scratch_bytes < wt_rank_select_scratch_bytes(n, L)) return WT_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t W = cdiv(n, 64), T = cdiv(n, kTile), rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1,
+                   cap = cdiv(n, WT_SELECT_SAMPLE) + 1;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    uint32_t *tickets = (uint32_t *)sc;
+    uint64_t *zeros_tot = (uint64_t *)(sc + align_up(4ull * L, 256));
+    uint64_t *states = (uint64_t *)(sc + align_up(4ull * L, 256) + align_up(8ull * L, 256));
+    uint64_t nz = wt_rank_select_scratch_bytes(n, L) / 8;
+    zero_fill<<<(unsigned)std::min<uint64_t>(cdiv(nz, kBlock), 4096), kBlock, 0, s>>>((uint64_t *)sc, nz, nullptr,
+                                                                                       0);
+    if (T > 0) {
+        dim3 g((unsigned)T, L);
+        dir_tiles<<<g, kWave, 0, s>>>(d_bits, n, W, states, T, tickets, zeros_tot, d_rank, rank_len, d_sel1, d_sel0,
+                                      cap);
+    }
+    dim3 g2((unsigned)cdiv(cap, kBlock), L);
+    dir_finish<<<g2, kBlock, 0, s>>>(nullptr, zeros_tot, n, L, d_rank, rank_len, d_sel1, d_sel0, cap, d_sel_counts);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_status_get(const void *d_scratch, void *stream) {
+    if (!d_scratch) return WT_ERR_ARG;
+    uint32_t st = 0;
+    if (hipMemcpyAsync(&st, d_scratch, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+        return WT_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return WT_ERR_HIP;
+    return st == 0 ? WT_OK : (st == kStatusSymbol ? WT_ERR_SYMBOL : WT_ERR_HIP);
+}
+
+extern "C" int wt_timing_enable(int enable) {
+    g_timing = enable != 0;
+    return WT_OK;
+}
+
+extern "C" int wt_timing_collect(float *ms, int cap) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        evs.swap(g_events);
+    }
+    int count = (int)evs.size();
+    int rc = count;
+    for (int i = 0; i < count; ++i) {
+        float t = 0.f;
+        if (hipEventSynchronize(evs[i].second) != hipSuccess ||
+            hipEventElapsedTime(&t, evs[i].first, evs[i].second) != hipSuccess)
+            rc = WT_ERR_HIP;
+        if (ms && i < cap) ms[i] = t;
+    }
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_free.insert(g_free.end(), evs.begin(), evs.end());
+    return rc;
+}

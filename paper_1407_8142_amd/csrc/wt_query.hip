@@ -1,0 +1,189 @@
+// Batched access / rank / select on a built levelwise wavelet tree
+// (queries as defined in "Preliminaries"; tree walks without parent/child
+// pointers: node offsets come from C, in-node positions from rank/select on
+// the level bitmaps).  One thread per query; each query takes L dependent
+// steps of a few cached loads, so these kernels are latency-bound.
+#include <hip/hip_runtime.h>
+
+#include "../../include/wt.h"
+#include "wt_device.hpp"
+
+namespace wt {
+
+struct TreeDev {
+    const uint64_t *bits, *C, *rank, *sel1, *sel0, *sel_counts;
+    uint64_t n, sigma, W, rank_len, cap;
+    uint32_t L;
+};
+
+__device__ __forceinline__ uint64_t Cat(const TreeDev &t, uint64_t x) { return t.C[x < t.sigma ? x : t.sigma]; }
+
+// Ones of level l in [0, j), j <= n: directory entry + whole words + a partial word.
+__device__ __forceinline__ uint64_t rank1(const TreeDev &t, uint32_t l, uint64_t j) {
+    const uint64_t *B = t.bits + (uint64_t)l * t.W;
+    uint64_t blk = j >> 9;
+    uint64_t r = t.rank[(uint64_t)l * t.rank_len + blk];
+    uint64_t w_end = j >> 6;
+    for (uint64_t w = blk << 3; w < w_end; ++w) r += (uint64_t)__popcll(B[w]);
+    if (j & 63) r += (uint64_t)__popcll(B[w_end] & ((1ull << (j & 63)) - 1ull));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t rank_b(const TreeDev &t, uint32_t l, uint64_t j, uint32_t b) {
+    uint64_t r1 = rank1(t, l, j);
+    return b ? r1 : j - r1;
+}
+
+// Position of the b-bit of level l with 0-based ordinal o (o < count of b-bits).
+__device__ uint64_t select_b(const TreeDev &t, uint32_t l, uint32_t b, uint64_t o) {
+    const uint64_t *samp = (b ? t.sel1 : t.sel0) + (uint64_t)l * t.cap;
+    const uint64_t *R = t.rank + (uint64_t)l * t.rank_len;
+    const uint64_t *B = t.bits + (uint64_t)l * t.W;
+    uint64_t s = o / WT_SELECT_SAMPLE;
+    uint64_t lo_pos = samp[s], hi_pos = samp[s + 1];
+    // Largest 512-bit block start whose b-rank is <= o, between the samples.
+    uint64_t lo = lo_pos >> 9, hi = (hi_pos >= t.n ? (t.n - 1) : hi_pos) >> 9;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi + 1) >> 1;
+        uint64_t pos = mid << 9;
+        uint64_t rb = b ? R[mid] : pos - R[mid];
+        if (rb <= o) lo = mid;
+        else hi = mid - 1;
+    }
+    uint64_t pos = lo << 9;
+    uint64_t rem = o - (b ? R[lo] : pos - R[lo]);
+    for (uint64_t w = lo << 3; w < t.W; ++w) {
+        uint64_t x = b ? B[w] : ~B[w];
+        if ((w << 6) + 64 > t.n) x &= (1ull << (t.n & 63)) - 1ull;
+        uint64_t c = (uint64_t)__popcll(x);
+        if (rem < c) return (w << 6) + select_in_word(x, (uint32_t)rem);
+        rem -= c;
+    }
+    return t.n;  // unreachable for a well-formed tree
+}
+
+__global__ void access_kernel(TreeDev t, const uint64_t *qi, uint64_t m, uint32_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    uint64_t j = qi[q];
+    if (j >= t.n) {
+        out[q] = 0xFFFFFFFFu;
+        return;
+    }
+    uint64_t p = 0;
+    for (uint32_t l = 0; l < t.L; ++l) {
+        uint32_t k = t.L - 1 - l;
+        uint64_t a = Cat(t, p << (k + 1));
+        uint32_t b = (uint32_t)((t.bits[(uint64_t)l * t.W + (j >> 6)] >> (j & 63)) & 1ull);
+        uint64_t ones = rank1(t, l, j) - rank1(t, l, a);
+        if (b) j = Cat(t, ((2 * p + 1) << k)) + ones;
+        else j = j - ones;  // a + (j - a) - ones
+        p = 2 * p + b;
+        if (j >= t.n && l + 1 < t.L) break;  // unreachable for a well-formed tree
+    }
+    out[q] = (uint32_t)p;
+}
+
+__global__ void rank_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qi, uint64_t m, uint64_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    uint64_t c = qc[q], i = qi[q];
+    if (i > t.n) i = t.n;
+    if (c >= t.sigma) {
+        out[q] = 0;
+        return;
+    }
+    if (t.L == 0) {
+        out[q] = i;
+        return;
+    }
+    uint64_t p = 0, r = i;  // r: elements of node p that precede the query position
+    for (uint32_t l = 0; l < t.L && r > 0; ++l) {
+        uint32_t k = t.L - 1 - l;
+        uint64_t a = Cat(t, p << (k + 1));
+        uint32_t b = (uint32_t)((c >> k) & 1u);
+        if (a + r > t.n) break;  // unreachable for a well-formed tree
+        uint64_t ones = rank1(t, l, a + r) - rank1(t, l, a);
+        r = b ? ones : r - ones;
+        p = 2 * p + b;
+    }
+    out[q] = r;
+}
+
+__global__ void select_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qk, uint64_t m, int64_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    uint64_t c = qc[q], kk = qk[q];
+    if (c >= t.sigma || kk == 0 || kk > t.C[c + 1] - t.C[c]) {
+        out[q] = -1;
+        return;
+    }
+    uint64_t r = kk - 1;  // 0-based index inside the current child
+    for (uint32_t d = t.L; d-- > 0;) {
+        uint32_t k = t.L - 1 - d;
+        uint64_t p = c >> (k + 1);
+        uint32_t b = (uint32_t)((c >> k) & 1u);
+        uint64_t a = Cat(t, p << (k + 1));
+        uint64_t j = select_b(t, d, b, rank_b(t, d, a, b) + r);
+        if (j >= t.n) {  // unreachable for a well-formed tree
+            out[q] = -1;
+            return;
+        }
+        r = j - a;
+    }
+    out[q] = (int64_t)r;
+}
+
+static bool make_tree(const wt_view *v, TreeDev &t) {
+    if (!v || !v->C) return false;
+    if (v->L > 0 && v->n > 0 && (!v->bits || !v->rank || !v->sel1 || !v->sel0)) return false;
+    t.bits = v->bits;
+    t.C = v->C;
+    t.rank = v->rank;
+    t.sel1 = v->sel1;
+    t.sel0 = v->sel0;
+    t.sel_counts = v->sel_counts;
+    t.n = v->n;
+    t.sigma = v->sigma;
+    t.L = v->L;
+    t.W = (v->n + 63) / 64;
+    t.rank_len = (v->n + WT_RANK_BLOCK_BITS - 1) / WT_RANK_BLOCK_BITS + 1;
+    t.cap = (v->n + WT_SELECT_SAMPLE - 1) / WT_SELECT_SAMPLE + 1;
+    return true;
+}
+
+constexpr int kQBlock = 256;
+
+}  // namespace wt
+
+using namespace wt;
+
+extern "C" int wt_access(const wt_view *v, const uint64_t *d_i, uint64_t m, uint32_t *d_sym, void *stream) {
+    TreeDev t;
+    if (!make_tree(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_i || !d_sym) return WT_ERR_ARG;
+    access_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_i, m, d_sym);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_rank(const wt_view *v, const uint32_t *d_c, const uint64_t *d_i, uint64_t m, uint64_t *d_out,
+                       void *stream) {
+    TreeDev t;
+    if (!make_tree(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_i || !d_out) return WT_ERR_ARG;
+    rank_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_i, m, d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_select(const wt_view *v, const uint32_t *d_c, const uint64_t *d_k, uint64_t m, int64_t *d_out,
+                         void *stream) {
+    TreeDev t;
+    if (!make_tree(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
+    select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_k, m,
+                                                                                                 d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}

@@ -1,0 +1,235 @@
+"""Python binding of libwt.so: argument marshalling only.
+
+Every step of construction and every query runs in the HIP kernels of
+libwt.so; torch supplies device memory and the current stream.  Importing
+this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwt.so")
+
+WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL, WT_ERR_SCRATCH, WT_ERR_RANGE, WT_ERR_HIP, WT_ERR_NOMEM = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_ARG", -2: "WT_ERR_SYMBOL", -3: "WT_ERR_SCRATCH", -4: "WT_ERR_RANGE",
+                -5: "WT_ERR_HIP", -6: "WT_ERR_NOMEM"}
+RANK_BLOCK_BITS = 512
+SELECT_SAMPLE = 4096
+
+EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
+           "wt_access", "wt_rank", "wt_select", "wt_timing_enable", "wt_timing_collect"]
+
+
+class WTError(RuntimeError):
+    def __init__(self, rc: int, what: str):
+        super().__init__(f"{what} failed: {STATUS_NAMES.get(rc, rc)}")
+        self.rc = rc
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32),
+                ("sym_bytes", ctypes.c_uint32), ("words_per_level", ctypes.c_uint64),
+                ("bits_words", ctypes.c_uint64), ("C_len", ctypes.c_uint64), ("rank_len", ctypes.c_uint64),
+                ("sel_cap", ctypes.c_uint64), ("sel_counts_len", ctypes.c_uint64),
+                ("scratch_bytes", ctypes.c_uint64), ("rs_scratch_bytes", ctypes.c_uint64)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1407_8142_amd/build.py "
+                              "(or __graft_entry__.build()) before use")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        L.wt_plan.argtypes = [u64, u64, i32, ctypes.POINTER(Layout)]
+        L.wt_build.argtypes = [vp, u64, u64, i32, ctypes.POINTER(Outputs), vp, u64, vp]
+        L.wt_build_rank_select.argtypes = [vp, u64, u32, vp, vp, vp, vp, vp, u64, vp]
+        L.wt_rank_select_scratch_bytes.argtypes = [u64, u32]
+        L.wt_rank_select_scratch_bytes.restype = u64
+        L.wt_status_get.argtypes = [vp, vp]
+        L.wt_access.argtypes = [ctypes.POINTER(View), vp, u64, vp, vp]
+        L.wt_rank.argtypes = [ctypes.POINTER(View), vp, vp, u64, vp, vp]
+        L.wt_select.argtypes = [ctypes.POINTER(View), vp, vp, u64, vp, vp]
+        L.wt_timing_enable.argtypes = [i32]
+        L.wt_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
+        for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
+                  "wt_select", "wt_timing_enable", "wt_timing_collect"):
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != WT_OK:
+        raise WTError(rc, what)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None or t.numel() == 0:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def plan(n: int, sigma: int, sym_bytes: int) -> Layout:
+    lay = Layout()
+    _check(lib().wt_plan(n, sigma, sym_bytes, ctypes.byref(lay)), "wt_plan")
+    return lay
+
+
+@dataclass
+class WaveletTree:
+    """Device buffers of one built tree (int64 tensors hold the uint64 words)."""
+    n: int
+    sigma: int
+    L: int
+    sym_bytes: int
+    bits: torch.Tensor
+    C: torch.Tensor
+    rank: torch.Tensor | None
+    sel1: torch.Tensor | None
+    sel0: torch.Tensor | None
+    sel_counts: torch.Tensor | None
+    scratch: torch.Tensor
+    layout: Layout
+
+    @staticmethod
+    def allocate(n: int, sigma: int, sym_bytes: int, directories: bool = True, device="cuda") -> "WaveletTree":
+        lay = plan(n, sigma, sym_bytes)
+        L, W = lay.L, lay.words_per_level
+        e = lambda *shape: torch.empty(*shape, dtype=torch.int64, device=device)
+        return WaveletTree(
+            n=n, sigma=sigma, L=L, sym_bytes=sym_bytes,
+            bits=e(L, W), C=e(sigma + 1),
+            rank=e(L, lay.rank_len) if directories else None,
+            sel1=e(L, lay.sel_cap) if directories else None,
+            sel0=e(L, lay.sel_cap) if directories else None,
+            sel_counts=e(2 * L) if directories else None,
+            scratch=torch.empty(max(lay.scratch_bytes, 256), dtype=torch.uint8, device=device),
+            layout=lay)
+
+    def outputs(self) -> Outputs:
+        return Outputs(_ptr(self.bits), _ptr(self.C), _ptr(self.rank), _ptr(self.sel1), _ptr(self.sel0),
+                       _ptr(self.sel_counts))
+
+    def view(self) -> View:
+        return View(_ptr(self.bits), _ptr(self.C), _ptr(self.rank), _ptr(self.sel1), _ptr(self.sel0),
+                    _ptr(self.sel_counts), self.n, self.sigma, self.L)
+
+    # -- construction -------------------------------------------------------
+    def build_from(self, seq: torch.Tensor, stream=None) -> "WaveletTree":
+        """Launch wt_build on ``seq`` into this tree's buffers (asynchronous)."""
+        if not seq.is_cuda:
+            raise ValueError("seq must be a device tensor")
+        if seq.element_size() != self.sym_bytes or seq.numel() != self.n or not seq.is_contiguous():
+            raise ValueError("seq does not match the allocated layout")
+        out = self.outputs()
+        rc = lib().wt_build(_ptr(seq), self.n, self.sigma, self.sym_bytes, ctypes.byref(out),
+                            _ptr(self.scratch), self.scratch.numel(), _stream(stream))
+        _check(rc, "wt_build")
+        return self
+
+    def status(self, stream=None) -> int:
+        return int(lib().wt_status_get(_ptr(self.scratch), _stream(stream)))
+
+    # -- queries ------------------------------------------------------------
+    def _need_dirs(self):
+        if self.rank is None:
+            raise ValueError("queries need a tree built with directories")
+
+    def access(self, i: torch.Tensor, stream=None) -> torch.Tensor:
+        self._need_dirs()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int32, device=i.device)
+        v = self.view()
+        _check(lib().wt_access(ctypes.byref(v), _ptr(i), i.numel(), _ptr(out), _stream(stream)), "wt_access")
+        return out
+
+    def rank_query(self, c: torch.Tensor, i: torch.Tensor, stream=None) -> torch.Tensor:
+        self._need_dirs()
+        c = c.to(torch.int32).contiguous()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int64, device=i.device)
+        v = self.view()
+        _check(lib().wt_rank(ctypes.byref(v), _ptr(c), _ptr(i), i.numel(), _ptr(out), _stream(stream)), "wt_rank")
+        return out
+
+    def select_query(self, c: torch.Tensor, k: torch.Tensor, stream=None) -> torch.Tensor:
+        self._need_dirs()
+        c = c.to(torch.int32).contiguous()
+        k = k.to(torch.int64).contiguous()
+        out = torch.empty(k.numel(), dtype=torch.int64, device=k.device)
+        v = self.view()
+        _check(lib().wt_select(ctypes.byref(v), _ptr(c), _ptr(k), k.numel(), _ptr(out), _stream(stream)),
+               "wt_select")
+        return out
+
+    def to_numpy(self) -> dict:
+        import numpy as np
+        u = lambda t: None if t is None else t.cpu().numpy().view(np.uint64)
+        return {"L": self.L, "n": self.n, "sigma": self.sigma, "bits": u(self.bits), "C": u(self.C),
+                "rank": u(self.rank), "sel1": u(self.sel1), "sel0": u(self.sel0), "sel_counts": u(self.sel_counts)}
+
+
+def build(seq: torch.Tensor, sigma: int, directories: bool = True, stream=None) -> WaveletTree:
+    """Allocate buffers and build the tree of ``seq`` (1-, 2- or 4-byte symbols)."""
+    t = WaveletTree.allocate(seq.numel(), sigma, seq.element_size(), directories, seq.device)
+    return t.build_from(seq, stream)
+
+
+def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
+    """Standalone directories of level bitmaps ``bits`` (L, ceil(n/64)) int64."""
+    rank_len = (n + RANK_BLOCK_BITS - 1) // RANK_BLOCK_BITS + 1
+    cap = (n + SELECT_SAMPLE - 1) // SELECT_SAMPLE + 1
+    dev = bits.device
+    e = lambda *shape: torch.empty(*shape, dtype=torch.int64, device=dev)
+    rank, sel1, sel0, counts = e(L, rank_len), e(L, cap), e(L, cap), e(2 * L)
+    sbytes = int(lib().wt_rank_select_scratch_bytes(n, L))
+    scratch = torch.empty(max(sbytes, 256), dtype=torch.uint8, device=dev)
+    rc = lib().wt_build_rank_select(_ptr(bits.contiguous()), n, L, _ptr(rank), _ptr(sel1), _ptr(sel0),
+                                    _ptr(counts), _ptr(scratch), scratch.numel(), _stream(stream))
+    _check(rc, "wt_build_rank_select")
+    return {"rank": rank, "sel1": sel1, "sel0": sel0, "sel_counts": counts, "_scratch": scratch}
+
+
+def timing_enable(on: bool = True):
+    _check(lib().wt_timing_enable(1 if on else 0), "wt_timing_enable")
+
+
+def timing_collect(cap: int = 1 << 16) -> list[float]:
+    buf = (ctypes.c_float * cap)()
+    rc = lib().wt_timing_collect(buf, cap)
+    if rc < 0:
+        raise WTError(rc, "wt_timing_collect")
+    return [float(buf[i]) for i in range(min(rc, cap))]
+
+
+def to_device(S, device="cuda") -> torch.Tensor:
+    """numpy symbols (uint8/uint16/uint32) -> device tensor of the same width."""
+    import numpy as np
+    raw = {1: np.int8, 2: np.int16, 4: np.int32}[S.dtype.itemsize]
+    return torch.from_numpy(np.ascontiguousarray(S).view(raw)).to(device)
