@@ -141,6 +141,13 @@ int wt_rank(const wt_view *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t
 int wt_select(const wt_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
               int64_t *d_out, void *stream);
 
+/* Look-back tuning and testing hook.  Tiles of a level pass find their
+ * prefix by looking back at earlier tiles; a tile whose predecessor has not
+ * published after `polls` polls reduces that predecessor's input itself
+ * (results are identical either way).  0 forces that path for every
+ * predecessor found unpublished.  Default 8.  Applies to later launches. */
+int wt_set_lookback_spin_limit(int polls);
+
 /* Kernel timing for measurement tools.  While enabled, wt_build brackets
  * every level-pass launch with a pair of HIP events on its stream.
  * wt_timing_collect waits for the recorded events, writes up to `cap`

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwt.so")
+PROBE = os.path.join(HERE, "bw_probe")
 SOURCES = ["wt_build.hip", "wt_query.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,5 +36,16 @@ def build_library(verbose: bool = False) -> str:
     return LIB
 
 
+def build_probe(verbose: bool = False) -> str:
+    """Streaming-copy probe (HBM bandwidth and counter calibration), an executable."""
+    flags = [f for f in hipcc_flags() if f not in ("-fPIC", "-shared")]
+    cmd = [HIPCC, *flags, "-o", PROBE, os.path.join(CSRC, "bw_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return PROBE
+
+
 if __name__ == "__main__":
     print(build_library(verbose="-v" in sys.argv))
+    print(build_probe(verbose="-v" in sys.argv))

@@ -2,7 +2,7 @@
 // Tree Construction") as one HBM pass per level, plus rank/select directories.
 //
 // Pipeline of wt_build on one stream:
-//   zero_fill      status word, look-back tile states, tickets, C
+//   zero_fill      status word, look-back tile states, C
 //   histogram      counts of every symbol into C[1..sigma] and the symbol check
 //   scan (C)       C[c] = #{S[i] < c}, a device-wide prefix sum
 //   node tables    per level l and node p: D_l[2p] = ones of B_l before node p,
@@ -30,11 +30,9 @@ namespace wt {
 
 constexpr int kBlock = 256;
 constexpr int kItems = 16;
-constexpr int kTile = kBlock * kItems;       // positions per tile
-constexpr int kTileWords = kTile / 64;       // level words per tile (= one wave)
+constexpr int kDirTile = 4096;               // bits per tile of the standalone directory builder
 constexpr int kWaves = kBlock / kWave;
 constexpr int kScanChunk = kBlock * kItems;  // elements per block in the generic scans
-static_assert(kTileWords == kWave, "one wave must own the words of a tile");
 
 constexpr uint32_t kStatusSymbol = 2u;
 
@@ -282,43 +280,77 @@ __global__ __launch_bounds__(kBlock) void scan_partials_seg(F f, uint64_t nchunk
 
 // ---------------------------------------------------------------------------
 // Level pass.
+//
+// A tile is 16 KiB of the level's sequence whatever the symbol width, so one
+// block has enough bytes in flight to cover HBM latency and a level has few
+// enough tiles for the look-back to stay short.  The 256 threads hold the
+// tile packed in 16 registers each (item r of thread t is position
+// r*256 + t), which frees the LDS stage for the split.
+template <typename T>
+struct TileCfg {
+    static constexpr int kBytes = 16384;
+    static constexpr int kItems = kBytes / (kBlock * (int)sizeof(T));  // per thread
+    static constexpr int kTile = kBlock * kItems;                       // positions
+    static constexpr int kWords = kTile / 64;                           // level words
+    static constexpr int kWPL = kWords / kWave;                         // words per lane of wave 0
+    static constexpr int kPer = 4 / (int)sizeof(T);                     // symbols per packed register
+    static constexpr int kRegs = kItems / kPer;
+};
+constexpr int kMinTile = TileCfg<uint32_t>::kTile;  // smallest tile: sizes the look-back state arrays
+constexpr int kSmallD = 512;                        // node tables up to this size are cached in LDS
+
 struct LevelArgs {
     const void *in;          // S_l (TIN), 16-byte aligned
     void *out;               // S_{l+1} (TOUT)
     uint64_t *bits;          // B_l
     const uint64_t *D;       // D_l: 2^(l+1) entries
     uint64_t nD;             // 2^(l+1)
-    uint64_t *tile_state;    // ceil(n/kTile) look-back words, zeroed
-    uint32_t *ticket;        // zeroed
+    uint64_t *tile_state;    // ceil(n/tile) look-back words, zeroed
     const uint32_t *status;  // non-zero: input rejected, do nothing
     uint64_t *rank, *sel1, *sel0;  // directory rows of level l
     uint64_t n;
     uint32_t k;              // bit examined at this level: L-1-l
+    int spin_limit;          // look-back polls before reducing a missing predecessor
 };
 
+template <typename T>
+__device__ __forceinline__ uint32_t zero_bits(const uint4 &q, uint32_t k) {
+    union {
+        uint4 v;
+        T e[16 / sizeof(T)];
+    } u;
+    u.v = q;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < (int)(16 / sizeof(T)); ++j) c += (((uint32_t)u.e[j] >> k) & 1u) ^ 1u;
+    return c;
+}
+
 template <typename TIN, typename TOUT, bool SCATTER, bool DIRS>
-__global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
-    constexpr int kStageBytes = kTile * (sizeof(TIN) > sizeof(TOUT) ? sizeof(TIN) : sizeof(TOUT));
-    __shared__ __align__(16) unsigned char s_stage[kStageBytes];
-    __shared__ uint64_t s_words[kTileWords];
-    __shared__ uint32_t s_zpre[kTileWords];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void level_pass(LevelArgs a) {
+    using Cfg = TileCfg<TIN>;
+    constexpr int kTile = Cfg::kTile, kItems = Cfg::kItems, kWPL = Cfg::kWPL;
+    constexpr int V = 16 / sizeof(TIN);
+    __shared__ __align__(16) unsigned char s_stage[Cfg::kBytes];
+    __shared__ uint64_t s_words[Cfg::kWords];
+    __shared__ uint32_t s_zpre[Cfg::kWords];
+    __shared__ uint64_t s_D[SCATTER ? kSmallD : 1];
     __shared__ uint64_t s_Z0;
     __shared__ uint32_t s_Zt;
-    __shared__ uint32_t s_tile;
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const uint64_t tile = s_tile;
+    const uint64_t tile = blockIdx.x;
     const uint64_t t0 = tile * kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
+    const bool d_lds = SCATTER && a.nD <= (uint64_t)kSmallD;
+    if (d_lds)
+        for (int i = tid; i < (int)a.nD; i += kBlock) s_D[i] = a.D[i];
 
-    // 1. Coalesced 16-byte loads of the tile into LDS (blocked layout).
+    // 1. Coalesced 16-byte loads of the tile into LDS.
     TIN *stage_in = reinterpret_cast<TIN *>(s_stage);
     const TIN *in = reinterpret_cast<const TIN *>(a.in) + t0;
-    constexpr int V = 16 / sizeof(TIN);
     if (len == (uint32_t)kTile) {
 #pragma unroll
         for (int r = 0; r < kItems / V; ++r) {
@@ -330,19 +362,20 @@ __global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
     }
     __syncthreads();
 
-    // 2. Striped view: item r of wave w, lane j is position r*kBlock + 64w + j,
+    // 2. Striped view: item r of wave w, lane j is position r*256 + 64w + j,
     //    so each ballot is one position-ordered word of B_l (word 4r + w).
-    uint32_t sym[kItems];
-    uint64_t wbits[kItems];
+    uint32_t pk[Cfg::kRegs];
+#pragma unroll
+    for (int i = 0; i < Cfg::kRegs; ++i) pk[i] = 0;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         uint32_t e = (uint32_t)(r * kBlock + tid);
         bool valid = e < len;
-        sym[r] = valid ? (uint32_t)stage_in[e] : 0u;
-        bool bit = valid && ((sym[r] >> k) & 1u);
+        uint32_t sym = valid ? (uint32_t)stage_in[e] : 0u;
+        pk[r / Cfg::kPer] |= sym << (8 * sizeof(TIN) * (r % Cfg::kPer));
+        bool bit = valid && ((sym >> k) & 1u);
         uint64_t vm = __ballot(valid);
         uint64_t w = __ballot(bit);
-        wbits[r] = w;
         if (lane == 0) {
             s_words[r * kWaves + wave] = w;
             s_zpre[r * kWaves + wave] = (uint32_t)(__popcll(vm) - __popcll(w));
@@ -350,22 +383,50 @@ __global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
     }
     __syncthreads();
 
-    // 3. Wave 0: scan of the 64 word zero-counts, look-back across tiles,
-    //    bit words to HBM, directory entries.
+    // 3. Wave 0: scan of the word zero-counts, look-back across tiles, bit
+    //    words to HBM, directory entries.
     if (wave == 0) {
-        uint32_t zc = s_zpre[lane];
-        uint32_t inc = wave_incl_scan_u32(zc, lane);
-        uint32_t excl = inc - zc;
+        uint32_t zp[kWPL];
+        uint64_t wd[kWPL];
+        uint32_t own = 0;
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            zp[m] = own;
+            own += s_zpre[lane * kWPL + m];
+            wd[m] = s_words[lane * kWPL + m];
+        }
+        uint32_t inc = wave_incl_scan_u32(own, lane);
         uint32_t Zt = __shfl(inc, kWave - 1, kWave);
-        uint64_t Z0 = lookback_exclusive(a.tile_state, tile, Zt, lane);
-        s_zpre[lane] = excl;
+        // Fallback reduction of a predecessor tile: zeros of bit k in it.
+        auto zeros_of_tile = [&](uint64_t ft) -> uint64_t {
+            const TIN *p = reinterpret_cast<const TIN *>(a.in) + ft * kTile;
+            const uint32_t flen = (uint32_t)min((uint64_t)kTile, a.n - ft * kTile);
+            uint64_t c = 0;
+            if (flen == (uint32_t)kTile) {
+                for (int i = lane; i < kTile / V; i += kWave)
+                    c += zero_bits<TIN>(reinterpret_cast<const uint4 *>(p)[i], k);
+            } else {
+                for (uint32_t e = (uint32_t)lane; e < flen; e += kWave) c += (((uint32_t)p[e] >> k) & 1u) ^ 1u;
+            }
+            return wave_sum_u64(c);
+        };
+        uint64_t Z0 = lookback_exclusive<4>(a.tile_state, tile, Zt, lane, a.spin_limit, zeros_of_tile);
+        const uint32_t ex = inc - own;
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            zp[m] += ex;
+            s_zpre[lane * kWPL + m] = zp[m];
+        }
         if (lane == 0) {
             s_Z0 = Z0;
             s_Zt = Zt;
         }
-        uint64_t word = s_words[lane];
-        if ((uint32_t)lane * 64u < len) a.bits[(t0 >> 6) + lane] = word;
-        if (DIRS) emit_directories(word, excl, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            uint32_t w = (uint32_t)lane * kWPL + m;
+            if (w * 64u < len) a.bits[(t0 >> 6) + w] = wd[m];
+        }
+        if (DIRS) emit_directories<kWPL>(wd, zp, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
     }
     if (!SCATTER) return;
     __syncthreads();
@@ -382,10 +443,12 @@ __global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
     for (int r = 0; r < kItems; ++r) {
         uint32_t e = (uint32_t)(r * kBlock + tid);
         if (e < len) {
-            uint64_t w = wbits[r];
+            uint64_t w = s_words[r * kWaves + wave];
             uint32_t zl = s_zpre[r * kWaves + wave] + (uint32_t)__popcll(~w & lt);
             uint32_t slot = ((w >> lane) & 1ull) ? Zt + (e - zl) : zl;
-            stage_out[slot] = (TOUT)sym[r];
+            uint32_t sym = (pk[r / Cfg::kPer] >> (8 * sizeof(TIN) * (r % Cfg::kPer))) &
+                           (sizeof(TIN) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(TIN))) - 1u));
+            stage_out[slot] = (TOUT)sym;
         }
     }
     __syncthreads();
@@ -397,15 +460,204 @@ __global__ __launch_bounds__(kBlock) void level_pass(LevelArgs a) {
     //    counts rebased to level-wide counts through the tables.
     TOUT *out = reinterpret_cast<TOUT *>(a.out);
     const uint64_t O0 = t0 - Z0;
-#pragma unroll
+#pragma unroll 4
     for (int r = 0; r < kItems; ++r) {
         uint32_t s = (uint32_t)(r * kBlock + tid);
         if (s < len) {
             TOUT v = stage_out[s];
             uint64_t q = (uint64_t)((uint32_t)v >> k);
             if (q < a.nD) {
-                uint64_t dest = a.D[q] + (s < Zt ? Z0 + s : O0 + (s - Zt));
+                uint64_t base = d_lds ? s_D[q] : a.D[q];
+                uint64_t dest = base + (s < Zt ? Z0 + s : O0 + (s - Zt));
                 if (dest < a.n) out[dest] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level pass for byte symbols (n < 2^32): the same steps as level_pass with
+// SWAR arithmetic, since at HBM rate a byte symbol leaves only about ten
+// lane operations per level.  A tile is 4 rows of 4096 bytes; thread t owns
+// bytes [16t, 16t+16) of every row as four dwords.
+//   bits:  a 4x4 byte transpose (v_perm) lines bit k of the 16 bytes up so
+//          that a few shifts and ORs give them as a 16-bit mask in position
+//          order; four lanes' masks are one word of B_l, so the LDS array of
+//          masks read as 64-bit words *is* the tile's slice of B_l.
+//   scan:  two rows per 32-bit value (16-bit fields), one wave scan each.
+//   split: bytes go to their LDS slot while wave 0 runs the look-back.
+//   scatter: four slots per lane; inside one run (same node, same bit) the
+//          four bytes have consecutive destinations and leave as one
+//          (possibly unaligned) dword store.
+typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
+
+__device__ __forceinline__ uint32_t mask16_bit(uint4 d, uint32_t k) {
+    // Transpose so that byte B of t_i is byte 4B+i of the chunk ...
+    const uint32_t a0 = __builtin_amdgcn_perm(d.y, d.x, 0x05010400u);
+    const uint32_t a1 = __builtin_amdgcn_perm(d.y, d.x, 0x07030602u);
+    const uint32_t a2 = __builtin_amdgcn_perm(d.w, d.z, 0x05010400u);
+    const uint32_t a3 = __builtin_amdgcn_perm(d.w, d.z, 0x07030602u);
+    const uint32_t t0 = __builtin_amdgcn_perm(a2, a0, 0x05040100u);
+    const uint32_t t1 = __builtin_amdgcn_perm(a2, a0, 0x07060302u);
+    const uint32_t t2 = __builtin_amdgcn_perm(a3, a1, 0x05040100u);
+    const uint32_t t3 = __builtin_amdgcn_perm(a3, a1, 0x07060302u);
+    // ... then byte B of u holds bit k of chunk bytes 4B..4B+3 at bits 0..3.
+    const uint32_t M = 0x01010101u;
+    uint32_t u = ((t0 >> k) & M) | (((t1 >> k) & M) << 1) | (((t2 >> k) & M) << 2) | (((t3 >> k) & M) << 3);
+    u |= u >> 4;
+    return (u & 0xFFu) | ((u >> 8) & 0xFF00u);
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4 &d, int b) {
+    const uint32_t w = b < 4 ? d.x : (b < 8 ? d.y : (b < 12 ? d.z : d.w));
+    return (w >> (8 * (b & 3))) & 0xFFu;
+}
+
+template <bool SCATTER, bool DIRS>
+__global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
+    constexpr int kTile = 16384, kRows = 4, kRowBytes = 4096;
+    __shared__ __align__(16) uint8_t s_stage[kTile];
+    __shared__ __align__(16) uint16_t s_m16[kTile / 16];  // 256 words of B_l
+    __shared__ uint32_t s_wz[kRows][kWaves];
+    __shared__ uint32_t s_zpre[kTile / 64];
+    __shared__ uint32_t s_D[SCATTER ? 256 : 1];
+    __shared__ uint32_t s_Z0;
+
+    if (*a.status) return;  // uniform across the grid: the input was rejected
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t tile = blockIdx.x;
+    const uint32_t t0 = tile * (uint32_t)kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
+    const uint32_t k = a.k;
+    if (SCATTER)
+        for (int i = tid; i < (int)a.nD; i += kBlock) s_D[i] = (uint32_t)a.D[i];
+
+    // Load: thread t, row r holds positions r*4096 + 16t .. +15.
+    const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
+    uint4 d[kRows];
+    uint32_t m[kRows], z[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+        if (p + 16 <= len) {
+            d[r] = *reinterpret_cast<const uint4 *>(in + p);
+        } else {
+            uint32_t w[4] = {0, 0, 0, 0};
+            for (uint32_t j = 0; j < 16 && p + j < len; ++j) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+            d[r] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+        const uint32_t nv = p >= len ? 0u : min(16u, len - p);
+        m[r] = mask16_bit(d[r], k) & ((1u << nv) - 1u);
+        z[r] = nv - (uint32_t)__popc(m[r]);
+        s_m16[r * kBlock + tid] = (uint16_t)m[r];
+    }
+
+    // Zero-count scan in position order (rows outer, threads inner).
+    const uint32_t v01 = z[0] | (z[1] << 16), v23 = z[2] | (z[3] << 16);
+    const uint32_t i01 = wave_incl_scan_u32(v01, lane), i23 = wave_incl_scan_u32(v23, lane);
+    if (lane == kWave - 1) {
+        s_wz[0][wave] = i01 & 0xFFFFu;
+        s_wz[1][wave] = i01 >> 16;
+        s_wz[2][wave] = i23 & 0xFFFFu;
+        s_wz[3][wave] = i23 >> 16;
+    }
+    __syncthreads();
+    const uint32_t e01 = i01 - v01, e23 = i23 - v23;
+    const uint32_t we[kRows] = {e01 & 0xFFFFu, e01 >> 16, e23 & 0xFFFFu, e23 >> 16};
+    uint32_t zl[kRows], acc = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t x = s_wz[r][w];
+            before += w < wave ? x : 0u;
+            tot += x;
+        }
+        zl[r] = acc + before + we[r];
+        acc += tot;
+    }
+    const uint32_t Zt = acc;
+    if ((tid & 3) == 0)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) s_zpre[r * (kBlock / 4) + tid / 4] = zl[r];
+    __syncthreads();
+
+    // Bit words of the tile (word tid = s_m16[4 tid .. 4 tid + 3]).
+    const uint64_t *s_w64 = reinterpret_cast<const uint64_t *>(s_m16);
+    if ((uint32_t)tid * 64u < len) a.bits[(t0 >> 6) + tid] = s_w64[tid];
+
+    if (wave == 0) {
+        auto zeros_of_tile = [&](uint64_t ft) -> uint64_t {
+            const uint8_t *p = reinterpret_cast<const uint8_t *>(a.in) + ft * kTile;
+            const uint32_t flen = (uint32_t)min((uint64_t)kTile, a.n - ft * kTile);
+            uint64_t c = 0;
+            if (flen == (uint32_t)kTile) {
+                const uint32_t M = 0x01010101u << k;
+                for (int i = lane; i < kTile / 16; i += kWave) {
+                    const uint4 q = reinterpret_cast<const uint4 *>(p)[i];
+                    c += 16u - (uint32_t)(__popc(q.x & M) + __popc(q.y & M) + __popc(q.z & M) + __popc(q.w & M));
+                }
+            } else {
+                for (uint32_t e = (uint32_t)lane; e < flen; e += kWave) c += (((uint32_t)p[e] >> k) & 1u) ^ 1u;
+            }
+            return wave_sum_u64(c);
+        };
+        const uint64_t Z0 = lookback_exclusive<4>(a.tile_state, tile, Zt, lane, a.spin_limit, zeros_of_tile);
+        if (lane == 0) s_Z0 = (uint32_t)Z0;
+        if (DIRS) {
+            uint64_t wd[4];
+            uint32_t zp[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                wd[j] = s_w64[lane * 4 + j];
+                zp[j] = s_zpre[lane * 4 + j];
+            }
+            emit_directories<4>(wd, zp, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
+        }
+    }
+    if (!SCATTER) return;
+
+    // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+        uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (e0 + b < len) {
+                const uint32_t bit = (m[r] >> b) & 1u;
+                s_stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
+                zc += bit ^ 1u;
+                oc += bit;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Scatter (see level_pass for the destination formula).
+    const uint32_t Z0 = s_Z0, O0 = t0 - Z0;
+    uint8_t *out = reinterpret_cast<uint8_t *>(a.out);
+    const uint32_t *s_st32 = reinterpret_cast<const uint32_t *>(s_stage);
+#pragma unroll 4
+    for (int i = 0; i < kTile / (4 * kBlock); ++i) {
+        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 4u * j;
+        if (sl >= len) break;
+        const uint32_t v = s_st32[j];
+        const uint32_t q0 = (v & 0xFFu) >> k, q3 = (v >> 24) >> k;
+        if (sl + 3 < len && q0 == q3) {
+            // One run: bit value is the low bit of q, so the region is uniform too.
+            const uint32_t dest = s_D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
+            if ((uint64_t)dest + 3 < a.n) *reinterpret_cast<u32_unaligned *>(out + dest) = v;
+        } else {
+            for (uint32_t c = 0; c < 4 && sl + c < len; ++c) {
+                const uint32_t bc = (v >> (8 * c)) & 0xFFu, qc = bc >> k, sc = sl + c;
+                const uint32_t dest = s_D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
+                if (dest < a.n) out[dest] = (uint8_t)bc;
             }
         }
     }
@@ -439,27 +691,34 @@ __global__ void dir_finish(const uint64_t *D, const uint64_t *zeros_tot, uint64_
 // Standalone directories from existing bits: one wave per tile of 64 words
 // of one level (grid.y = level), zero-count look-back per level.
 __global__ __launch_bounds__(kWave) void dir_tiles(const uint64_t *bits, uint64_t n, uint64_t W,
-                                                   uint64_t *state, uint64_t T, uint32_t *tickets,
-                                                   uint64_t *zeros_tot, uint64_t *rank, uint64_t rank_len,
-                                                   uint64_t *sel1, uint64_t *sel0, uint64_t cap) {
+                                                   uint64_t *state, uint64_t T, uint64_t *zeros_tot,
+                                                   uint64_t *rank, uint64_t rank_len, uint64_t *sel1,
+                                                   uint64_t *sel0, uint64_t cap, int spin_limit) {
     const uint32_t l = blockIdx.y;
     const int lane = lane_id();
-    uint32_t tk = 0;
-    if (lane == 0) tk = atomicAdd(tickets + l, 1u);
-    const uint64_t tile = (uint64_t)__shfl(tk, 0, kWave);
-    const uint64_t t0 = tile * kTile;
-    const uint32_t len = (uint32_t)min((uint64_t)kTile, n - t0);
+    const uint64_t tile = blockIdx.x;
+    const uint64_t t0 = tile * kDirTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kDirTile, n - t0);
     const uint64_t wi = (t0 >> 6) + lane;
     const bool has = (uint32_t)lane * 64u < len;
     const uint64_t word = has ? bits[(uint64_t)l * W + wi] : 0ull;
     const uint32_t nb = has ? min(64u, len - (uint32_t)lane * 64u) : 0u;
     const uint32_t zc = nb - (uint32_t)__popcll(word);
     uint32_t inc = wave_incl_scan_u32(zc, lane);
-    uint32_t excl = inc - zc;
     uint32_t Zt = __shfl(inc, kWave - 1, kWave);
-    uint64_t Z0 = lookback_exclusive(state + (uint64_t)l * T, tile, Zt, lane);
-    emit_directories(word, excl, Z0, t0, len, Zt, n, rank + (uint64_t)l * rank_len, sel1 + (uint64_t)l * cap,
-                     sel0 + (uint64_t)l * cap, lane);
+    auto zeros_of_tile = [&](uint64_t ft) -> uint64_t {
+        const uint64_t f0 = ft * kDirTile;
+        const uint32_t flen = (uint32_t)min((uint64_t)kDirTile, n - f0);
+        const bool fh = (uint32_t)lane * 64u < flen;
+        const uint32_t fnb = fh ? min(64u, flen - (uint32_t)lane * 64u) : 0u;
+        const uint64_t fw = fh ? bits[(uint64_t)l * W + (f0 >> 6) + lane] : 0ull;
+        return wave_sum_u64((uint64_t)(fnb - (uint32_t)__popcll(fw)));
+    };
+    uint64_t Z0 = lookback_exclusive<4>(state + (uint64_t)l * T, tile, Zt, lane, spin_limit, zeros_of_tile);
+    const uint64_t wd[1] = {word};
+    const uint32_t zp[1] = {inc - zc};
+    emit_directories<1>(wd, zp, Z0, t0, len, Zt, n, rank + (uint64_t)l * rank_len, sel1 + (uint64_t)l * cap,
+                        sel0 + (uint64_t)l * cap, lane);
     if (tile == T - 1 && lane == 0) zeros_tot[l] = Z0 + Zt;
 }
 
@@ -469,7 +728,7 @@ struct Plan {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
-    uint64_t off_status, off_tickets, off_states, off_D, off_part, off_S0, off_S1, total;
+    uint64_t off_status, off_states, off_D, off_part, off_S0, off_S1, total;
     uint64_t n_part;
 };
 
@@ -490,7 +749,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     p.in_bytes = (uint32_t)sym_bytes;
     p.mid_bytes = p.L <= 8 ? 1u : (p.L <= 16 ? 2u : 4u);  // width of S_l for l >= 1
     p.W = cdiv(n, 64);
-    p.T = cdiv(n, kTile);
+    p.T = cdiv(n, kMinTile);
     p.rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1;
     p.cap = cdiv(n, WT_SELECT_SAMPLE) + 1;
     const uint64_t table_elems = p.L ? (1ull << p.L) : 0;        // node heap indices [0, 2^L)
@@ -501,8 +760,6 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     uint64_t o = 0;
     p.off_status = o;
     o += 256;
-    p.off_tickets = o;
-    o = align_up(o + 4ull * std::max<uint32_t>(p.L, 1u), 256);
     p.off_states = o;
     o = align_up(o + 8ull * p.L * p.T, 256);
     p.off_D = o;
@@ -519,6 +776,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
 }
 
 static bool g_timing = false;
+static int g_spin_limit = 8;
 static std::mutex g_timing_mu;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;  // recorded, not yet collected
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_free;
@@ -542,8 +800,19 @@ static int timing_end(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
 }
 
 template <typename TIN, typename TOUT>
-static void launch_level(bool scatter, bool dirs, uint64_t T, hipStream_t s, const LevelArgs &a) {
-    dim3 grid((unsigned)T), block(kBlock);
+static void launch_level(bool scatter, bool dirs, hipStream_t s, const LevelArgs &a) {
+    if (sizeof(TIN) == 1 && sizeof(TOUT) == 1 && a.n < (1ull << 32)) {
+        dim3 g8((unsigned)cdiv(a.n, 16384)), b8(kBlock);
+        if (scatter) {
+            if (dirs) level_pass_u8<true, true><<<g8, b8, 0, s>>>(a);
+            else level_pass_u8<true, false><<<g8, b8, 0, s>>>(a);
+        } else {
+            if (dirs) level_pass_u8<false, true><<<g8, b8, 0, s>>>(a);
+            else level_pass_u8<false, false><<<g8, b8, 0, s>>>(a);
+        }
+        return;
+    }
+    dim3 grid((unsigned)cdiv(a.n, TileCfg<TIN>::kTile)), block(kBlock);
     if (scatter) {
         if (dirs) level_pass<TIN, TOUT, true, true><<<grid, block, 0, s>>>(a);
         else level_pass<TIN, TOUT, true, false><<<grid, block, 0, s>>>(a);
@@ -553,11 +822,11 @@ static void launch_level(bool scatter, bool dirs, uint64_t T, hipStream_t s, con
     }
 }
 
-static void launch_level_any(uint32_t tin, uint32_t tout, bool scatter, bool dirs, uint64_t T, hipStream_t s,
+static void launch_level_any(uint32_t tin, uint32_t tout, bool scatter, bool dirs, hipStream_t s,
                              const LevelArgs &a) {
 #define WT_LV(I, O)                                            \
     if (tin == sizeof(I) && tout == sizeof(O)) {               \
-        launch_level<I, O>(scatter, dirs, T, s, a);            \
+        launch_level<I, O>(scatter, dirs, s, a);               \
         return;                                                \
     }
     WT_LV(uint8_t, uint8_t)
@@ -615,10 +884,9 @@ extern "C" int wt_plan(uint64_t n, uint64_t sigma, int sym_bytes, wt_layout *out
 }
 
 extern "C" uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L) {
-    uint64_t T = cdiv(n, kTile);
-    // tickets, per-level zero totals, per-level look-back states
-    return align_up(4ull * std::max<uint32_t>(L, 1u), 256) + align_up(8ull * std::max<uint32_t>(L, 1u), 256) +
-           align_up(8ull * L * T, 256);
+    uint64_t T = cdiv(n, kDirTile);
+    // per-level zero totals, per-level look-back states
+    return align_up(8ull * std::max<uint32_t>(L, 1u), 256) + align_up(8ull * L * T, 256);
 }
 
 extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
@@ -635,12 +903,11 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     hipStream_t s = (hipStream_t)stream;
     unsigned char *sc = (unsigned char *)d_scratch;
     uint32_t *status = (uint32_t *)(sc + p.off_status);
-    uint32_t *tickets = (uint32_t *)(sc + p.off_tickets);
     uint64_t *states = (uint64_t *)(sc + p.off_states);
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint64_t *part = (uint64_t *)(sc + p.off_part);
 
-    // Zero: status + tickets + states (one contiguous range), and C.
+    // Zero: status + look-back states (one contiguous range), and C.
     {
         uint64_t na = p.off_D / 8, nb = sigma + 1;
         uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
@@ -694,16 +961,16 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         a.D = D + ((2ull << l) - 2);
         a.nD = 2ull << l;
         a.tile_state = states + (uint64_t)l * p.T;
-        a.ticket = tickets + l;
         a.status = status;
         a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
         a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
         a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
         a.n = n;
         a.k = p.L - 1 - l;
+        a.spin_limit = g_spin_limit;
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (g_timing && (rc = timing_begin(s, ev))) return rc;
-        launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, p.T, s, a);
+        launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);
         if (g_timing && (rc = timing_end(s, ev))) return rc;
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
         cur = dst;
@@ -721,19 +988,18 @@ extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t
     if ((uintptr_t)d_scratch & 255u) return WT_ERR_ARG;
     if (scratch_bytes < wt_rank_select_scratch_bytes(n, L)) return WT_ERR_SCRATCH;
     hipStream_t s = (hipStream_t)stream;
-    const uint64_t W = cdiv(n, 64), T = cdiv(n, kTile), rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1,
+    const uint64_t W = cdiv(n, 64), T = cdiv(n, kDirTile), rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1,
                    cap = cdiv(n, WT_SELECT_SAMPLE) + 1;
     unsigned char *sc = (unsigned char *)d_scratch;
-    uint32_t *tickets = (uint32_t *)sc;
-    uint64_t *zeros_tot = (uint64_t *)(sc + align_up(4ull * L, 256));
-    uint64_t *states = (uint64_t *)(sc + align_up(4ull * L, 256) + align_up(8ull * L, 256));
+    uint64_t *zeros_tot = (uint64_t *)sc;
+    uint64_t *states = (uint64_t *)(sc + align_up(8ull * L, 256));
     uint64_t nz = wt_rank_select_scratch_bytes(n, L) / 8;
     zero_fill<<<(unsigned)std::min<uint64_t>(cdiv(nz, kBlock), 4096), kBlock, 0, s>>>((uint64_t *)sc, nz, nullptr,
                                                                                        0);
     if (T > 0) {
         dim3 g((unsigned)T, L);
-        dir_tiles<<<g, kWave, 0, s>>>(d_bits, n, W, states, T, tickets, zeros_tot, d_rank, rank_len, d_sel1, d_sel0,
-                                      cap);
+        dir_tiles<<<g, kWave, 0, s>>>(d_bits, n, W, states, T, zeros_tot, d_rank, rank_len, d_sel1, d_sel0, cap,
+                                      g_spin_limit);
     }
     dim3 g2((unsigned)cdiv(cap, kBlock), L);
     dir_finish<<<g2, kBlock, 0, s>>>(nullptr, zeros_tot, n, L, d_rank, rank_len, d_sel1, d_sel0, cap, d_sel_counts);
@@ -747,6 +1013,12 @@ extern "C" int wt_status_get(const void *d_scratch, void *stream) {
         return WT_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return WT_ERR_HIP;
     return st == 0 ? WT_OK : (st == kStatusSymbol ? WT_ERR_SYMBOL : WT_ERR_HIP);
+}
+
+extern "C" int wt_set_lookback_spin_limit(int polls) {
+    if (polls < 0) return WT_ERR_ARG;
+    g_spin_limit = polls;
+    return WT_OK;
 }
 
 extern "C" int wt_timing_enable(int enable) {

@@ -68,71 +68,118 @@ __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
     return pos;
 }
 
-// Decoupled look-back, run by one full wave.  Publishes `agg` for `tile`
-// and returns the exclusive prefix (sum of the aggregates of all earlier
-// tiles).  Tiles are numbered in the order blocks obtained them from an
-// atomic ticket, so every tile this one waits on belongs to a block that is
-// already running and publishes its aggregate without waiting itself.
-__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *state, uint64_t tile, uint64_t agg,
-                                                       int lane) {
+// Decoupled look-back with fallback, run by one full wave.  Publishes `agg`
+// for `tile` and returns the exclusive prefix (sum of the aggregates of all
+// earlier tiles).  Each poll reads a window of 64*LBM predecessors (LBM
+// loads in flight per lane), so a long run of tiles that have published
+// only their aggregates costs few round trips.  Tile numbers are block
+// indices, so nothing guarantees that an earlier tile's block has been
+// scheduled: when the closest predecessor still missing has not published
+// after `spin_limit` polls, the wave computes that tile's aggregate itself
+// with `agg_of(tile)` (a pure function of the input) and counts it locally
+// (Smith, Levien & Owens, "Decoupled Fallback: A Portable Single-Pass GPU
+// Scan").  Every wait therefore ends, whatever the dispatch order, and the
+// only words written are this tile's own (relaxed agent-scope stores).
+template <int LBM, typename AggOf>
+__device__ __forceinline__ uint64_t lookback_exclusive(uint64_t *state, uint64_t tile, uint64_t agg, int lane,
+                                                       int spin_limit, AggOf agg_of) {
+    constexpr int kWin = LBM * kWave;
     if (tile == 0) {
         if (lane == 0) st_relaxed(state, kStInc | agg);
         return 0;
     }
     if (lane == 0) st_relaxed(state + tile, kStAgg | agg);
     uint64_t excl = 0;
-    int64_t base = (int64_t)tile - 1;
+    int64_t base = (int64_t)tile - 1;  // closest predecessor not yet counted
+    int spins = 0;
     for (;;) {
-        int64_t idx = base - lane;
-        uint64_t v = idx >= 0 ? ld_relaxed(state + idx) : kStInc;
-        uint32_t st = (uint32_t)(v >> 62);
-        uint64_t inc_mask = __ballot(st == 2u);
-        uint64_t bad_mask = __ballot(st == 0u);
-        int first_inc = inc_mask ? __ffsll((unsigned long long)inc_mask) - 1 : kWave;
-        uint64_t need = first_inc >= kWave - 1 ? ~0ull : ((2ull << first_inc) - 1ull);
-        if (bad_mask & need) {
-            __builtin_amdgcn_s_sleep(1);
+        uint64_t v[LBM];
+#pragma unroll
+        for (int m = 0; m < LBM; ++m) {
+            int64_t idx = base - (m * kWave + lane);
+            v[m] = idx >= 0 ? ld_relaxed(state + idx) : kStInc;  // "tile -1" is an empty inclusive prefix
+        }
+        int f = kWin, b = kWin;  // closest inclusive, closest missing (distance from base)
+#pragma unroll
+        for (int m = 0; m < LBM; ++m) {
+            uint32_t st = (uint32_t)(v[m] >> 62);
+            uint64_t inc = __ballot(st == 2u), bad = __ballot(st == 0u);
+            if (f == kWin && inc) f = m * kWave + __ffsll((unsigned long long)inc) - 1;
+            if (b == kWin && bad) b = m * kWave + __ffsll((unsigned long long)bad) - 1;
+        }
+        uint64_t part = 0;
+        const int lim = b < f ? b : f + 1;  // count distances < lim
+#pragma unroll
+        for (int m = 0; m < LBM; ++m)
+            if (m * kWave + lane < lim) part += v[m] & kStVal;
+        excl += wave_sum_u64(part);
+        if (b < f) {
+            // Counted the ready aggregates before the missing tile; now wait
+            // for it or reduce it here.
+            base -= b;
+            if (b > 0) {
+                spins = 0;
+            } else if (++spins >= spin_limit) {
+                excl += agg_of((uint64_t)base);
+                base -= 1;
+                spins = 0;
+            } else {
+                __builtin_amdgcn_s_sleep(2);
+            }
             continue;
         }
-        uint64_t val = lane <= first_inc ? (v & kStVal) : 0ull;
-        excl += wave_sum_u64(val);
-        if (first_inc < kWave) break;
-        base -= kWave;
+        if (f < kWin) break;
+        base -= kWin;
     }
     if (lane == 0) st_relaxed(state + tile, kStInc | (excl + agg));
     return excl;
 }
 
-// Directory entries for one tile of up to 64 level words, run by one wave
-// (lane j holds word j of the tile).  zpre = zeros before word j inside the
-// tile, Z0 = zeros of the level before the tile, t0 = first position of the
-// tile (a multiple of 4096), len = valid positions in the tile, n = level
-// length (an ordinal >= n cannot exist, so it is never written).
-__device__ __forceinline__ void emit_directories(uint64_t word, uint32_t zpre, uint64_t Z0, uint64_t t0,
-                                                 uint32_t len, uint32_t Ztile, uint64_t n, uint64_t *rank,
-                                                 uint64_t *sel1, uint64_t *sel0, int lane) {
-    const bool has = (uint32_t)lane * 64u < len;
-    const uint32_t nb = has ? min(64u, len - (uint32_t)lane * 64u) : 0u;
-    const uint64_t vmask = nb >= 64u ? ~0ull : ((1ull << nb) - 1ull);
-    // rank[j] = ones before position 512 j (positions before the word are all valid).
-    if (has && (lane & 7) == 0)
-        rank[(t0 >> 9) + (uint64_t)(lane >> 3)] = (t0 + (uint64_t)lane * 64u) - (Z0 + zpre);
+// Directory entries for one tile of up to 64*WPL level words, run by one
+// wave; lane j holds words j*WPL .. j*WPL+WPL-1 (position order).
+// zpre[m] = zeros before word m of the lane inside the tile, Z0 = zeros of
+// the level before the tile, t0 = first position of the tile (a multiple of
+// 4096), len = valid positions in the tile, n = level length (an ordinal
+// >= n cannot exist, so it is never written).
+template <int WPL>
+__device__ __forceinline__ void emit_directories(const uint64_t (&word)[WPL], const uint32_t (&zpre)[WPL],
+                                                 uint64_t Z0, uint64_t t0, uint32_t len, uint32_t Ztile,
+                                                 uint64_t n, uint64_t *rank, uint64_t *sel1, uint64_t *sel0,
+                                                 int lane) {
+    constexpr uint64_t S = 4096;
     const uint64_t O0 = t0 - Z0;
     const uint32_t Otile = len - Ztile;
-    const uint32_t opre = (uint32_t)lane * 64u - zpre;
-    const uint32_t ow = (uint32_t)__popcll(word);
-    const uint64_t zword = ~word & vmask;
-    const uint32_t zw = (uint32_t)__popcll(zword);
-    constexpr uint64_t S = 4096;
+#pragma unroll
+    for (int m = 0; m < WPL; ++m) {
+        const uint32_t w = (uint32_t)lane * WPL + m;
+        // rank[j] = ones before position 512 j (positions before the word are all valid).
+        if (w * 64u < len && (w & 7u) == 0)
+            rank[(t0 >> 9) + (w >> 3)] = (t0 + (uint64_t)w * 64u) - (Z0 + zpre[m]);
+    }
     for (uint64_t o = (O0 + S - 1) / S * S; o < O0 + Otile; o += S) {
-        uint32_t loc = (uint32_t)(o - O0);
-        if (has && o < n && opre <= loc && loc < opre + ow)
-            sel1[o / S] = t0 + (uint64_t)lane * 64u + select_in_word(word, loc - opre);
+        const uint32_t loc = (uint32_t)(o - O0);
+#pragma unroll
+        for (int m = 0; m < WPL; ++m) {
+            const uint32_t w = (uint32_t)lane * WPL + m;
+            const uint32_t opre = w * 64u - zpre[m];
+            const uint32_t ow = w * 64u < len ? (uint32_t)__popcll(word[m]) : 0u;
+            if (o < n && opre <= loc && loc < opre + ow)
+                sel1[o / S] = t0 + (uint64_t)w * 64u + select_in_word(word[m], loc - opre);
+        }
     }
     for (uint64_t o = (Z0 + S - 1) / S * S; o < Z0 + Ztile; o += S) {
-        uint32_t loc = (uint32_t)(o - Z0);
-        if (has && o < n && zpre <= loc && loc < zpre + zw)
-            sel0[o / S] = t0 + (uint64_t)lane * 64u + select_in_word(zword, loc - zpre);
+        const uint32_t loc = (uint32_t)(o - Z0);
+#pragma unroll
+        for (int m = 0; m < WPL; ++m) {
+            const uint32_t w = (uint32_t)lane * WPL + m;
+            const bool has = w * 64u < len;
+            const uint32_t nb = has ? min(64u, len - w * 64u) : 0u;
+            const uint64_t vmask = nb >= 64u ? ~0ull : ((1ull << nb) - 1ull);
+            const uint64_t zword = ~word[m] & vmask;
+            const uint32_t zw = (uint32_t)__popcll(zword);
+            if (o < n && zpre[m] <= loc && loc < zpre[m] + zw)
+                sel0[o / S] = t0 + (uint64_t)w * 64u + select_in_word(zword, loc - zpre[m]);
+        }
     }
 }
 

@@ -22,7 +22,7 @@ RANK_BLOCK_BITS = 512
 SELECT_SAMPLE = 4096
 
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
-           "wt_access", "wt_rank", "wt_select", "wt_timing_enable", "wt_timing_collect"]
+           "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect"]
 
 
 class WTError(RuntimeError):
@@ -70,10 +70,11 @@ def lib() -> ctypes.CDLL:
         L.wt_access.argtypes = [ctypes.POINTER(View), vp, u64, vp, vp]
         L.wt_rank.argtypes = [ctypes.POINTER(View), vp, vp, u64, vp, vp]
         L.wt_select.argtypes = [ctypes.POINTER(View), vp, vp, u64, vp, vp]
+        L.wt_set_lookback_spin_limit.argtypes = [i32]
         L.wt_timing_enable.argtypes = [i32]
         L.wt_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
-                  "wt_select", "wt_timing_enable", "wt_timing_collect"):
+                  "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -214,6 +215,10 @@ def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
                                     _ptr(counts), _ptr(scratch), scratch.numel(), _stream(stream))
     _check(rc, "wt_build_rank_select")
     return {"rank": rank, "sel1": sel1, "sel0": sel0, "sel_counts": counts, "_scratch": scratch}
+
+
+def set_lookback_spin_limit(polls: int):
+    _check(lib().wt_set_lookback_spin_limit(polls), "wt_set_lookback_spin_limit")
 
 
 def timing_enable(on: bool = True):

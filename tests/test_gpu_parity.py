@@ -205,3 +205,22 @@ def test_queries_exhaustive_tiny(wtmod):
                              torch.from_numpy(ks.ravel()).cuda()).cpu().numpy()
         want = [pins.naive_select(S, int(c), int(k)) if c < sigma else -1 for c, k in zip(cs.ravel(), ks.ravel())]
         assert list(got) == want
+
+
+def test_lookback_fallback_forced(wtmod, oracle_mod):
+    """Spin limit 0: every tile that finds a predecessor unpublished reduces it
+    itself instead of waiting; outputs must not change."""
+    wtmod.set_lookback_spin_limit(0)
+    try:
+        for cfg, n in [("text256", 1 << 21), ("alpha20", 1 << 19), ("uniform256", 1 << 20)]:
+            S, sigma = inputs.workload(cfg, n)
+            check_against_oracle(wtmod, oracle_mod, S, sigma, f"fallback {cfg} n={n}")
+        S = np.random.default_rng(9).integers(0, 256, 300001).astype(np.uint8)
+        t = gpu_build(wtmod, S, 256, directories=False)
+        d = wtmod.build_rank_select(t.bits, S.size, t.L)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy().view(np.uint64) for k, v in d.items() if not k.startswith("_")}
+        want = oracle_mod.rank_select(oracle_mod.build(S, 256)["bits"], S.size, t.L)
+        assert_same(got, want, keys=("rank", "sel1", "sel0", "sel_counts"), ctx="fallback standalone")
+    finally:
+        wtmod.set_lookback_spin_limit(8)
