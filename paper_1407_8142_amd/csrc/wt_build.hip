@@ -64,46 +64,27 @@ __device__ __forceinline__ void hist_flush(uint32_t *s_hist, uint64_t *Cp1, bool
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
-                                                    uint64_t *Cp1, uint32_t *status, uint32_t reps) {
+                                                    uint64_t *Cp1, uint32_t *status, uint32_t reps, uint32_t ktop,
+                                                    uint32_t *cnt0, uint32_t tile_shift, uint64_t ntiles) {
+    // Blocks take whole tiles of level 0, so the zeros of the top bit in each
+    // tile (the count-ahead input of level 0) come out of the same read.
     extern __shared__ uint32_t s_hist_all[];
+    __shared__ uint32_t s_red[kWaves];
     const bool lds = reps > 0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     if (lds) {
         for (uint64_t i = tid; i < sigma * reps; i += kBlock) s_hist_all[i] = 0;
         __syncthreads();
     }
     uint32_t *s_hist = lds ? s_hist_all + (uint64_t)(tid % reps) * sigma : nullptr;
     constexpr int V = 16 / sizeof(T);
-    const uint64_t nvec = n / V;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint32_t tile_elems = 1u << tile_shift;
     bool bad = false;
     uint32_t cur = 0xFFFFFFFFu, cnt = 0;
-    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + tid; v < nvec; v += stride) {
-        union {
-            uint4 q;
-            T e[V];
-        } u;
-        u.q = *(const uint4 *)(S + v * V);
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            uint32_t s = (uint32_t)u.e[j];
-            if ((uint64_t)s >= sigma) {
-                bad = true;
-                continue;
-            }
-            if (s != cur) {
-                hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
-                cur = s;
-                cnt = 0;
-            }
-            ++cnt;
-        }
-    }
-    for (uint64_t i = nvec * V + (uint64_t)blockIdx.x * kBlock + tid; i < n; i += stride) {
-        uint32_t s = (uint32_t)S[i];
+    auto visit = [&](uint32_t s) -> uint32_t {
         if ((uint64_t)s >= sigma) {
             bad = true;
-            continue;
+            return 0u;
         }
         if (s != cur) {
             hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
@@ -111,6 +92,36 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
             cnt = 0;
         }
         ++cnt;
+        return ((s >> ktop) & 1u) ^ 1u;
+    };
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = tile << tile_shift;
+        const uint32_t len = (uint32_t)min((uint64_t)tile_elems, n - base);
+        uint32_t zeros = 0;
+        if (len == tile_elems) {
+            for (uint32_t v = tid; v < tile_elems / V; v += kBlock) {
+                union {
+                    uint4 q;
+                    T e[V];
+                } u;
+                u.q = *reinterpret_cast<const uint4 *>(S + base + (uint64_t)v * V);
+#pragma unroll
+                for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+            }
+        } else {
+            for (uint32_t e = tid; e < len; e += kBlock) zeros += visit((uint32_t)S[base + e]);
+        }
+        if (cnt0) {
+            uint32_t w = (uint32_t)wave_sum_u64(zeros);
+            if (lane == 0) s_red[wave] = w;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t t = 0;
+                for (int i = 0; i < kWaves; ++i) t += s_red[i];
+                cnt0[tile] = t;
+            }
+            __syncthreads();
+        }
     }
     hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
     if (bad) atomicMax(status, kStatusSymbol);
@@ -121,6 +132,41 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
             for (uint32_t r = 0; r < reps; ++r) sum += s_hist_all[(uint64_t)r * sigma + c];
             if (sum) atomicAdd((unsigned long long *)(Cp1 + c), (unsigned long long)sum);
         }
+    }
+}
+
+// Exclusive prefix of per-tile zero counts (one block of 1024 threads).
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void tile_prefix_scan(const uint32_t *cnt, uint64_t *pre, uint64_t T) {
+    __shared__ uint32_t s_w[kScanThreads / kWave];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    uint64_t carry = 0;
+    for (uint64_t c0 = 0; c0 < T; c0 += (uint64_t)kScanThreads * 16) {
+        const uint64_t base = c0 + (uint64_t)tid * 16;
+        uint32_t v[16], own = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            v[j] = base + j < T ? cnt[base + j] : 0u;
+            own += v[j];
+        }
+        const uint32_t inc = wave_incl_scan_u32(own, lane);
+        if (lane == kWave - 1) s_w[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kScanThreads / kWave; ++w) {
+            const uint32_t x = s_w[w];
+            before += w < wave ? x : 0u;
+            total += x;
+        }
+        uint64_t run = carry + before + inc - own;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (base + j < T) pre[base + j] = run;
+            run += v[j];
+        }
+        carry += total;
+        __syncthreads();
     }
 }
 
@@ -305,12 +351,64 @@ struct LevelArgs {
     uint64_t *bits;          // B_l
     const uint64_t *D;       // D_l: 2^(l+1) entries
     uint64_t nD;             // 2^(l+1)
-    uint64_t *tile_state;    // ceil(n/tile) look-back words, zeroed
+    const uint64_t *tile_prefix;  // zeros of B_l before each tile of this level
+    uint32_t *next_cnt;      // zeros of B_{l+1} per tile of the next level (accumulated here)
+    uint32_t next_shift;     // log2(positions per tile of the next level)
     const uint32_t *status;  // non-zero: input rejected, do nothing
     uint64_t *rank, *sel1, *sel0;  // directory rows of level l
     uint64_t n;
     uint32_t k;              // bit examined at this level: L-1-l
-    int spin_limit;          // look-back polls before reducing a missing predecessor
+};
+
+// Count-ahead: while level l scatters S_{l+1}, it also counts, for every tile
+// of level l+1, the zeros that tile will hold (bit k-1 of the symbols that
+// land in it).  A scan of those counts gives each tile of level l+1 its
+// exclusive zero prefix before level l+1 starts, so no tile ever waits for
+// another.  Each lane keeps a running count for the destination tile it is
+// filling and hands it to a small LDS table keyed by destination tile when
+// that tile changes (a block's runs touch few tiles); the table reaches HBM
+// as one atomic add per touched tile when the block ends, and a slot
+// collision falls back to a direct atomic.
+constexpr int kCountSlots = 64;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+struct CountTable {
+    uint32_t key[kCountSlots];
+    uint32_t cnt[kCountSlots];
+};
+
+__device__ __forceinline__ void count_init(CountTable &t, int tid) {
+    if (tid < kCountSlots) {
+        t.key[tid] = kNoTile;
+        t.cnt[tid] = 0;
+    }
+}
+
+__device__ __forceinline__ void count_add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+    const uint32_t slot = ntile & (kCountSlots - 1);
+    const uint32_t old = atomicCAS(&t.key[slot], kNoTile, ntile);
+    if (old == kNoTile || old == ntile) atomicAdd(&t.cnt[slot], c);
+    else atomicAdd(next_cnt + ntile, c);
+}
+
+__device__ __forceinline__ void count_flush(CountTable &t, uint32_t *next_cnt, int tid) {
+    if (tid < kCountSlots && t.key[tid] != kNoTile && t.cnt[tid]) atomicAdd(next_cnt + t.key[tid], t.cnt[tid]);
+}
+
+// Per-lane running count for one destination tile.
+struct LaneCount {
+    uint32_t tile = kNoTile, cnt = 0;
+    __device__ __forceinline__ void add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+        if (ntile != tile) {
+            if (cnt) count_add(t, next_cnt, tile, cnt);
+            tile = ntile;
+            cnt = 0;
+        }
+        cnt += c;
+    }
+    __device__ __forceinline__ void flush(CountTable &t, uint32_t *next_cnt) {
+        if (cnt) count_add(t, next_cnt, tile, cnt);
+        cnt = 0;
+    }
 };
 
 template <typename T>
@@ -337,6 +435,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __shared__ uint64_t s_D[SCATTER ? kSmallD : 1];
     __shared__ uint64_t s_Z0;
     __shared__ uint32_t s_Zt;
+    __shared__ CountTable s_ct;
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -347,6 +446,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const bool d_lds = SCATTER && a.nD <= (uint64_t)kSmallD;
     if (d_lds)
         for (int i = tid; i < (int)a.nD; i += kBlock) s_D[i] = a.D[i];
+    if (SCATTER) count_init(s_ct, tid);
 
     // 1. Coalesced 16-byte loads of the tile into LDS.
     TIN *stage_in = reinterpret_cast<TIN *>(s_stage);
@@ -397,20 +497,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
         uint32_t inc = wave_incl_scan_u32(own, lane);
         uint32_t Zt = __shfl(inc, kWave - 1, kWave);
-        // Fallback reduction of a predecessor tile: zeros of bit k in it.
-        auto zeros_of_tile = [&](uint64_t ft) -> uint64_t {
-            const TIN *p = reinterpret_cast<const TIN *>(a.in) + ft * kTile;
-            const uint32_t flen = (uint32_t)min((uint64_t)kTile, a.n - ft * kTile);
-            uint64_t c = 0;
-            if (flen == (uint32_t)kTile) {
-                for (int i = lane; i < kTile / V; i += kWave)
-                    c += zero_bits<TIN>(reinterpret_cast<const uint4 *>(p)[i], k);
-            } else {
-                for (uint32_t e = (uint32_t)lane; e < flen; e += kWave) c += (((uint32_t)p[e] >> k) & 1u) ^ 1u;
-            }
-            return wave_sum_u64(c);
-        };
-        uint64_t Z0 = lookback_exclusive<4>(a.tile_state, tile, Zt, lane, a.spin_limit, zeros_of_tile);
+        const uint64_t Z0 = a.tile_prefix[tile];
         const uint32_t ex = inc - own;
 #pragma unroll
         for (int m = 0; m < kWPL; ++m) {
@@ -460,6 +547,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     //    counts rebased to level-wide counts through the tables.
     TOUT *out = reinterpret_cast<TOUT *>(a.out);
     const uint64_t O0 = t0 - Z0;
+    const uint32_t kn = k - 1;  // bit of the next level
+    LaneCount lc;
 #pragma unroll 4
     for (int r = 0; r < kItems; ++r) {
         uint32_t s = (uint32_t)(r * kBlock + tid);
@@ -469,10 +558,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             if (q < a.nD) {
                 uint64_t base = d_lds ? s_D[q] : a.D[q];
                 uint64_t dest = base + (s < Zt ? Z0 + s : O0 + (s - Zt));
-                if (dest < a.n) out[dest] = v;
+                if (dest < a.n) {
+                    out[dest] = v;
+                    lc.add(s_ct, a.next_cnt, (uint32_t)(dest >> a.next_shift), (((uint32_t)v >> kn) & 1u) ^ 1u);
+                }
             }
         }
     }
+    lc.flush(s_ct, a.next_cnt);
+    __syncthreads();
+    count_flush(s_ct, a.next_cnt, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,10 +581,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
 //          masks read as 64-bit words *is* the tile's slice of B_l.
 //   scan:  two rows per 32-bit value (16-bit fields), one wave scan each.
 //   split: bytes go to their LDS slot while wave 0 runs the look-back.
-//   scatter: four slots per lane; inside one run (same node, same bit) the
-//          four bytes have consecutive destinations and leave as one
-//          (possibly unaligned) dword store.
-typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
+//   scatter: sixteen slots per lane; inside one run (same node, same bit)
+//          they have consecutive destinations and leave as one (possibly
+//          unaligned) 16-byte store.
+typedef uint32_t u128_unaligned __attribute__((ext_vector_type(4), aligned(1)));
 
 __device__ __forceinline__ uint32_t mask16_bit(uint4 d, uint32_t k) {
     // Transpose so that byte B of t_i is byte 4B+i of the chunk ...
@@ -522,6 +617,7 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     __shared__ uint32_t s_zpre[kTile / 64];
     __shared__ uint32_t s_D[SCATTER ? 256 : 1];
     __shared__ uint32_t s_Z0;
+    __shared__ CountTable s_ct;
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -529,8 +625,10 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     const uint32_t t0 = tile * (uint32_t)kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
-    if (SCATTER)
+    if (SCATTER) {
         for (int i = tid; i < (int)a.nD; i += kBlock) s_D[i] = (uint32_t)a.D[i];
+        count_init(s_ct, tid);
+    }
 
     // Load: thread t, row r holds positions r*4096 + 16t .. +15.
     const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
@@ -592,22 +690,7 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     if ((uint32_t)tid * 64u < len) a.bits[(t0 >> 6) + tid] = s_w64[tid];
 
     if (wave == 0) {
-        auto zeros_of_tile = [&](uint64_t ft) -> uint64_t {
-            const uint8_t *p = reinterpret_cast<const uint8_t *>(a.in) + ft * kTile;
-            const uint32_t flen = (uint32_t)min((uint64_t)kTile, a.n - ft * kTile);
-            uint64_t c = 0;
-            if (flen == (uint32_t)kTile) {
-                const uint32_t M = 0x01010101u << k;
-                for (int i = lane; i < kTile / 16; i += kWave) {
-                    const uint4 q = reinterpret_cast<const uint4 *>(p)[i];
-                    c += 16u - (uint32_t)(__popc(q.x & M) + __popc(q.y & M) + __popc(q.z & M) + __popc(q.w & M));
-                }
-            } else {
-                for (uint32_t e = (uint32_t)lane; e < flen; e += kWave) c += (((uint32_t)p[e] >> k) & 1u) ^ 1u;
-            }
-            return wave_sum_u64(c);
-        };
-        const uint64_t Z0 = lookback_exclusive<4>(a.tile_state, tile, Zt, lane, a.spin_limit, zeros_of_tile);
+        const uint64_t Z0 = a.tile_prefix[tile];
         if (lane == 0) s_Z0 = (uint32_t)Z0;
         if (DIRS) {
             uint64_t wd[4];
@@ -623,13 +706,24 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     if (!SCATTER) return;
 
     // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).
+    if (len == (uint32_t)kTile) {
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
-        uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            if (e0 + b < len) {
+            for (int b = 0; b < 16; ++b) {
+                const uint32_t bit = (m[r] >> b) & 1u;
+                s_stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
+                zc += bit ^ 1u;
+                oc += bit;
+            }
+        }
+    } else {
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+            for (int b = 0; b < 16 && e0 + b < len; ++b) {
                 const uint32_t bit = (m[r] >> b) & 1u;
                 s_stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
                 zc += bit ^ 1u;
@@ -639,28 +733,53 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     }
     __syncthreads();
 
-    // Scatter (see level_pass for the destination formula).
+    // Scatter (see level_pass for the destination formula), sixteen slots
+    // per lane: inside one run (same node, same bit) the sixteen bytes have
+    // consecutive destinations and leave as one unaligned 16-byte store.
     const uint32_t Z0 = s_Z0, O0 = t0 - Z0;
+    const uint32_t kn = k - 1;  // bit of the next level
+    const uint32_t Mn = 0x01010101u << kn;
+    const uint32_t n16 = a.n > 15 ? (uint32_t)(a.n - 15) : 0u;  // dest < n16 <=> dest + 15 < n
     uint8_t *out = reinterpret_cast<uint8_t *>(a.out);
-    const uint32_t *s_st32 = reinterpret_cast<const uint32_t *>(s_stage);
-#pragma unroll 4
-    for (int i = 0; i < kTile / (4 * kBlock); ++i) {
-        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 4u * j;
-        if (sl >= len) break;
-        const uint32_t v = s_st32[j];
-        const uint32_t q0 = (v & 0xFFu) >> k, q3 = (v >> 24) >> k;
-        if (sl + 3 < len && q0 == q3) {
-            // One run: bit value is the low bit of q, so the region is uniform too.
+    const uint4 *s_st128 = reinterpret_cast<const uint4 *>(s_stage);
+    LaneCount lc;
+#pragma unroll
+    for (int i = 0; i < kTile / (16 * kBlock); ++i) {
+        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
+        if (sl >= len) continue;
+        const uint4 v = s_st128[j];
+        const uint32_t q0 = (v.x & 0xFFu) >> k, q15 = (v.w >> 24) >> k;
+        if (sl + 15 < len && q0 == q15) {
+            // One run: the bit is the low bit of q, so the region is uniform too.
             const uint32_t dest = s_D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
-            if ((uint64_t)dest + 3 < a.n) *reinterpret_cast<u32_unaligned *>(out + dest) = v;
+            if (dest < n16) {
+                *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                const uint32_t nt = dest >> a.next_shift;
+                if (((dest + 15) >> a.next_shift) == nt) {
+                    const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) + __popc(v.z & Mn) +
+                                                     __popc(v.w & Mn));
+                    lc.add(s_ct, a.next_cnt, nt, 16u - ones);
+                } else {
+                    for (uint32_t c = 0; c < 16; ++c)
+                        if (!((byte_of(v, (int)c) >> kn) & 1u))
+                            count_add(s_ct, a.next_cnt, (dest + c) >> a.next_shift, 1u);
+                }
+            }
         } else {
-            for (uint32_t c = 0; c < 4 && sl + c < len; ++c) {
-                const uint32_t bc = (v >> (8 * c)) & 0xFFu, qc = bc >> k, sc = sl + c;
+            // Several runs meet here (or the tile ends): byte by byte.
+            for (uint32_t c = 0; c < 16 && sl + c < len; ++c) {
+                const uint32_t bc = byte_of(v, (int)c), qc = bc >> k, sc = sl + c;
                 const uint32_t dest = s_D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
-                if (dest < a.n) out[dest] = (uint8_t)bc;
+                if (dest < a.n) {
+                    out[dest] = (uint8_t)bc;
+                    if (!((bc >> kn) & 1u)) count_add(s_ct, a.next_cnt, dest >> a.next_shift, 1u);
+                }
             }
         }
     }
+    lc.flush(s_ct, a.next_cnt);
+    __syncthreads();
+    count_flush(s_ct, a.next_cnt, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,7 +847,7 @@ struct Plan {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
-    uint64_t off_status, off_states, off_D, off_part, off_S0, off_S1, total;
+    uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_S0, off_S1, total;
     uint64_t n_part;
 };
 
@@ -760,7 +879,9 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     uint64_t o = 0;
     p.off_status = o;
     o += 256;
-    p.off_states = o;
+    p.off_cnt = o;  // zeros per tile, per level (count-ahead), zeroed each build
+    o = align_up(o + 4ull * p.L * p.T, 256);
+    p.off_pre = o;  // exclusive zero prefix per tile, per level
     o = align_up(o + 8ull * p.L * p.T, 256);
     p.off_D = o;
     o = align_up(o + 8ull * D_len, 256);
@@ -849,14 +970,20 @@ static int num_cus() {
     return cus;
 }
 
+// Positions per tile of a level whose sequence has `width`-byte symbols.
+static uint32_t tile_shift_for(uint32_t width) { return width == 1 ? 14u : (width == 2 ? 13u : 12u); }
+
 template <typename T>
-static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, hipStream_t s) {
+static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
+                        hipStream_t s) {
     uint32_t reps = 0;
     if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / p.sigma));
-    uint64_t vec = p.n / (16 / sizeof(T));
-    uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(vec, kBlock * 4), (uint64_t)num_cus() * 8));
+    const uint32_t shift = tile_shift_for(sizeof(T));
+    const uint64_t ntiles = cdiv(p.n, 1ull << shift);
+    uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)num_cus() * 8));
     size_t shm = reps ? (size_t)reps * p.sigma * 4 : 0;
-    histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, Cp1, status, reps);
+    histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, Cp1, status, reps,
+                                                       p.L ? p.L - 1 : 0u, p.L ? cnt0 : nullptr, shift, ntiles);
 }
 
 }  // namespace wt
@@ -903,20 +1030,21 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     hipStream_t s = (hipStream_t)stream;
     unsigned char *sc = (unsigned char *)d_scratch;
     uint32_t *status = (uint32_t *)(sc + p.off_status);
-    uint64_t *states = (uint64_t *)(sc + p.off_states);
+    uint32_t *cnt = (uint32_t *)(sc + p.off_cnt);
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint64_t *part = (uint64_t *)(sc + p.off_part);
 
-    // Zero: status + look-back states (one contiguous range), and C.
+    // Zero: status + per-tile zero counts (one contiguous range), and C.
     {
-        uint64_t na = p.off_D / 8, nb = sigma + 1;
+        uint64_t na = p.off_pre / 8, nb = sigma + 1;
         uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
         zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
     }
     if (n > 0) {
-        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, s);
-        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, s);
-        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, s);
+        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, s);
+        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, s);
+        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, cnt, s);
         // C: prefix sums of the counts.
         CScanOp cop{out->C + 1};
         uint64_t chunks = cdiv(sigma, kScanChunk);
@@ -954,20 +1082,24 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     for (uint32_t l = 0; l < p.L; ++l) {
         const bool scatter = l + 1 < p.L;
         void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+        // Tile prefixes of this level from the counts its predecessor left.
+        const uint64_t Tl = cdiv(n, 1ull << tile_shift_for(cur_w));
+        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
         LevelArgs a;
         a.in = cur;
         a.out = scatter ? dst : nullptr;
         a.bits = out->bits + (uint64_t)l * p.W;
         a.D = D + ((2ull << l) - 2);
         a.nD = 2ull << l;
-        a.tile_state = states + (uint64_t)l * p.T;
+        a.tile_prefix = pre + (uint64_t)l * p.T;
+        a.next_cnt = scatter ? cnt + (uint64_t)(l + 1) * p.T : nullptr;
+        a.next_shift = tile_shift_for(p.mid_bytes);
         a.status = status;
         a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
         a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
         a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
         a.n = n;
         a.k = p.L - 1 - l;
-        a.spin_limit = g_spin_limit;
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (g_timing && (rc = timing_begin(s, ev))) return rc;
         launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);
