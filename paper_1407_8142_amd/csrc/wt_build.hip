@@ -616,7 +616,6 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     __shared__ uint32_t s_wz[kRows][kWaves];
     __shared__ uint32_t s_zpre[kTile / 64];
     __shared__ uint32_t s_D[SCATTER ? 256 : 1];
-    __shared__ uint32_t s_Z0;
     __shared__ CountTable s_ct;
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
@@ -625,6 +624,7 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     const uint32_t t0 = tile * (uint32_t)kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
+    const uint32_t Z0 = (uint32_t)a.tile_prefix[tile];  // zeros of the level before this tile
     if (SCATTER) {
         for (int i = tid; i < (int)a.nD; i += kBlock) s_D[i] = (uint32_t)a.D[i];
         count_init(s_ct, tid);
@@ -689,18 +689,16 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     const uint64_t *s_w64 = reinterpret_cast<const uint64_t *>(s_m16);
     if ((uint32_t)tid * 64u < len) a.bits[(t0 >> 6) + tid] = s_w64[tid];
 
-    if (wave == 0) {
-        const uint64_t Z0 = a.tile_prefix[tile];
-        if (lane == 0) s_Z0 = (uint32_t)Z0;
-        if (DIRS) {
-            uint64_t wd[4];
-            uint32_t zp[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                wd[j] = s_w64[lane * 4 + j];
-                zp[j] = s_zpre[lane * 4 + j];
-            }
-            emit_directories<4>(wd, zp, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
+    // Directory entries: wave w covers row w, i.e. words 64w .. 64w+63.
+    if (DIRS) {
+        const uint32_t wbase = (uint32_t)wave * kRowBytes;
+        if (wbase < len) {
+            const uint32_t zb = s_zpre[wave * kWave];  // zeros of the tile before this row
+            const uint32_t ze = wave + 1 < kWaves ? s_zpre[(wave + 1) * kWave] : Zt;
+            const uint64_t wd[1] = {s_w64[tid]};
+            const uint32_t zp[1] = {s_zpre[tid] - zb};
+            emit_directories<1>(wd, zp, (uint64_t)Z0 + zb, (uint64_t)t0 + wbase, min(len - wbase, (uint32_t)kRowBytes),
+                                ze - zb, a.n, a.rank, a.sel1, a.sel0, lane);
         }
     }
     if (!SCATTER) return;
@@ -736,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     // Scatter (see level_pass for the destination formula), sixteen slots
     // per lane: inside one run (same node, same bit) the sixteen bytes have
     // consecutive destinations and leave as one unaligned 16-byte store.
-    const uint32_t Z0 = s_Z0, O0 = t0 - Z0;
+    const uint32_t O0 = t0 - Z0;
     const uint32_t kn = k - 1;  // bit of the next level
     const uint32_t Mn = 0x01010101u << kn;
     const uint32_t n16 = a.n > 15 ? (uint32_t)(a.n - 15) : 0u;  // dest < n16 <=> dest + 15 < n
