@@ -68,30 +68,47 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
                                                     uint32_t *cnt0, uint32_t tile_shift, uint64_t ntiles) {
     // Blocks take whole tiles of level 0, so the zeros of the top bit in each
     // tile (the count-ahead input of level 0) come out of the same read.
+    // Small alphabets count in LDS: `reps` replicas with a stride of sigma+1
+    // words (replicas of one symbol fall in different banks), one LDS atomic
+    // per symbol and no branches; a symbol >= sigma is clamped into the pad
+    // word of its replica and raises the status flag.  Large alphabets count
+    // with global atomics, merging runs of equal symbols first.
     extern __shared__ uint32_t s_hist_all[];
     __shared__ uint32_t s_red[kWaves];
     const bool lds = reps > 0;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint64_t stride = sigma + 1;
     if (lds) {
-        for (uint64_t i = tid; i < sigma * reps; i += kBlock) s_hist_all[i] = 0;
+        for (uint64_t i = tid; i < stride * reps; i += kBlock) s_hist_all[i] = 0;
         __syncthreads();
     }
-    uint32_t *s_hist = lds ? s_hist_all + (uint64_t)(tid % reps) * sigma : nullptr;
+    uint32_t *s_hist = lds ? s_hist_all + (uint64_t)(lane % reps) * stride : nullptr;
+    const uint32_t smax = (uint32_t)min(sigma, (uint64_t)0xFFFFFFFFu);
+    const bool need_check = sigma < (1ull << (8 * sizeof(T)));
     constexpr int V = 16 / sizeof(T);
     const uint32_t tile_elems = 1u << tile_shift;
     bool bad = false;
     uint32_t cur = 0xFFFFFFFFu, cnt = 0;
-    auto visit = [&](uint32_t s) -> uint32_t {
+    auto visit_global = [&](uint32_t s) -> uint32_t {
         if ((uint64_t)s >= sigma) {
             bad = true;
             return 0u;
         }
         if (s != cur) {
-            hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
+            hist_flush<T>(nullptr, Cp1, false, cur, cnt);
             cur = s;
             cnt = 0;
         }
         ++cnt;
+        return ((s >> ktop) & 1u) ^ 1u;
+    };
+    auto visit_lds = [&](uint32_t s) -> uint32_t {
+        uint32_t bin = s;
+        if (need_check) {
+            bad |= s >= smax;
+            bin = min(s, smax);
+        }
+        atomicAdd(s_hist + bin, 1u);
         return ((s >> ktop) & 1u) ^ 1u;
     };
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -105,11 +122,17 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
                     T e[V];
                 } u;
                 u.q = *reinterpret_cast<const uint4 *>(S + base + (uint64_t)v * V);
+                if (lds) {
 #pragma unroll
-                for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+                    for (int j = 0; j < V; ++j) zeros += visit_lds((uint32_t)u.e[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) zeros += visit_global((uint32_t)u.e[j]);
+                }
             }
         } else {
-            for (uint32_t e = tid; e < len; e += kBlock) zeros += visit((uint32_t)S[base + e]);
+            for (uint32_t e = tid; e < len; e += kBlock)
+                zeros += lds ? visit_lds((uint32_t)S[base + e]) : visit_global((uint32_t)S[base + e]);
         }
         if (cnt0) {
             uint32_t w = (uint32_t)wave_sum_u64(zeros);
@@ -123,19 +146,20 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
             __syncthreads();
         }
     }
-    hist_flush<T>(s_hist, Cp1, lds, cur, cnt);
-    if (bad) atomicMax(status, kStatusSymbol);
+    if (!lds) hist_flush<T>(nullptr, Cp1, false, cur, cnt);
+    if (__ballot(bad) && lane == 0) atomicMax(status, kStatusSymbol);
     if (lds) {
         __syncthreads();
         for (uint64_t c = tid; c < sigma; c += kBlock) {
             uint32_t sum = 0;
-            for (uint32_t r = 0; r < reps; ++r) sum += s_hist_all[(uint64_t)r * sigma + c];
+            for (uint32_t r = 0; r < reps; ++r) sum += s_hist_all[(uint64_t)r * stride + c];
             if (sum) atomicAdd((unsigned long long *)(Cp1 + c), (unsigned long long)sum);
         }
     }
 }
 
-// Exclusive prefix of per-tile zero counts (one block of 1024 threads).
+// Exclusive prefix of per-tile zero counts (one block of 1024 threads, 16
+// counts per thread; `cnt` and `pre` are 64-entry aligned).
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void tile_prefix_scan(const uint32_t *cnt, uint64_t *pre, uint64_t T) {
     __shared__ uint32_t s_w[kScanThreads / kWave];
@@ -144,11 +168,22 @@ __global__ __launch_bounds__(kScanThreads) void tile_prefix_scan(const uint32_t 
     for (uint64_t c0 = 0; c0 < T; c0 += (uint64_t)kScanThreads * 16) {
         const uint64_t base = c0 + (uint64_t)tid * 16;
         uint32_t v[16], own = 0;
+        if (base + 16 <= T) {
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(cnt + base);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            v[j] = base + j < T ? cnt[base + j] : 0u;
-            own += v[j];
+            for (int q = 0; q < 4; ++q) {
+                const uint4 x = p4[q];
+                v[4 * q] = x.x;
+                v[4 * q + 1] = x.y;
+                v[4 * q + 2] = x.z;
+                v[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = base + j < T ? cnt[base + j] : 0u;
         }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) own += v[j];
         const uint32_t inc = wave_incl_scan_u32(own, lane);
         if (lane == kWave - 1) s_w[wave] = inc;
         __syncthreads();
@@ -160,10 +195,20 @@ __global__ __launch_bounds__(kScanThreads) void tile_prefix_scan(const uint32_t 
             total += x;
         }
         uint64_t run = carry + before + inc - own;
+        uint64_t o[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            if (base + j < T) pre[base + j] = run;
+            o[j] = run;
             run += v[j];
+        }
+        if (base + 16 <= T) {
+            ulonglong2 *q2 = reinterpret_cast<ulonglong2 *>(pre + base);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) q2[q] = make_ulonglong2(o[2 * q], o[2 * q + 1]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (base + j < T) pre[base + j] = o[j];
         }
         carry += total;
         __syncthreads();
@@ -877,6 +922,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     uint64_t o = 0;
     p.off_status = o;
     o += 256;
+    p.T = align_up(p.T, 64);  // per-level stride of the tile arrays (keeps vector loads aligned)
     p.off_cnt = o;  // zeros per tile, per level (count-ahead), zeroed each build
     o = align_up(o + 4ull * p.L * p.T, 256);
     p.off_pre = o;  // exclusive zero prefix per tile, per level
@@ -974,12 +1020,12 @@ static uint32_t tile_shift_for(uint32_t width) { return width == 1 ? 14u : (widt
 template <typename T>
 static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
                         hipStream_t s) {
-    uint32_t reps = 0;
-    if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / p.sigma));
+    uint32_t reps = 0;  // LDS replicas (64 lanes share them), 0 = global atomics
+    if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / (p.sigma + 1)));
     const uint32_t shift = tile_shift_for(sizeof(T));
     const uint64_t ntiles = cdiv(p.n, 1ull << shift);
     uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)num_cus() * 8));
-    size_t shm = reps ? (size_t)reps * p.sigma * 4 : 0;
+    size_t shm = reps ? (size_t)reps * (p.sigma + 1) * 4 : 0;
     histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, Cp1, status, reps,
                                                        p.L ? p.L - 1 : 0u, p.L ? cnt0 : nullptr, shift, ntiles);
 }

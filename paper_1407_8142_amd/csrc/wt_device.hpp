@@ -156,8 +156,11 @@ __device__ __forceinline__ void emit_directories(const uint64_t (&word)[WPL], co
         if (w * 64u < len && (w & 7u) == 0)
             rank[(t0 >> 9) + (w >> 3)] = (t0 + (uint64_t)w * 64u) - (Z0 + zpre[m]);
     }
-    for (uint64_t o = (O0 + S - 1) / S * S; o < O0 + Otile; o += S) {
-        const uint32_t loc = (uint32_t)(o - O0);
+    // Targets are counted by their offset inside the tile, so the loops run
+    // at most Otile/S + 1 (resp. Ztile/S + 1) times whatever O0 and Z0 hold.
+    for (uint64_t loc64 = (S - O0 % S) % S; loc64 < Otile; loc64 += S) {
+        const uint32_t loc = (uint32_t)loc64;
+        const uint64_t o = O0 + loc64;
 #pragma unroll
         for (int m = 0; m < WPL; ++m) {
             const uint32_t w = (uint32_t)lane * WPL + m;
@@ -167,8 +170,9 @@ __device__ __forceinline__ void emit_directories(const uint64_t (&word)[WPL], co
                 sel1[o / S] = t0 + (uint64_t)w * 64u + select_in_word(word[m], loc - opre);
         }
     }
-    for (uint64_t o = (Z0 + S - 1) / S * S; o < Z0 + Ztile; o += S) {
-        const uint32_t loc = (uint32_t)(o - Z0);
+    for (uint64_t loc64 = (S - Z0 % S) % S; loc64 < Ztile; loc64 += S) {
+        const uint32_t loc = (uint32_t)loc64;
+        const uint64_t o = Z0 + loc64;
 #pragma unroll
         for (int m = 0; m < WPL; ++m) {
             const uint32_t w = (uint32_t)lane * WPL + m;
