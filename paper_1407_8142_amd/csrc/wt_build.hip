@@ -429,10 +429,20 @@ __device__ __forceinline__ void count_init(CountTable &t, int tid) {
 }
 
 __device__ __forceinline__ void count_add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
-    const uint32_t slot = ntile & (kCountSlots - 1);
-    const uint32_t old = atomicCAS(&t.key[slot], kNoTile, ntile);
-    if (old == kNoTile || old == ntile) atomicAdd(&t.cnt[slot], c);
-    else atomicAdd(next_cnt + ntile, c);
+    // Hashed slot with a short linear probe: the tiles one block touches are
+    // few but can be far apart by large powers of two (a run of zeros and a
+    // run of ones half a level apart), so the low bits alone would collide.
+    uint32_t slot = (ntile * 0x9E3779B9u) >> 26;
+#pragma unroll 1
+    for (int probe = 0; probe < 8; ++probe) {
+        const uint32_t old = atomicCAS(&t.key[slot], kNoTile, ntile);
+        if (old == kNoTile || old == ntile) {
+            atomicAdd(&t.cnt[slot], c);
+            return;
+        }
+        slot = (slot + 1) & (kCountSlots - 1);
+    }
+    atomicAdd(next_cnt + ntile, c);
 }
 
 __device__ __forceinline__ void count_flush(CountTable &t, uint32_t *next_cnt, int tid) {
