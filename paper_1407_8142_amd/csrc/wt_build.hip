@@ -55,84 +55,102 @@ __global__ void zero_fill(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb) {
 // keeps atomics off the hot symbol of skewed text.  Small alphabets count in
 // LDS (kRep replicas indexed by lane to spread same-address atomics).
 template <typename T>
-__device__ __forceinline__ void hist_flush(uint32_t *s_hist, uint64_t *Cp1, bool lds, uint32_t sym,
-                                           uint32_t cnt) {
-    if (cnt == 0) return;
-    if (lds) atomicAdd(s_hist + sym, cnt);
-    else atomicAdd((unsigned long long *)(Cp1 + sym), (unsigned long long)cnt);
-}
-
-template <typename T>
 __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
                                                     uint64_t *Cp1, uint32_t *status, uint32_t reps, uint32_t ktop,
                                                     uint32_t *cnt0, uint32_t tile_shift, uint64_t ntiles) {
     // Blocks take whole tiles of level 0, so the zeros of the top bit in each
     // tile (the count-ahead input of level 0) come out of the same read.
-    // Small alphabets count in LDS: `reps` replicas with a stride of sigma+1
-    // words (replicas of one symbol fall in different banks), one LDS atomic
-    // per symbol and no branches; a symbol >= sigma is clamped into the pad
-    // word of its replica and raises the status flag.  Large alphabets count
-    // with global atomics, merging runs of equal symbols first.
-    extern __shared__ uint32_t s_hist_all[];
+    // Small alphabets (reps > 0) count in LDS: `reps` replicas with a stride
+    // of sigma+1 words (replicas of one symbol fall in different banks), one
+    // LDS atomic per symbol and no branches; a symbol >= sigma is clamped
+    // into the pad word and raises the status flag.  Large alphabets
+    // aggregate every 2048 symbols in an LDS hash table (so skewed data does
+    // not hammer a few global counters) and flush one global atomic per
+    // distinct symbol.
+    extern __shared__ uint32_t s_dyn[];
     __shared__ uint32_t s_red[kWaves];
+    __shared__ uint32_t s_nused;
+    constexpr uint32_t kH = 4096, kChunk = 2048, kEmpty = 0xFFFFFFFFu;
     const bool lds = reps > 0;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint64_t stride = sigma + 1;
+    uint32_t *keys = s_dyn, *vals = s_dyn + kH, *used = s_dyn + 2 * kH;  // hash path
     if (lds) {
-        for (uint64_t i = tid; i < stride * reps; i += kBlock) s_hist_all[i] = 0;
-        __syncthreads();
+        for (uint64_t i = tid; i < stride * reps; i += kBlock) s_dyn[i] = 0;
+    } else {
+        for (uint32_t i = tid; i < kH; i += kBlock) {
+            keys[i] = kEmpty;
+            vals[i] = 0;
+        }
+        if (tid == 0) s_nused = 0;
     }
-    uint32_t *s_hist = lds ? s_hist_all + (uint64_t)(lane % reps) * stride : nullptr;
+    __syncthreads();
+    uint32_t *s_hist = lds ? s_dyn + (uint64_t)(lane % reps) * stride : nullptr;
     const uint32_t smax = (uint32_t)min(sigma, (uint64_t)0xFFFFFFFFu);
     const bool need_check = sigma < (1ull << (8 * sizeof(T)));
     constexpr int V = 16 / sizeof(T);
     const uint32_t tile_elems = 1u << tile_shift;
     bool bad = false;
-    uint32_t cur = 0xFFFFFFFFu, cnt = 0;
-    auto visit_global = [&](uint32_t s) -> uint32_t {
-        if ((uint64_t)s >= sigma) {
+    auto visit = [&](uint32_t s) -> uint32_t {
+        if (lds) {
+            uint32_t bin = s;
+            if (need_check) {
+                bad |= s >= smax;
+                bin = min(s, smax);
+            }
+            atomicAdd(s_hist + bin, 1u);
+        } else if ((uint64_t)s >= sigma) {
             bad = true;
-            return 0u;
+        } else {
+            uint32_t h = (s * 0x9E3779B1u) >> 20;  // 12 bits
+            bool done = false;
+#pragma unroll 1
+            for (int probe = 0; probe < 8 && !done; ++probe) {
+                const uint32_t old = atomicCAS(keys + h, kEmpty, s);
+                if (old == kEmpty) used[atomicAdd(&s_nused, 1u)] = h;
+                if (old == kEmpty || old == s) {
+                    atomicAdd(vals + h, 1u);
+                    done = true;
+                }
+                h = (h + 1) & (kH - 1);
+            }
+            if (!done) atomicAdd((unsigned long long *)(Cp1 + s), 1ull);
         }
-        if (s != cur) {
-            hist_flush<T>(nullptr, Cp1, false, cur, cnt);
-            cur = s;
-            cnt = 0;
-        }
-        ++cnt;
         return ((s >> ktop) & 1u) ^ 1u;
     };
-    auto visit_lds = [&](uint32_t s) -> uint32_t {
-        uint32_t bin = s;
-        if (need_check) {
-            bad |= s >= smax;
-            bin = min(s, smax);
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t nu = s_nused;
+        for (uint32_t i = tid; i < nu; i += kBlock) {
+            const uint32_t h = used[i];
+            atomicAdd((unsigned long long *)(Cp1 + keys[h]), (unsigned long long)vals[h]);
+            keys[h] = kEmpty;
+            vals[h] = 0;
         }
-        atomicAdd(s_hist + bin, 1u);
-        return ((s >> ktop) & 1u) ^ 1u;
+        __syncthreads();
+        if (tid == 0) s_nused = 0;
+        __syncthreads();
     };
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = tile << tile_shift;
         const uint32_t len = (uint32_t)min((uint64_t)tile_elems, n - base);
         uint32_t zeros = 0;
-        if (len == tile_elems) {
-            for (uint32_t v = tid; v < tile_elems / V; v += kBlock) {
-                union {
-                    uint4 q;
-                    T e[V];
-                } u;
-                u.q = *reinterpret_cast<const uint4 *>(S + base + (uint64_t)v * V);
-                if (lds) {
+        for (uint32_t c0 = 0; c0 < len; c0 += kChunk) {  // hash path: at most kChunk symbols per flush
+            const uint32_t clen = min(kChunk, len - c0);
+            if (clen == kChunk) {
+                for (uint32_t v = tid; v < kChunk / V; v += kBlock) {
+                    union {
+                        uint4 q;
+                        T e[V];
+                    } u;
+                    u.q = *reinterpret_cast<const uint4 *>(S + base + c0 + (uint64_t)v * V);
 #pragma unroll
-                    for (int j = 0; j < V; ++j) zeros += visit_lds((uint32_t)u.e[j]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < V; ++j) zeros += visit_global((uint32_t)u.e[j]);
+                    for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
                 }
+            } else {
+                for (uint32_t e = tid; e < clen; e += kBlock) zeros += visit((uint32_t)S[base + c0 + e]);
             }
-        } else {
-            for (uint32_t e = tid; e < len; e += kBlock)
-                zeros += lds ? visit_lds((uint32_t)S[base + e]) : visit_global((uint32_t)S[base + e]);
+            if (!lds) flush();
         }
         if (cnt0) {
             uint32_t w = (uint32_t)wave_sum_u64(zeros);
@@ -146,13 +164,12 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
             __syncthreads();
         }
     }
-    if (!lds) hist_flush<T>(nullptr, Cp1, false, cur, cnt);
     if (__ballot(bad) && lane == 0) atomicMax(status, kStatusSymbol);
     if (lds) {
         __syncthreads();
         for (uint64_t c = tid; c < sigma; c += kBlock) {
             uint32_t sum = 0;
-            for (uint32_t r = 0; r < reps; ++r) sum += s_hist_all[(uint64_t)r * stride + c];
+            for (uint32_t r = 0; r < reps; ++r) sum += s_dyn[(uint64_t)r * stride + c];
             if (sum) atomicAdd((unsigned long long *)(Cp1 + c), (unsigned long long)sum);
         }
     }
@@ -1035,7 +1052,7 @@ static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t 
     const uint32_t shift = tile_shift_for(sizeof(T));
     const uint64_t ntiles = cdiv(p.n, 1ull << shift);
     uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)num_cus() * 8));
-    size_t shm = reps ? (size_t)reps * (p.sigma + 1) * 4 : 0;
+    size_t shm = reps ? (size_t)reps * (p.sigma + 1) * 4 : (size_t)(2 * 4096 + 2048) * 4;  // replicas, or hash table + used list
     histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, Cp1, status, reps,
                                                        p.L ? p.L - 1 : 0u, p.L ? cnt0 : nullptr, shift, ntiles);
 }
