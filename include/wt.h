@@ -49,7 +49,8 @@ typedef enum {
     WT_ERR_SCRATCH = -3, /* scratch buffer smaller than the plan requires */
     WT_ERR_RANGE = -4,   /* size beyond what the library supports */
     WT_ERR_HIP = -5,     /* a HIP call or kernel launch failed */
-    WT_ERR_NOMEM = -6    /* host-side allocation failed */
+    WT_ERR_NOMEM = -6,   /* host-side allocation failed */
+    WT_ERR_TIMEOUT = -7  /* a batched build gave up waiting for its work items (see wt_tune.spin_limit) */
 } wt_status;
 
 /* Directory format constants (a practical reading of Jacobson's rank and
@@ -140,6 +141,75 @@ int wt_rank(const wt_view *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t
             uint64_t *d_out, void *stream);
 int wt_select(const wt_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
               int64_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched construction: many sequences of uneven length and alphabet, each
+ * built exactly as wt_build builds it (levelWT, Fig. 1), by one kernel that
+ * takes work items from a per-level queue: histogram tiles of every job,
+ * then each job's tables, then level 0 tiles of every job, level 1 tiles,
+ * and so on.  A level's tiles start once that job's previous level is done.
+ * The outputs of every job are identical to wt_build's for the same input.
+ *
+ * Use: wt_batch_plan (host only: sizes), allocate the scratch, then
+ * wt_batch_prepare once (uploads the job and queue tables, synchronous), then
+ * wt_batch_run as often as wanted (kernel launches only, no host work or
+ * allocation: capturable in a HIP graph), then wt_batch_status.  A run
+ * rebuilds every job from the current contents of its input. */
+
+/* One sequence of a batch.  The output buffers are sized as wt_plan gives
+ * for (n, sigma, sym_bytes); directories are required (all four pointers)
+ * when L > 0. */
+typedef struct {
+    const void *seq;     /* device, n symbols of sym_bytes each, 16-byte aligned */
+    uint64_t n;          /* < 2^32 */
+    uint64_t sigma;      /* as for wt_build */
+    uint32_t sym_bytes;  /* 1, 2 or 4 */
+    uint32_t reserved;   /* 0 */
+    wt_outputs out;
+} wt_job;
+
+#define WT_BATCH_PERSISTENT 0u /* one launch of the work kernel for the whole queue */
+#define WT_BATCH_PER_PHASE 1u  /* one launch per phase (histograms, tables, level 0, 1, ...) */
+
+/* Launch tunables of wt_batch_run; a zero field takes the default. */
+typedef struct {
+    uint32_t mode;          /* WT_BATCH_PERSISTENT (default) or WT_BATCH_PER_PHASE */
+    uint32_t blocks_per_cu; /* resident work-kernel blocks per CU (default: as many as fit) */
+    uint32_t chunk;         /* consecutive work items taken per queue access (default 1, at most 4096) */
+    uint32_t spin_limit;    /* polls before a waiting block gives up (default 2^22, roughly seconds);
+                               a give-up marks the job WT_ERR_TIMEOUT and leaves its outputs unspecified */
+} wt_tune;
+
+/* Sizes and queue shape of a batch: a pure function of the jobs' (n, sigma,
+ * sym_bytes), in the given order. */
+typedef struct {
+    uint64_t scratch_bytes;   /* device scratch of wt_batch_prepare / wt_batch_run (256-byte aligned) */
+    uint64_t clear_bytes;     /* leading scratch bytes every run clears */
+    uint64_t off_jobs, off_segs, off_seg_of; /* offsets of the tables wt_batch_prepare writes */
+    uint32_t njobs;
+    uint32_t nsegs;           /* queue segments: (job, phase) pairs with work */
+    uint32_t items;           /* work items in the queue */
+    uint32_t phases;          /* 2 + the most levels of any job with n > 0 */
+    uint32_t phase_first[33]; /* first item of each phase; phase_first[phases] = items */
+} wt_batch_layout;
+
+/* Host only.  WT_ERR_ARG / WT_ERR_RANGE as wt_plan (and n >= 2^32). */
+int wt_batch_plan(const wt_job *jobs, uint32_t njobs, wt_batch_layout *out);
+
+/* Writes the job and queue tables into d_scratch (>= scratch_bytes, 256-byte
+ * aligned) and waits for the copies.  `lay` must come from wt_batch_plan on
+ * the same jobs.  The jobs' input and output pointers are recorded: they
+ * must stay valid for every later wt_batch_run. */
+int wt_batch_prepare(const wt_job *jobs, uint32_t njobs, const wt_batch_layout *lay, void *d_scratch,
+                     uint64_t scratch_bytes, void *stream);
+
+/* Builds every job (asynchronous on `stream`; tune may be NULL). */
+int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, void *d_scratch, void *stream);
+
+/* Waits for `stream`; writes each job's code (WT_OK, WT_ERR_SYMBOL,
+ * WT_ERR_TIMEOUT) to codes[0..njobs) when codes is not NULL and returns
+ * WT_ERR_TIMEOUT if any job timed out, else the first error, else WT_OK. */
+int wt_batch_status(const wt_batch_layout *lay, const void *d_scratch, int32_t *codes, void *stream);
 
 /* Look-back tuning and testing hook.  Tiles of a level pass find their
  * prefix by looking back at earlier tiles; a tile whose predecessor has not

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwt.so")
 PROBE = os.path.join(HERE, "bw_probe")
-SOURCES = ["wt_build.hip", "wt_query.hip"]
+SOURCES = ["wt_build.hip", "wt_batch.hip", "wt_query.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,551 @@
+// Batched construction: many sequences of uneven length and alphabet built
+// by one kernel that takes work items from a queue (levelWT, Fig. 1 of
+// "Parallel Wavelet Tree Construction", applied to every sequence).
+//
+// Work items, in queue order (level-major, so that the items one item waits
+// for were all taken from the queue long before it):
+//   histogram tile (job, t)   counts of one tile of S into the job's symbol
+//                             counts, the symbol check, the zeros of the top
+//                             bit in the tile
+//   tables (job)              after the job's last histogram tile: C, the
+//                             node tables D_l, the directory tails and the
+//                             tile prefixes of level 0
+//   level tile (job, l, t)    after the job's level l-1 (or its tables): one
+//                             tile of the level pass (bits, directories,
+//                             stable split and scatter, count-ahead of l+1)
+// The block that finishes the last tile of a level scans the count-ahead
+// totals into the next level's tile prefixes and marks that level ready.
+//
+// Progress: a block only waits on items that precede its own in the queue,
+// and items are handed out in queue order to blocks that are running, so
+// every wait ends whatever the residency (induction on queue position).  A
+// wait is still bounded: after `spin_limit` polls it raises the batch's
+// abort flag and the job's timeout status and goes on (outputs are then
+// unspecified); later waits return at once once the flag is up.
+//
+// The same kernel also runs one phase per launch (histograms, tables, level
+// 0, level 1, ...): kernel boundaries then order the phases and the waits
+// return at once.  Either form is a fixed sequence of kernel launches with
+// no host work in between, so it can be captured in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/wt.h"
+#include "wt_device.hpp"
+#include "wt_kernels.hpp"
+
+namespace wt {
+namespace batch {
+
+constexpr uint32_t kStatusTimeout = 4u;
+constexpr uint32_t kHistH = 2048;                         // hash slots of the batched histogram
+constexpr uint32_t kHistWords = HistHash<kHistH>::kWords;  // LDS words of its table (replicas or hash)
+constexpr uint32_t kKindHist = 0, kKindPrep = 1, kKindLevel = 2;  // level l is kind 2 + l
+
+// Control words of one job (cleared by every run): status, done counters
+// (histogram, then one per level), ready flags (one per level).
+constexpr int kCtlWords = 64;
+constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32;
+constexpr int kMaxLevels = 30;
+constexpr uint64_t kHeaderBytes = 256;  // queue heads [0, 32), abort flag [32]
+constexpr int kAbortWord = 32;
+
+struct JobDev {
+    const void *seq;
+    uint64_t n, sigma;
+    uint32_t L, in_bytes, mid_bytes, reps;
+    uint32_t T0, Tm, Tpad, pad0;
+    uint64_t W, rank_len, cap;
+    uint64_t *bits, *C, *rank, *sel1, *sel0, *sel_counts;
+    uint32_t *ctl, *symcnt, *cnt;
+    uint64_t *pre, *D;
+    void *S0, *S1;
+};
+
+struct Seg {
+    uint32_t job, kind, first, count;
+};
+
+struct Args {
+    const JobDev *jobs;
+    const Seg *segs;
+    const uint32_t *seg_of;  // segment of every item
+    uint32_t *head;          // queue head of this launch
+    uint32_t *abort;
+    uint32_t lo, hi;         // item range of this launch
+    uint32_t chunk;          // items taken per queue access
+    uint32_t spin_limit;
+};
+
+struct LdsHistB {
+    uint32_t tab[kHistWords];
+    uint32_t red[kWaves];
+    uint32_t nused;
+};
+
+union LdsBatch {
+    LdsLevelU8 u8;
+    LdsLevel<uint16_t> g16;
+    LdsLevel<uint32_t> g32;
+    LdsHistB hist;
+    BlockScanTmp scan;
+};
+
+// A job or segment record: constant while the kernel runs and uniform
+// across the block, so it is read through the constant address space
+// (scalar loads into SGPRs, which the compiler may reload instead of
+// keeping vector registers busy).
+template <typename T>
+__device__ __forceinline__ T load_const(const T *p) {
+#if __HIP_DEVICE_COMPILE__
+    typedef const __attribute__((address_space(4))) T *const_ptr;
+    return *(const_ptr)(uintptr_t)p;
+#else
+    return *p;
+#endif
+}
+
+__device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Cross-block hand-off.  A barrier orders nothing in memory beyond the
+// workgroup (it does not even wait for the other waves' stores to leave),
+// so every wave releases its own writes at agent scope before the barrier
+// that precedes the signalling atomic, and every wave acquires after the
+// barrier that follows a successful wait.
+__device__ __forceinline__ void block_release() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+}
+
+__device__ __forceinline__ void block_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// The block waits until *p >= target (thread 0 polls), then acquires.
+__device__ __forceinline__ void wait_for(const Args &b, const uint32_t *p, uint32_t target, uint32_t *status) {
+    if (threadIdx.x == 0) {
+        uint32_t spins = 0;
+        while (ld_u32(p) < target) {
+            if (ld_u32(b.abort)) break;
+            if (++spins >= b.spin_limit) {
+                atomicOr(b.abort, 1u);
+                atomicOr(status, kStatusTimeout);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    block_acquire();
+}
+
+// Counts one finished item of a segment (after releasing the block's
+// writes); true in every thread of the block that finished the last one,
+// which has then acquired the other items' writes.
+__device__ __forceinline__ bool finish_item(uint32_t *done, uint32_t count, uint32_t *s_flag) {
+    block_release();
+    if (threadIdx.x == 0) *s_flag = atomicAdd(done, 1u) == count - 1 ? 1u : 0u;
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    if (last) block_acquire();
+    return last;
+}
+
+__device__ __forceinline__ void publish(uint32_t *flag) {
+    block_release();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void hist_item(const JobDev &j, uint32_t tile, LdsHistB &s) {
+    const uint32_t shift = tile_shift_for(sizeof(T));
+    const uint64_t base = (uint64_t)tile << shift;
+    const uint32_t len = (uint32_t)min(1ull << shift, j.n - base);
+    hist_init<kHistH>(s.tab, &s.nused, j.reps, j.sigma);
+    bool bad = false;
+    const uint32_t zeros = hist_count<T, kHistH>(reinterpret_cast<const T *>(j.seq), base, len, j.sigma, j.reps,
+                                                 j.L ? j.L - 1 : 0u, s.tab, &s.nused, j.symcnt, bad);
+    if (j.reps) hist_flush_replicas(s.tab, j.reps, j.sigma, j.symcnt);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(j.ctl + kCtlStatus, kStatusSymbol);
+    if (j.L) {
+        const uint32_t t = block_sum_u32(zeros, s.red);
+        if (threadIdx.x == 0) j.cnt[tile] = t;
+    }
+}
+
+// C, node tables, directory tails and level-0 tile prefixes of one job.
+__device__ __forceinline__ void prep_item(const JobDev &j, BlockScanTmp &tmp) {
+    const uint64_t total = block_scan_all<4>(
+        j.sigma, tmp, [&](uint64_t g) -> uint64_t { return j.symcnt[g]; },
+        [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
+    if (threadIdx.x == 0) j.C[j.sigma] = total;
+    __threadfence();
+    __syncthreads();
+    if (j.L == 0) return;
+    const TableOp top{j.C, j.D, j.sigma, j.L};
+    for (uint32_t l = 0; l < j.L; ++l) {
+        const uint64_t g0 = 1ull << l;
+        block_scan_all<4>(
+            g0, tmp, [&](uint64_t i) -> uint64_t { return top.value(g0 + i); },
+            [&](uint64_t i, uint64_t ex) { top.store(g0 + i, ex); });
+    }
+    __threadfence();
+    __syncthreads();
+    for (uint32_t l = 0; l < j.L; ++l)
+        dir_tail(l, j.D[(1ull << (l + 2)) - 3], j.n, j.L, j.rank, j.rank_len, j.sel1, j.sel0, j.cap, j.sel_counts,
+                 threadIdx.x, kBlock);
+    tile_prefix_block(j.cnt, j.pre, j.T0, tmp);
+}
+
+__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LdsBatch &s) {
+    const bool scatter = l + 1 < j.L;
+    const uint32_t win = l == 0 ? j.in_bytes : j.mid_bytes, wout = j.mid_bytes;
+    LevelArgs a;
+    a.in = l == 0 ? j.seq : ((l - 1) % 2 == 0 ? j.S0 : j.S1);
+    a.out = scatter ? (l % 2 == 0 ? j.S0 : j.S1) : nullptr;
+    a.bits = j.bits + (uint64_t)l * j.W;
+    a.D = j.D + ((2ull << l) - 2);
+    a.nD = 2ull << l;
+    a.tile_prefix = j.pre + (uint64_t)l * j.Tpad;
+    a.next_cnt = scatter ? j.cnt + (uint64_t)(l + 1) * j.Tpad : nullptr;
+    a.next_shift = tile_shift_for(j.mid_bytes);
+    a.status = j.ctl + kCtlStatus;
+    a.rank = j.rank + (uint64_t)l * j.rank_len;
+    a.sel1 = j.sel1 + (uint64_t)l * j.cap;
+    a.sel0 = j.sel0 + (uint64_t)l * j.cap;
+    a.n = j.n;
+    a.k = j.L - 1 - l;
+    if (scatter) {
+        if (win == 1) level_tile_u8<true, true>(a, tile, s.u8);
+        else if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
+        else if (win == 2) level_tile<uint16_t, uint16_t, true, true>(a, tile, s.g16);
+        else if (wout == 1) level_tile<uint32_t, uint8_t, true, true>(a, tile, s.g32);
+        else if (wout == 2) level_tile<uint32_t, uint16_t, true, true>(a, tile, s.g32);
+        else level_tile<uint32_t, uint32_t, true, true>(a, tile, s.g32);
+    } else {
+        if (win == 1) level_tile_u8<false, true>(a, tile, s.u8);
+        else if (win == 2) level_tile<uint16_t, uint16_t, false, true>(a, tile, s.g16);
+        else level_tile<uint32_t, uint32_t, false, true>(a, tile, s.g32);
+    }
+}
+
+__device__ __forceinline__ void run_item(const Args &b, uint32_t it, LdsBatch &s, uint32_t *s_flag) {
+    const uint32_t si = __builtin_amdgcn_readfirstlane(b.seg_of[it]);
+    const Seg sg = load_const(b.segs + si);
+    const uint32_t jid = __builtin_amdgcn_readfirstlane(sg.job), kind = __builtin_amdgcn_readfirstlane(sg.kind);
+    const uint32_t count = __builtin_amdgcn_readfirstlane(sg.count);
+    const uint32_t tile = it - __builtin_amdgcn_readfirstlane(sg.first);
+    const JobDev j = load_const(b.jobs + jid);
+    uint32_t *ctl = j.ctl;
+    if (kind == kKindHist) {
+        if (j.in_bytes == 1) hist_item<uint8_t>(j, tile, s.hist);
+        else if (j.in_bytes == 2) hist_item<uint16_t>(j, tile, s.hist);
+        else hist_item<uint32_t>(j, tile, s.hist);
+        finish_item(ctl + kCtlDone, count, s_flag);
+    } else if (kind == kKindPrep) {
+        wait_for(b, ctl + kCtlDone, j.T0, ctl + kCtlStatus);
+        prep_item(j, s.scan);
+        publish(ctl + kCtlReady);
+    } else {
+        const uint32_t l = kind - kKindLevel;
+        wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
+        level_item(j, l, tile, s);
+        if (finish_item(ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
+            tile_prefix_block(j.cnt + (uint64_t)(l + 1) * j.Tpad, j.pre + (uint64_t)(l + 1) * j.Tpad, j.Tm, s.scan);
+            publish(ctl + kCtlReady + 1 + l);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void work_kernel(Args b) {
+    __shared__ LdsBatch s;
+    __shared__ uint32_t s_first, s_flag;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint64_t f = (uint64_t)b.lo + atomicAdd(b.head, b.chunk);
+            s_first = (uint32_t)min(f, (uint64_t)b.hi);
+        }
+        __syncthreads();
+        const uint32_t first = s_first;
+        if (first >= b.hi) break;
+        const uint32_t last = min(first + b.chunk, b.hi);
+        for (uint32_t it = first; it < last; ++it) {
+            __syncthreads();  // the previous item's LDS is free
+            run_item(b, it, s, &s_flag);
+        }
+    }
+}
+
+__global__ void clear_kernel(uint64_t *a, uint64_t na) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) a[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+struct HostJob {
+    uint64_t n, sigma;
+    uint32_t L, in_bytes, mid_bytes, reps, T0, Tm, Tpad;
+    uint64_t off_ctl, off_symcnt, off_cnt, off_pre, off_D, off_S0, off_S1;
+};
+
+struct HostPlan {
+    std::vector<HostJob> jobs;
+    std::vector<Seg> segs;
+    std::vector<uint32_t> phase_first;
+    uint64_t items = 0, off_jobs = 0, off_segs = 0, off_seg_of = 0, clear_bytes = 0, total = 0;
+};
+
+static uint32_t levels_of(uint64_t sigma) {
+    uint32_t L = 0;
+    while (L < 64 && (1ull << L) < sigma) ++L;
+    return L;
+}
+
+static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
+    if (njobs > 0 && !jobs) return WT_ERR_ARG;
+    hp.jobs.resize(njobs);
+    uint32_t maxL = 0;
+    for (uint32_t i = 0; i < njobs; ++i) {
+        const wt_job &q = jobs[i];
+        HostJob &h = hp.jobs[i];
+        if (q.sigma == 0 || (q.sym_bytes != 1 && q.sym_bytes != 2 && q.sym_bytes != 4)) return WT_ERR_ARG;
+        if (q.sigma > (1ull << (8 * q.sym_bytes))) return WT_ERR_ARG;
+        if (q.n >= (1ull << 32)) return WT_ERR_RANGE;
+        h.n = q.n;
+        h.sigma = q.sigma;
+        h.L = levels_of(q.sigma);
+        if (h.L > (uint32_t)kMaxLevels) return WT_ERR_RANGE;
+        h.in_bytes = q.sym_bytes;
+        h.mid_bytes = h.L <= 8 ? 1u : (h.L <= 16 ? 2u : 4u);
+        h.reps = q.sigma + 1 <= kHistWords ? (uint32_t)std::min<uint64_t>(16, kHistWords / (q.sigma + 1)) : 0u;
+        h.T0 = (uint32_t)cdiv(q.n, 1ull << tile_shift_for(h.in_bytes));
+        h.Tm = (uint32_t)cdiv(q.n, 1ull << tile_shift_for(h.mid_bytes));
+        h.Tpad = (uint32_t)align_up(std::max<uint32_t>(std::max(h.T0, h.Tm), 1), 4);
+        maxL = std::max(maxL, h.n ? h.L : 0u);
+    }
+    // Clear region: header, control words of every job, then every job's
+    // symbol counts and count-ahead totals.
+    uint64_t o = kHeaderBytes;
+    for (auto &h : hp.jobs) {
+        h.off_ctl = o;
+        o += kCtlWords * 4;
+    }
+    for (auto &h : hp.jobs) {
+        h.off_symcnt = o;
+        o = align_up(o + 4 * h.sigma, 256);
+        h.off_cnt = o;
+        o = align_up(o + 4ull * h.L * h.Tpad, 256);
+    }
+    hp.clear_bytes = o;
+    // Segments in queue order.
+    hp.segs.clear();
+    hp.phase_first.clear();
+    uint64_t items = 0;
+    auto add = [&](uint32_t job, uint32_t kind, uint32_t count) {
+        if (count == 0) return;
+        hp.segs.push_back(Seg{job, kind, (uint32_t)items, count});
+        items += count;
+    };
+    hp.phase_first.push_back(0);
+    for (uint32_t i = 0; i < njobs; ++i) add(i, kKindHist, hp.jobs[i].T0);
+    hp.phase_first.push_back((uint32_t)items);
+    for (uint32_t i = 0; i < njobs; ++i) add(i, kKindPrep, 1);
+    for (uint32_t l = 0; l < maxL; ++l) {
+        hp.phase_first.push_back((uint32_t)items);
+        for (uint32_t i = 0; i < njobs; ++i) {
+            const HostJob &h = hp.jobs[i];
+            if (h.n > 0 && l < h.L) add(i, kKindLevel + l, l == 0 ? h.T0 : h.Tm);
+        }
+        if (items >= (1ull << 31)) return WT_ERR_RANGE;
+    }
+    hp.phase_first.push_back((uint32_t)items);
+    hp.items = items;
+    o = align_up(o, 256);
+    hp.off_jobs = o;
+    o = align_up(o + sizeof(JobDev) * njobs, 256);
+    hp.off_segs = o;
+    o = align_up(o + sizeof(Seg) * hp.segs.size(), 256);
+    hp.off_seg_of = o;
+    o = align_up(o + 4 * items, 256);
+    for (auto &h : hp.jobs) {
+        h.off_pre = o;
+        o = align_up(o + 8ull * h.L * h.Tpad, 256);
+        h.off_D = o;
+        o = align_up(o + (h.L ? 8ull * ((2ull << h.L) - 2) : 0), 256);
+        const uint64_t sbytes = h.L >= 2 ? align_up(h.n * h.mid_bytes, 256) : 0;
+        h.off_S0 = o;
+        o += sbytes;
+        h.off_S1 = o;
+        o += h.L >= 3 ? sbytes : 0;
+    }
+    hp.total = std::max<uint64_t>(o, 256);
+    return WT_OK;
+}
+
+// Resident blocks of work_kernel: per CU and CUs of the current device.
+static int residency(uint32_t &per_cu, uint32_t &cus) {
+    static int s_per_cu = 0, s_cus = 0;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!s_per_cu) {
+        int dev = 0, c = 0, b = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            return WT_ERR_HIP;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, work_kernel, kBlock, 0) != hipSuccess || b <= 0) b = 1;
+        s_cus = c;
+        s_per_cu = b;
+    }
+    per_cu = (uint32_t)s_per_cu;
+    cus = (uint32_t)s_cus;
+    return WT_OK;
+}
+
+}  // namespace batch
+}  // namespace wt
+
+using namespace wt;
+using namespace wt::batch;
+
+extern "C" int wt_batch_plan(const wt_job *jobs, uint32_t njobs, wt_batch_layout *out) {
+    if (!out) return WT_ERR_ARG;
+    HostPlan hp;
+    int rc = make_batch_plan(jobs, njobs, hp);
+    if (rc) return rc;
+    *out = wt_batch_layout{};
+    out->scratch_bytes = hp.total;
+    out->clear_bytes = hp.clear_bytes;
+    out->njobs = njobs;
+    out->nsegs = (uint32_t)hp.segs.size();
+    out->items = (uint32_t)hp.items;
+    out->phases = (uint32_t)hp.phase_first.size() - 1;
+    for (size_t i = 0; i < hp.phase_first.size(); ++i) out->phase_first[i] = hp.phase_first[i];
+    out->off_jobs = hp.off_jobs;
+    out->off_segs = hp.off_segs;
+    out->off_seg_of = hp.off_seg_of;
+    return WT_OK;
+}
+
+extern "C" int wt_batch_prepare(const wt_job *jobs, uint32_t njobs, const wt_batch_layout *lay, void *d_scratch,
+                                uint64_t scratch_bytes, void *stream) {
+    if (!lay || !d_scratch || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    HostPlan hp;
+    int rc = make_batch_plan(jobs, njobs, hp);
+    if (rc) return rc;
+    if (lay->njobs != njobs || lay->items != hp.items || lay->scratch_bytes != hp.total) return WT_ERR_ARG;
+    if (scratch_bytes < hp.total) return WT_ERR_SCRATCH;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    std::vector<JobDev> dev(njobs);
+    for (uint32_t i = 0; i < njobs; ++i) {
+        const wt_job &q = jobs[i];
+        const HostJob &h = hp.jobs[i];
+        const wt_outputs &o = q.out;
+        if (!o.C) return WT_ERR_ARG;
+        if (h.L > 0 && (!o.rank || !o.sel1 || !o.sel0 || !o.sel_counts)) return WT_ERR_ARG;  // directories required
+        if (h.n > 0 && (!q.seq || ((uintptr_t)q.seq & 15u))) return WT_ERR_ARG;
+        if (h.n > 0 && h.L > 0 && !o.bits) return WT_ERR_ARG;
+        JobDev &d = dev[i];
+        d = JobDev{};
+        d.seq = q.seq;
+        d.n = h.n;
+        d.sigma = h.sigma;
+        d.L = h.L;
+        d.in_bytes = h.in_bytes;
+        d.mid_bytes = h.mid_bytes;
+        d.reps = h.reps;
+        d.T0 = h.T0;
+        d.Tm = h.Tm;
+        d.Tpad = h.Tpad;
+        d.W = cdiv(h.n, 64);
+        d.rank_len = cdiv(h.n, WT_RANK_BLOCK_BITS) + 1;
+        d.cap = cdiv(h.n, WT_SELECT_SAMPLE) + 1;
+        d.bits = o.bits;
+        d.C = o.C;
+        d.rank = o.rank;
+        d.sel1 = o.sel1;
+        d.sel0 = o.sel0;
+        d.sel_counts = o.sel_counts;
+        d.ctl = (uint32_t *)(sc + h.off_ctl);
+        d.symcnt = (uint32_t *)(sc + h.off_symcnt);
+        d.cnt = (uint32_t *)(sc + h.off_cnt);
+        d.pre = (uint64_t *)(sc + h.off_pre);
+        d.D = (uint64_t *)(sc + h.off_D);
+        d.S0 = sc + h.off_S0;
+        d.S1 = sc + h.off_S1;
+    }
+    std::vector<uint32_t> seg_of(hp.items);
+    for (uint32_t s = 0; s < hp.segs.size(); ++s)
+        for (uint32_t t = 0; t < hp.segs[s].count; ++t) seg_of[hp.segs[s].first + t] = s;
+    hipStream_t st = (hipStream_t)stream;
+    if (njobs && hipMemcpyAsync(sc + hp.off_jobs, dev.data(), sizeof(JobDev) * njobs, hipMemcpyHostToDevice, st))
+        return WT_ERR_HIP;
+    if (!hp.segs.empty() &&
+        hipMemcpyAsync(sc + hp.off_segs, hp.segs.data(), sizeof(Seg) * hp.segs.size(), hipMemcpyHostToDevice, st))
+        return WT_ERR_HIP;
+    if (hp.items && hipMemcpyAsync(sc + hp.off_seg_of, seg_of.data(), 4 * hp.items, hipMemcpyHostToDevice, st))
+        return WT_ERR_HIP;
+    // The host tables are released on return: wait for the copies.
+    return hipStreamSynchronize(st) == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, void *d_scratch, void *stream) {
+    if (!lay || !d_scratch || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    wt_tune t = tune ? *tune : wt_tune{};
+    if (t.mode > WT_BATCH_PER_PHASE) return WT_ERR_ARG;
+    const uint32_t chunk = t.chunk ? t.chunk : 1u;
+    const uint32_t spin = t.spin_limit ? t.spin_limit : (1u << 22);
+    if (chunk > 4096) return WT_ERR_ARG;
+    uint32_t max_per_cu = 0, cus = 0;
+    if (residency(max_per_cu, cus) != WT_OK) return WT_ERR_HIP;
+    const uint32_t per_cu = t.blocks_per_cu ? std::min(t.blocks_per_cu, max_per_cu) : max_per_cu;
+    const uint64_t resident = (uint64_t)per_cu * cus;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    const uint64_t nclear = lay->clear_bytes / 8;
+    clear_kernel<<<(unsigned)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(nclear, kBlock), 8192)), kBlock, 0, s>>>(
+        (uint64_t *)sc, nclear);
+    Args a;
+    a.jobs = (const JobDev *)(sc + lay->off_jobs);
+    a.segs = (const Seg *)(sc + lay->off_segs);
+    a.seg_of = (const uint32_t *)(sc + lay->off_seg_of);
+    a.abort = (uint32_t *)sc + kAbortWord;
+    a.chunk = chunk;
+    a.spin_limit = spin;
+    auto launch = [&](uint32_t phase, uint32_t lo, uint32_t hi) {
+        if (hi <= lo) return;
+        a.head = (uint32_t *)sc + phase;
+        a.lo = lo;
+        a.hi = hi;
+        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(resident, cdiv(hi - lo, chunk)));
+        work_kernel<<<(unsigned)grid, kBlock, 0, s>>>(a);
+    };
+    if (t.mode == WT_BATCH_PERSISTENT) {
+        launch(0, 0, lay->items);
+    } else {
+        for (uint32_t p = 0; p < lay->phases; ++p) launch(p, lay->phase_first[p], lay->phase_first[p + 1]);
+    }
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_batch_status(const wt_batch_layout *lay, const void *d_scratch, int32_t *codes, void *stream) {
+    if (!lay || !d_scratch) return WT_ERR_ARG;
+    std::vector<uint32_t> ctl((size_t)lay->njobs * kCtlWords);
+    hipStream_t s = (hipStream_t)stream;
+    if (lay->njobs && hipMemcpyAsync(ctl.data(), (const unsigned char *)d_scratch + kHeaderBytes, ctl.size() * 4,
+                                     hipMemcpyDeviceToHost, s) != hipSuccess)
+        return WT_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return WT_ERR_HIP;
+    int worst = WT_OK;
+    for (uint32_t i = 0; i < lay->njobs; ++i) {
+        const uint32_t st = ctl[(size_t)i * kCtlWords + kCtlStatus];
+        const int code = (st & kStatusTimeout) ? WT_ERR_TIMEOUT : (st & kStatusSymbol) ? WT_ERR_SYMBOL : WT_OK;
+        if (codes) codes[i] = code;
+        if (code == WT_ERR_TIMEOUT || worst == WT_OK) worst = code == WT_OK ? worst : code;
+    }
+    return worst;
+}

@@ -25,6 +25,17 @@ __device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// Valid elements of a group of k that starts at `start` in a range of `len`:
+// min(k, len - start), and 0 when start >= len.  Computed in signed
+// arithmetic (len, start < 2^31): the form `start >= len ? 0 : min(k, len -
+// start)` has been compiled with the unsigned subtraction hoisted out of
+// its guard and then used as if it could not wrap, which made every guard
+// built on the count pass for groups past the end.
+__device__ __forceinline__ uint32_t clamp_count(uint32_t len, uint32_t start, uint32_t k) {
+    const int32_t rem = (int32_t)len - (int32_t)start;
+    return (uint32_t)min(max(rem, 0), (int32_t)k);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
 // Inclusive prefix sum across the 64 lanes of a wave.
@@ -177,7 +188,7 @@ __device__ __forceinline__ void emit_directories(const uint64_t (&word)[WPL], co
         for (int m = 0; m < WPL; ++m) {
             const uint32_t w = (uint32_t)lane * WPL + m;
             const bool has = w * 64u < len;
-            const uint32_t nb = has ? min(64u, len - w * 64u) : 0u;
+            const uint32_t nb = clamp_count(len, w * 64u, 64u);
             const uint64_t vmask = nb >= 64u ? ~0ull : ((1ull << nb) - 1ull);
             const uint64_t zword = ~word[m] & vmask;
             const uint32_t zw = (uint32_t)__popcll(zword);

@@ -1,0 +1,751 @@
+// Per-tile steps of levelWT (Fig. 1 of "Parallel Wavelet Tree Construction")
+// on gfx950, shared by the single-sequence build (one kernel launch per step)
+// and the batched build (one persistent kernel that runs the same steps as
+// work items).  Every step here is a __device__ function run by one block of
+// kBlock threads on one tile; its LDS is a struct the caller provides, so a
+// kernel that runs several kinds of steps can overlay them in one union.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/wt.h"
+#include "wt_device.hpp"
+
+namespace wt {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kWaves = kBlock / kWave;
+constexpr int kScanChunk = kBlock * kItems;  // elements per block in the generic scans
+
+constexpr uint32_t kStatusSymbol = 2u;
+
+__host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline uint64_t align_up(uint64_t a, uint64_t b) { return cdiv(a, b) * b; }
+
+// Positions per tile of a level whose sequence has `width`-byte symbols:
+// a tile is 16 KiB whatever the width.
+__host__ __device__ inline uint32_t tile_shift_for(uint32_t width) {
+    return width == 1 ? 14u : (width == 2 ? 13u : 12u);
+}
+
+// Sum of one value per thread over the block (result valid in every thread).
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red) {
+    const int lane = lane_id(), wave = (int)threadIdx.x / kWave;
+    const uint32_t w = (uint32_t)wave_sum_u64(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[i];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Histogram of one tile: the counts behind C (C[c] = #{S[i] < c}), the
+// symbol check, and the zeros of the top bit in the tile (the count-ahead
+// input of level 0).  Each thread reads 16 bytes at a time.
+//   Small alphabets (reps > 0) count in LDS: `reps` replicas with a stride
+//   of sigma+1 words (replicas of one symbol fall in different banks, the
+//   lane picks its replica), one LDS atomic per symbol and no branches; a
+//   symbol >= sigma is clamped into the pad word and raises the flag.
+//   Large alphabets aggregate every kH/2 symbols in an LDS hash table of kH
+//   slots (so skewed data does not hammer a few global counters) and flush
+//   one global atomic per distinct symbol.
+// LDS: `tab` holds reps*(sigma+1) words, or keys[kH] | vals[kH] | used[kH/2].
+template <uint32_t kH>
+struct HistHash {
+    static constexpr uint32_t kChunk = kH / 2, kEmpty = 0xFFFFFFFFu;
+    static constexpr uint32_t kWords = 2 * kH + kChunk;
+};
+
+template <uint32_t kH>
+__device__ __forceinline__ void hist_init(uint32_t *tab, uint32_t *nused, uint32_t reps, uint64_t sigma) {
+    const int tid = threadIdx.x;
+    if (reps) {
+        for (uint64_t i = tid; i < (sigma + 1) * reps; i += kBlock) tab[i] = 0;
+    } else {
+        for (uint32_t i = tid; i < kH; i += kBlock) {
+            tab[i] = HistHash<kH>::kEmpty;
+            tab[kH + i] = 0;
+        }
+        if (tid == 0) *nused = 0;
+    }
+    __syncthreads();
+}
+
+// Counts S[base, base+len) into the LDS table (hash path: flushed to
+// `counts` every kH/2 symbols).  Returns this thread's zeros of bit ktop.
+template <typename T, uint32_t kH, typename CNT>
+__device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t base, uint32_t len, uint64_t sigma,
+                                               uint32_t reps, uint32_t ktop, uint32_t *tab, uint32_t *nused,
+                                               CNT *counts, bool &bad) {
+    using H = HistHash<kH>;
+    const int tid = threadIdx.x, lane = lane_id();
+    const bool lds = reps > 0;
+    uint32_t *keys = tab, *vals = tab + kH, *used = tab + 2 * kH;
+    uint32_t *s_hist = lds ? tab + (uint64_t)(lane % reps) * (sigma + 1) : nullptr;
+    const uint32_t smax = (uint32_t)min(sigma, (uint64_t)0xFFFFFFFFu);
+    const bool need_check = sigma < (1ull << (8 * sizeof(T)));
+    constexpr int V = 16 / sizeof(T);
+    auto visit = [&](uint32_t s) -> uint32_t {
+        if (lds) {
+            uint32_t bin = s;
+            if (need_check) {
+                bad |= s >= smax;
+                bin = min(s, smax);
+            }
+            atomicAdd(s_hist + bin, 1u);
+        } else if ((uint64_t)s >= sigma) {
+            bad = true;
+        } else {
+            uint32_t h = (s * 0x9E3779B1u) >> (32 - __builtin_ctz(kH));
+            bool done = false;
+#pragma unroll 1
+            for (int probe = 0; probe < 8; ++probe) {
+                const uint32_t old = atomicCAS(keys + h, H::kEmpty, s);
+                if (old == H::kEmpty) used[atomicAdd(nused, 1u)] = h;
+                if (old == H::kEmpty || old == s) {
+                    atomicAdd(vals + h, 1u);
+                    done = true;
+                    break;
+                }
+                h = (h + 1) & (kH - 1);
+            }
+            if (!done) atomicAdd(counts + s, (CNT)1);
+        }
+        return ((s >> ktop) & 1u) ^ 1u;
+    };
+    uint32_t zeros = 0;
+    const uint32_t chunk = lds ? len : H::kChunk;  // hash path: at most kH/2 symbols per flush
+    for (uint32_t c0 = 0; c0 < len; c0 += chunk) {
+        const uint32_t clen = clamp_count(len, c0, chunk);
+        if (clen % V == 0 && ((base + c0) % V) == 0) {
+            for (uint32_t v = tid; v < clen / V; v += kBlock) {
+                union {
+                    uint4 q;
+                    T e[V];
+                } u;
+                u.q = *reinterpret_cast<const uint4 *>(S + base + c0 + (uint64_t)v * V);
+#pragma unroll
+                for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+            }
+        } else {
+            for (uint32_t e = tid; e < clen; e += kBlock) zeros += visit((uint32_t)S[base + c0 + e]);
+        }
+        if (!lds) {
+            __syncthreads();
+            const uint32_t nu = *nused;
+            for (uint32_t i = tid; i < nu; i += kBlock) {
+                const uint32_t h = used[i];
+                atomicAdd(counts + keys[h], (CNT)vals[h]);
+                keys[h] = H::kEmpty;
+                vals[h] = 0;
+            }
+            __syncthreads();
+            if (tid == 0) *nused = 0;
+            __syncthreads();
+        }
+    }
+    return zeros;
+}
+
+// Replica path: one global atomic per symbol present.
+template <typename CNT>
+__device__ __forceinline__ void hist_flush_replicas(const uint32_t *tab, uint32_t reps, uint64_t sigma,
+                                                    CNT *counts) {
+    __syncthreads();
+    for (uint64_t c = threadIdx.x; c < sigma; c += kBlock) {
+        uint32_t sum = 0;
+        for (uint32_t r = 0; r < reps; ++r) sum += tab[(uint64_t)r * (sigma + 1) + c];
+        if (sum) atomicAdd(counts + c, (CNT)sum);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of kItems values per thread (blocked layout).
+struct BlockScanTmp {
+    uint64_t wave_tot[kWaves];
+};
+
+template <int N = kItems>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t (&v)[N], BlockScanTmp &tmp, uint64_t &total) {
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    uint64_t own = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) own += v[j];
+    uint64_t inc = wave_incl_scan_u64(own, lane);
+    if (lane == kWave - 1) tmp.wave_tot[wave] = inc;
+    __syncthreads();
+    uint64_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        uint64_t t = tmp.wave_tot[w];
+        if (w < wave) before += t;
+        total += t;
+    }
+    __syncthreads();
+    uint64_t run = before + inc - own;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        uint64_t x = v[j];
+        v[j] = run;
+        run += x;
+    }
+    return before + inc - own;
+}
+
+// One block scans `count` values, N per thread at a time:
+// store(g, value(0) + ... + value(g-1)) for every g < count.  Returns the total.
+template <int N, typename Val, typename Store>
+__device__ __forceinline__ uint64_t block_scan_all(uint64_t count, BlockScanTmp &tmp, Val value, Store store) {
+    uint64_t carry = 0;
+    for (uint64_t c0 = 0; c0 < count; c0 += (uint64_t)kBlock * N) {
+        const uint64_t base = c0 + (uint64_t)threadIdx.x * N;
+        uint64_t v[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = base + j < count ? value(base + j) : 0;
+        uint64_t total;
+        block_excl_scan<N>(v, tmp, total);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (base + j < count) store(base + j, carry + v[j]);
+        carry += total;
+    }
+    return carry;
+}
+
+// ---------------------------------------------------------------------------
+// Node tables.  Element g in [1, 2^L) is node p = g - 2^l of level l =
+// floor(log2 g) (heap numbering from 1).  Its value is the ones of B_l
+// inside node p = the symbols of its range whose bit k_l is 1 = C[end] -
+// C[middle]; the exclusive scan of these values inside each level gives
+//   D_l[2p]   = ones of B_l before node p,
+//   D_l[2p+1] = zeros of B_l before node p+1,
+// stored at D[2g-2] and D[2g-1] (level l occupies D[2^(l+1)-2, 2^(l+2)-2)).
+struct TableOp {
+    const uint64_t *C;
+    uint64_t *D;
+    uint64_t sigma;
+    uint32_t L;
+    __device__ static uint32_t level_of(uint64_t g) { return 63u - (uint32_t)__clzll((long long)g); }
+    __device__ uint64_t Cc(uint64_t x) const { return C[x < sigma ? x : sigma]; }
+    __device__ uint64_t value(uint64_t g) const {
+        if (g == 0) return 0;
+        uint32_t l = level_of(g), k = L - 1 - l;
+        uint64_t p = g - (1ull << l);
+        return Cc((p + 1) << (k + 1)) - Cc(((2 * p + 1) << k));
+    }
+    __device__ void store(uint64_t g, uint64_t ex) const {
+        if (g == 0) return;
+        uint32_t l = level_of(g), k = L - 1 - l;
+        uint64_t p = g - (1ull << l);
+        uint64_t ones = Cc((p + 1) << (k + 1)) - Cc(((2 * p + 1) << k));
+        D[2 * g - 2] = ex;                                  // ones before node p
+        D[2 * g - 1] = Cc((p + 1) << (k + 1)) - (ex + ones);  // zeros before node p+1
+    }
+    __device__ uint64_t seg_start(uint64_t g) const { return g == 0 ? 0 : (1ull << level_of(g)); }
+    __device__ uint64_t chunk_seg_first(uint64_t c) const {
+        // chunks >= 1 hold one level each; a level with several chunks
+        // starts at chunk 2^(l-12) for 4096-element chunks.
+        if (c == 0) return 0;
+        return 1ull << (63u - (uint32_t)__clzll((long long)c));
+    }
+};
+
+// Directory tail of level l: rank[last] = ones of the level, the sample
+// counts, and the sample entries at or past the counts set to n.  Thread t
+// of `nthreads` handles sample entries t, t + nthreads, ...
+__device__ __forceinline__ void dir_tail(uint32_t l, uint64_t zeros, uint64_t n, uint32_t L, uint64_t *rank,
+                                         uint64_t rank_len, uint64_t *sel1, uint64_t *sel0, uint64_t cap,
+                                         uint64_t *sel_counts, uint64_t t, uint64_t nthreads) {
+    const uint64_t ones = n - zeros;
+    const uint64_t c1 = cdiv(ones, WT_SELECT_SAMPLE), c0 = cdiv(zeros, WT_SELECT_SAMPLE);
+    if (t == 0) {
+        rank[(uint64_t)l * rank_len + rank_len - 1] = ones;
+        sel_counts[l] = c1;
+        sel_counts[L + l] = c0;
+    }
+    for (uint64_t e = min(c1, c0) + t; e < cap; e += nthreads) {
+        if (e >= c1) sel1[(uint64_t)l * cap + e] = n;
+        if (e >= c0) sel0[(uint64_t)l * cap + e] = n;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level pass, one tile.
+//
+// A tile is 16 KiB of the level's sequence whatever the symbol width, so one
+// block has enough bytes in flight to cover HBM latency.  The 256 threads
+// hold the tile packed in 16 registers each (item r of thread t is position
+// r*256 + t), which frees the LDS stage for the split.
+template <typename T>
+struct TileCfg {
+    static constexpr int kBytes = 16384;
+    static constexpr int kItems = kBytes / (kBlock * (int)sizeof(T));  // per thread
+    static constexpr int kTile = kBlock * kItems;                       // positions
+    static constexpr int kWords = kTile / 64;                           // level words
+    static constexpr int kWPL = kWords / kWave;                         // words per lane of wave 0
+    static constexpr int kPer = 4 / (int)sizeof(T);                     // symbols per packed register
+    static constexpr int kRegs = kItems / kPer;
+};
+constexpr int kMinTile = TileCfg<uint32_t>::kTile;  // smallest tile: sizes the per-tile arrays
+constexpr int kSmallD = 512;                        // node tables up to this size are cached in LDS
+
+struct LevelArgs {
+    const void *in;          // S_l (TIN), 16-byte aligned
+    void *out;               // S_{l+1} (TOUT)
+    uint64_t *bits;          // B_l
+    const uint64_t *D;       // D_l: 2^(l+1) entries
+    uint64_t nD;             // 2^(l+1)
+    const uint64_t *tile_prefix;  // zeros of B_l before each tile of this level
+    uint32_t *next_cnt;      // zeros of B_{l+1} per tile of the next level (accumulated here)
+    uint32_t next_shift;     // log2(positions per tile of the next level)
+    const uint32_t *status;  // non-zero: input rejected, do nothing
+    uint64_t *rank, *sel1, *sel0;  // directory rows of level l
+    uint64_t n;
+    uint32_t k;              // bit examined at this level: L-1-l
+};
+
+// Count-ahead: while level l scatters S_{l+1}, it also counts, for every tile
+// of level l+1, the zeros that tile will hold (bit k-1 of the symbols that
+// land in it).  A scan of those counts gives each tile of level l+1 its
+// exclusive zero prefix before level l+1 starts, so no tile ever waits for
+// another.  Each lane keeps a running count for the destination tile it is
+// filling and hands it to a small LDS table keyed by destination tile when
+// that tile changes (a block's runs touch few tiles); the table reaches HBM
+// as one atomic add per touched tile when the block ends, and a table that
+// is full falls back to a direct atomic.
+constexpr int kCountSlots = 64;
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+struct CountTable {
+    uint32_t key[kCountSlots];
+    uint32_t cnt[kCountSlots];
+};
+
+__device__ __forceinline__ void count_init(CountTable &t, int tid) {
+    if (tid < kCountSlots) {
+        t.key[tid] = kNoTile;
+        t.cnt[tid] = 0;
+    }
+}
+
+__device__ __forceinline__ void count_add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+    // Hashed slot with a short linear probe: the tiles one block touches are
+    // few but can be far apart by large powers of two (a run of zeros and a
+    // run of ones half a level apart), so the low bits alone would collide.
+    uint32_t slot = (ntile * 0x9E3779B9u) >> 26;
+#pragma unroll 1
+    for (int probe = 0; probe < 8; ++probe) {
+        const uint32_t old = atomicCAS(&t.key[slot], kNoTile, ntile);
+        if (old == kNoTile || old == ntile) {
+            atomicAdd(&t.cnt[slot], c);
+            return;
+        }
+        slot = (slot + 1) & (kCountSlots - 1);
+    }
+    atomicAdd(next_cnt + ntile, c);
+}
+
+__device__ __forceinline__ void count_flush(CountTable &t, uint32_t *next_cnt, int tid) {
+    if (tid < kCountSlots && t.key[tid] != kNoTile && t.cnt[tid]) atomicAdd(next_cnt + t.key[tid], t.cnt[tid]);
+}
+
+// Per-lane running count for one destination tile.
+struct LaneCount {
+    uint32_t tile = kNoTile, cnt = 0;
+    __device__ __forceinline__ void add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+        if (ntile != tile) {
+            if (cnt) count_add(t, next_cnt, tile, cnt);
+            tile = ntile;
+            cnt = 0;
+        }
+        cnt += c;
+    }
+    __device__ __forceinline__ void flush(CountTable &t, uint32_t *next_cnt) {
+        if (cnt) count_add(t, next_cnt, tile, cnt);
+        cnt = 0;
+    }
+};
+
+template <typename TIN>
+struct LdsLevel {
+    __align__(16) unsigned char stage[TileCfg<TIN>::kBytes];
+    uint64_t words[TileCfg<TIN>::kWords];
+    uint32_t zpre[TileCfg<TIN>::kWords];
+    uint64_t D[kSmallD];
+    uint64_t Z0;
+    uint32_t Zt;
+    CountTable ct;
+};
+
+// Generic widths (TIN, TOUT in {1, 2, 4} bytes).  The caller synchronises
+// the block before reusing `s`.
+template <typename TIN, typename TOUT, bool SCATTER, bool DIRS>
+__device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, LdsLevel<TIN> &s) {
+    using Cfg = TileCfg<TIN>;
+    constexpr int kTile = Cfg::kTile, kIt = Cfg::kItems, kWPL = Cfg::kWPL;
+    constexpr int V = 16 / sizeof(TIN);
+
+    if (*a.status) return;  // uniform across the grid: the input was rejected
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint64_t t0 = tile * kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
+    const uint32_t k = a.k;
+    const bool d_lds = SCATTER && a.nD <= (uint64_t)kSmallD;
+    if (d_lds)
+        for (int i = tid; i < (int)a.nD; i += kBlock) s.D[i] = a.D[i];
+    if (SCATTER) count_init(s.ct, tid);
+
+    // 1. Coalesced 16-byte loads of the tile into LDS.
+    TIN *stage_in = reinterpret_cast<TIN *>(s.stage);
+    const TIN *in = reinterpret_cast<const TIN *>(a.in) + t0;
+    if (len == (uint32_t)kTile) {
+#pragma unroll
+        for (int r = 0; r < kIt / V; ++r) {
+            int e = (r * kBlock + tid) * V;
+            *reinterpret_cast<uint4 *>(stage_in + e) = *reinterpret_cast<const uint4 *>(in + e);
+        }
+    } else {
+        for (uint32_t e = tid; e < len; e += kBlock) stage_in[e] = in[e];
+    }
+    __syncthreads();
+
+    // 2. Striped view: item r of wave w, lane j is position r*256 + 64w + j,
+    //    so each ballot is one position-ordered word of B_l (word 4r + w).
+    uint32_t pk[Cfg::kRegs];
+#pragma unroll
+    for (int i = 0; i < Cfg::kRegs; ++i) pk[i] = 0;
+#pragma unroll
+    for (int r = 0; r < kIt; ++r) {
+        uint32_t e = (uint32_t)(r * kBlock + tid);
+        bool valid = e < len;
+        uint32_t sym = valid ? (uint32_t)stage_in[e] : 0u;
+        pk[r / Cfg::kPer] |= sym << (8 * sizeof(TIN) * (r % Cfg::kPer));
+        bool bit = valid && ((sym >> k) & 1u);
+        uint64_t vm = __ballot(valid);
+        uint64_t w = __ballot(bit);
+        if (lane == 0) {
+            s.words[r * kWaves + wave] = w;
+            s.zpre[r * kWaves + wave] = (uint32_t)(__popcll(vm) - __popcll(w));
+        }
+    }
+    __syncthreads();
+
+    // 3. Wave 0: scan of the word zero-counts, bit words to HBM, directory
+    //    entries.
+    if (wave == 0) {
+        uint32_t zp[kWPL];
+        uint64_t wd[kWPL];
+        uint32_t own = 0;
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            zp[m] = own;
+            own += s.zpre[lane * kWPL + m];
+            wd[m] = s.words[lane * kWPL + m];
+        }
+        uint32_t inc = wave_incl_scan_u32(own, lane);
+        uint32_t Zt = __shfl(inc, kWave - 1, kWave);
+        const uint64_t Z0 = a.tile_prefix[tile];
+        const uint32_t ex = inc - own;
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            zp[m] += ex;
+            s.zpre[lane * kWPL + m] = zp[m];
+        }
+        if (lane == 0) {
+            s.Z0 = Z0;
+            s.Zt = Zt;
+        }
+#pragma unroll
+        for (int m = 0; m < kWPL; ++m) {
+            uint32_t w = (uint32_t)lane * kWPL + m;
+            if (w * 64u < len) a.bits[(t0 >> 6) + w] = wd[m];
+        }
+        if (DIRS) emit_directories<kWPL>(wd, zp, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
+    }
+    if (!SCATTER) return;
+    __syncthreads();
+    const uint64_t Z0 = s.Z0;
+    const uint32_t Zt = s.Zt;
+
+    // 4. Stable split of the tile by the level bit into LDS: zeros keep their
+    //    order at [0, Zt), ones at [Zt, len).  Inside each region the
+    //    elements stay grouped by node, and each node's group lands on
+    //    consecutive positions of S_{l+1}.
+    TOUT *stage_out = reinterpret_cast<TOUT *>(s.stage);
+    const uint64_t lt = lanemask_lt(lane);
+#pragma unroll
+    for (int r = 0; r < kIt; ++r) {
+        uint32_t e = (uint32_t)(r * kBlock + tid);
+        if (e < len) {
+            uint64_t w = s.words[r * kWaves + wave];
+            uint32_t zl = s.zpre[r * kWaves + wave] + (uint32_t)__popcll(~w & lt);
+            uint32_t slot = ((w >> lane) & 1ull) ? Zt + (e - zl) : zl;
+            uint32_t sym = (pk[r / Cfg::kPer] >> (8 * sizeof(TIN) * (r % Cfg::kPer))) &
+                           (sizeof(TIN) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(TIN))) - 1u));
+            stage_out[slot] = (TOUT)sym;
+        }
+    }
+    __syncthreads();
+
+    // 5. Scatter.  Position s of the split tile holds a zero of node p iff
+    //    s < Zt; its destination is D[2p] + (zeros before it on the level)
+    //    for a zero and D[2p+1] + (ones before it) for a one -- Fig. 1's
+    //    start + X[i] and start + X_s + i - X[i] with the node-relative
+    //    counts rebased to level-wide counts through the tables.
+    TOUT *out = reinterpret_cast<TOUT *>(a.out);
+    const uint64_t O0 = t0 - Z0;
+    const uint32_t kn = k - 1;  // bit of the next level
+    LaneCount lc;
+#pragma unroll 4
+    for (int r = 0; r < kIt; ++r) {
+        uint32_t sp = (uint32_t)(r * kBlock + tid);
+        if (sp < len) {
+            TOUT v = stage_out[sp];
+            uint64_t q = (uint64_t)((uint32_t)v >> k);
+            if (q < a.nD) {
+                uint64_t base = d_lds ? s.D[q] : a.D[q];
+                uint64_t dest = base + (sp < Zt ? Z0 + sp : O0 + (sp - Zt));
+                if (dest < a.n) {
+                    out[dest] = v;
+                    lc.add(s.ct, a.next_cnt, (uint32_t)(dest >> a.next_shift), (((uint32_t)v >> kn) & 1u) ^ 1u);
+                }
+            }
+        }
+    }
+    lc.flush(s.ct, a.next_cnt);
+    __syncthreads();
+    count_flush(s.ct, a.next_cnt, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Level pass for byte symbols (n < 2^32): the same steps as level_tile with
+// SWAR arithmetic, since at HBM rate a byte symbol leaves only about ten
+// lane operations per level.  A tile is 4 rows of 4096 bytes; thread t owns
+// bytes [16t, 16t+16) of every row as four dwords.
+//   bits:  a 4x4 byte transpose (v_perm) lines bit k of the 16 bytes up so
+//          that a few shifts and ORs give them as a 16-bit mask in position
+//          order; four lanes' masks are one word of B_l, so the LDS array of
+//          masks read as 64-bit words *is* the tile's slice of B_l.
+//   scan:  two rows per 32-bit value (16-bit fields), one wave scan each.
+//   split: bytes go to their LDS slot one at a time.
+//   scatter: sixteen slots per lane; inside one run (same node, same bit)
+//          they have consecutive destinations and leave as one (possibly
+//          unaligned) 16-byte store.
+typedef uint32_t u128_unaligned __attribute__((ext_vector_type(4), aligned(1)));
+
+__device__ __forceinline__ uint32_t mask16_bit(uint4 d, uint32_t k) {
+    // Transpose so that byte B of t_i is byte 4B+i of the chunk ...
+    const uint32_t a0 = __builtin_amdgcn_perm(d.y, d.x, 0x05010400u);
+    const uint32_t a1 = __builtin_amdgcn_perm(d.y, d.x, 0x07030602u);
+    const uint32_t a2 = __builtin_amdgcn_perm(d.w, d.z, 0x05010400u);
+    const uint32_t a3 = __builtin_amdgcn_perm(d.w, d.z, 0x07030602u);
+    const uint32_t t0 = __builtin_amdgcn_perm(a2, a0, 0x05040100u);
+    const uint32_t t1 = __builtin_amdgcn_perm(a2, a0, 0x07060302u);
+    const uint32_t t2 = __builtin_amdgcn_perm(a3, a1, 0x05040100u);
+    const uint32_t t3 = __builtin_amdgcn_perm(a3, a1, 0x07060302u);
+    // ... then byte B of u holds bit k of chunk bytes 4B..4B+3 at bits 0..3.
+    const uint32_t M = 0x01010101u;
+    uint32_t u = ((t0 >> k) & M) | (((t1 >> k) & M) << 1) | (((t2 >> k) & M) << 2) | (((t3 >> k) & M) << 3);
+    u |= u >> 4;
+    return (u & 0xFFu) | ((u >> 8) & 0xFF00u);
+}
+
+__device__ __forceinline__ uint32_t byte_of(const uint4 &d, int b) {
+    const uint32_t w = b < 4 ? d.x : (b < 8 ? d.y : (b < 12 ? d.z : d.w));
+    return (w >> (8 * (b & 3))) & 0xFFu;
+}
+
+struct LdsLevelU8 {
+    static constexpr int kTile = 16384, kRows = 4, kRowBytes = 4096;
+    __align__(16) uint8_t stage[kTile];
+    __align__(16) uint16_t m16[kTile / 16];  // 256 words of B_l
+    uint32_t wz[kRows][kWaves];
+    uint32_t zpre[kTile / 64];
+    uint32_t D[256];
+    CountTable ct;
+};
+
+template <bool SCATTER, bool DIRS>
+__device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile, LdsLevelU8 &s) {
+    constexpr int kTile = LdsLevelU8::kTile, kRows = LdsLevelU8::kRows, kRowBytes = LdsLevelU8::kRowBytes;
+
+    if (*a.status) return;  // uniform across the grid: the input was rejected
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t t0 = tile * (uint32_t)kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
+    const uint32_t k = a.k;
+    const uint32_t Z0 = (uint32_t)a.tile_prefix[tile];  // zeros of the level before this tile
+    if (SCATTER) {
+        for (int i = tid; i < (int)a.nD; i += kBlock) s.D[i] = (uint32_t)a.D[i];
+        count_init(s.ct, tid);
+    }
+
+    // Load: thread t, row r holds positions r*4096 + 16t .. +15.
+    const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
+    uint4 d[kRows];
+    uint32_t m[kRows], z[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+        if (p + 16 <= len) {
+            d[r] = *reinterpret_cast<const uint4 *>(in + p);
+        } else {
+            const uint32_t nv = clamp_count(len, p, 16u);
+            uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+            d[r] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+        const uint32_t nv = clamp_count(len, p, 16u);
+        m[r] = mask16_bit(d[r], k) & ((1u << nv) - 1u);
+        z[r] = nv - (uint32_t)__popc(m[r]);
+        s.m16[r * kBlock + tid] = (uint16_t)m[r];
+    }
+
+    // Zero-count scan in position order (rows outer, threads inner).
+    const uint32_t v01 = z[0] | (z[1] << 16), v23 = z[2] | (z[3] << 16);
+    const uint32_t i01 = wave_incl_scan_u32(v01, lane), i23 = wave_incl_scan_u32(v23, lane);
+    if (lane == kWave - 1) {
+        s.wz[0][wave] = i01 & 0xFFFFu;
+        s.wz[1][wave] = i01 >> 16;
+        s.wz[2][wave] = i23 & 0xFFFFu;
+        s.wz[3][wave] = i23 >> 16;
+    }
+    __syncthreads();
+    const uint32_t e01 = i01 - v01, e23 = i23 - v23;
+    const uint32_t we[kRows] = {e01 & 0xFFFFu, e01 >> 16, e23 & 0xFFFFu, e23 >> 16};
+    uint32_t zl[kRows], acc = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t x = s.wz[r][w];
+            before += w < wave ? x : 0u;
+            tot += x;
+        }
+        zl[r] = acc + before + we[r];
+        acc += tot;
+    }
+    const uint32_t Zt = acc;
+    if ((tid & 3) == 0)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) s.zpre[r * (kBlock / 4) + tid / 4] = zl[r];
+    __syncthreads();
+
+    // Bit words of the tile (word tid = m16[4 tid .. 4 tid + 3]).
+    const uint64_t *s_w64 = reinterpret_cast<const uint64_t *>(s.m16);
+    if ((uint32_t)tid * 64u < len) a.bits[(t0 >> 6) + tid] = s_w64[tid];
+
+    // Directory entries: wave w covers row w, i.e. words 64w .. 64w+63.
+    if (DIRS) {
+        const uint32_t wbase = (uint32_t)wave * kRowBytes;
+        if (wbase < len) {
+            const uint32_t zb = s.zpre[wave * kWave];  // zeros of the tile before this row
+            const uint32_t ze = wave + 1 < kWaves ? s.zpre[(wave + 1) * kWave] : Zt;
+            const uint64_t wd[1] = {s_w64[tid]};
+            const uint32_t zp[1] = {s.zpre[tid] - zb};
+            emit_directories<1>(wd, zp, (uint64_t)Z0 + zb, (uint64_t)t0 + wbase, clamp_count(len, wbase, (uint32_t)kRowBytes),
+                                ze - zb, a.n, a.rank, a.sel1, a.sel0, lane);
+        }
+    }
+    if (!SCATTER) return;
+
+    // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).
+    if (len == (uint32_t)kTile) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const uint32_t bit = (m[r] >> b) & 1u;
+                s.stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
+                zc += bit ^ 1u;
+                oc += bit;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+            const uint32_t nv = clamp_count(len, e0, 16u);
+            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const uint32_t bit = (m[r] >> b) & 1u;
+                if ((uint32_t)b < nv) s.stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
+                zc += bit ^ 1u;
+                oc += bit;
+            }
+        }
+    }
+    __syncthreads();
+
+    // Scatter (see level_tile for the destination formula), sixteen slots
+    // per lane: inside one run (same node, same bit) the sixteen bytes have
+    // consecutive destinations and leave as one unaligned 16-byte store.
+    const uint32_t O0 = t0 - Z0;
+    const uint32_t kn = k - 1;  // bit of the next level
+    const uint32_t Mn = 0x01010101u << kn;
+    const uint32_t n16 = a.n > 15 ? (uint32_t)(a.n - 15) : 0u;  // dest < n16 <=> dest + 15 < n
+    uint8_t *out = reinterpret_cast<uint8_t *>(a.out);
+    const uint4 *s_st128 = reinterpret_cast<const uint4 *>(s.stage);
+    LaneCount lc;
+#pragma unroll
+    for (int i = 0; i < kTile / (16 * kBlock); ++i) {
+        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
+        if (sl >= len) continue;
+        const uint4 v = s_st128[j];
+        const uint32_t q0 = (v.x & 0xFFu) >> k, q15 = (v.w >> 24) >> k;
+        if (sl + 15 < len && q0 == q15) {
+            // One run: the bit is the low bit of q, so the region is uniform too.
+            const uint32_t dest = s.D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
+            if (dest < n16) {
+                *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                const uint32_t nt = dest >> a.next_shift;
+                if (((dest + 15) >> a.next_shift) == nt) {
+                    const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) + __popc(v.z & Mn) +
+                                                     __popc(v.w & Mn));
+                    lc.add(s.ct, a.next_cnt, nt, 16u - ones);
+                } else {
+                    for (uint32_t c = 0; c < 16; ++c)
+                        if (!((byte_of(v, (int)c) >> kn) & 1u))
+                            count_add(s.ct, a.next_cnt, (dest + c) >> a.next_shift, 1u);
+                }
+            }
+        } else {
+            // Several runs meet here (or the tile ends): byte by byte.
+            const uint32_t nc = clamp_count(len, sl, 16u);
+            for (uint32_t c = 0; c < nc; ++c) {
+                const uint32_t bc = byte_of(v, (int)c), qc = bc >> k, sc = sl + c;
+                const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
+                if (dest < a.n) {
+                    out[dest] = (uint8_t)bc;
+                    if (!((bc >> kn) & 1u)) count_add(s.ct, a.next_cnt, dest >> a.next_shift, 1u);
+                }
+            }
+        }
+    }
+    lc.flush(s.ct, a.next_cnt);
+    __syncthreads();
+    count_flush(s.ct, a.next_cnt, tid);
+}
+
+// Exclusive prefix of per-tile zero counts by one block: pre[t] =
+// cnt[0] + ... + cnt[t-1] for t < T.
+__device__ __forceinline__ void tile_prefix_block(const uint32_t *cnt, uint64_t *pre, uint64_t T, BlockScanTmp &tmp) {
+    block_scan_all<4>(
+        T, tmp, [&](uint64_t g) -> uint64_t { return cnt[g]; }, [&](uint64_t g, uint64_t ex) { pre[g] = ex; });
+}
+
+}  // namespace wt

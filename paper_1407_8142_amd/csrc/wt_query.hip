@@ -98,7 +98,8 @@ __global__ void rank_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qi, u
         return;
     }
     uint64_t p = 0, r = i;  // r: elements of node p that precede the query position
-    for (uint32_t l = 0; l < t.L && r > 0; ++l) {
+    for (uint32_t l = 0; l < t.L; ++l) {
+        if (r == 0) break;
         uint32_t k = t.L - 1 - l;
         uint64_t a = Cat(t, p << (k + 1));
         uint32_t b = (uint32_t)((c >> k) & 1u);

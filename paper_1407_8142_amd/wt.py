@@ -15,14 +15,17 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwt.so")
 
-WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL, WT_ERR_SCRATCH, WT_ERR_RANGE, WT_ERR_HIP, WT_ERR_NOMEM = 0, -1, -2, -3, -4, -5, -6
+WT_OK, WT_ERR_ARG, WT_ERR_SYMBOL, WT_ERR_SCRATCH, WT_ERR_RANGE, WT_ERR_HIP, WT_ERR_NOMEM, WT_ERR_TIMEOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "WT_OK", -1: "WT_ERR_ARG", -2: "WT_ERR_SYMBOL", -3: "WT_ERR_SCRATCH", -4: "WT_ERR_RANGE",
-                -5: "WT_ERR_HIP", -6: "WT_ERR_NOMEM"}
+                -5: "WT_ERR_HIP", -6: "WT_ERR_NOMEM", -7: "WT_ERR_TIMEOUT"}
+BATCH_PERSISTENT, BATCH_PER_PHASE = 0, 1
 RANK_BLOCK_BITS = 512
 SELECT_SAMPLE = 4096
 
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
-           "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect"]
+           "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
+           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status"]
 
 
 class WTError(RuntimeError):
@@ -50,6 +53,26 @@ class View(ctypes.Structure):
                 ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_void_p), ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64),
+                ("sym_bytes", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("out", Outputs)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("chunk", ctypes.c_uint32),
+                ("spin_limit", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class BatchLayout(ctypes.Structure):
+    _fields_ = [("scratch_bytes", ctypes.c_uint64), ("clear_bytes", ctypes.c_uint64), ("off_jobs", ctypes.c_uint64),
+                ("off_segs", ctypes.c_uint64), ("off_seg_of", ctypes.c_uint64), ("njobs", ctypes.c_uint32),
+                ("nsegs", ctypes.c_uint32), ("items", ctypes.c_uint32), ("phases", ctypes.c_uint32),
+                ("phase_first", ctypes.c_uint32 * 33)]
+
+
 _lib = None
 
 
@@ -73,8 +96,13 @@ def lib() -> ctypes.CDLL:
         L.wt_set_lookback_spin_limit.argtypes = [i32]
         L.wt_timing_enable.argtypes = [i32]
         L.wt_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_float), i32]
+        L.wt_batch_plan.argtypes = [ctypes.POINTER(Job), u32, ctypes.POINTER(BatchLayout)]
+        L.wt_batch_prepare.argtypes = [ctypes.POINTER(Job), u32, ctypes.POINTER(BatchLayout), vp, u64, vp]
+        L.wt_batch_run.argtypes = [ctypes.POINTER(BatchLayout), ctypes.POINTER(Tune), vp, vp]
+        L.wt_batch_status.argtypes = [ctypes.POINTER(BatchLayout), vp, ctypes.POINTER(ctypes.c_int32), vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
-                  "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect"):
+                  "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
+                  "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -117,6 +145,13 @@ class WaveletTree:
     sel_counts: torch.Tensor | None
     scratch: torch.Tensor
     layout: Layout
+
+    @staticmethod
+    def output_words(n: int, sigma: int, sym_bytes: int) -> tuple[Layout, list[tuple[int, ...]]]:
+        """Shapes (in int64 words) of bits, C, rank, sel1, sel0, sel_counts."""
+        lay = plan(n, sigma, sym_bytes)
+        L, W = lay.L, lay.words_per_level
+        return lay, [(L, W), (sigma + 1,), (L, lay.rank_len), (L, lay.sel_cap), (L, lay.sel_cap), (2 * L,)]
 
     @staticmethod
     def allocate(n: int, sigma: int, sym_bytes: int, directories: bool = True, device="cuda") -> "WaveletTree":
@@ -200,6 +235,72 @@ def build(seq: torch.Tensor, sigma: int, directories: bool = True, stream=None) 
     """Allocate buffers and build the tree of ``seq`` (1-, 2- or 4-byte symbols)."""
     t = WaveletTree.allocate(seq.numel(), sigma, seq.element_size(), directories, seq.device)
     return t.build_from(seq, stream)
+
+
+def batch_plan(jobs) -> BatchLayout:
+    arr = (Job * max(len(jobs), 1))(*jobs)
+    lay = BatchLayout()
+    _check(lib().wt_batch_plan(arr, len(jobs), ctypes.byref(lay)), "wt_batch_plan")
+    return lay
+
+
+class Batch:
+    """Many sequences built together by wt_batch_run (one persistent launch
+    of the work kernel, or one launch per phase).  All outputs live in one
+    int64 slab (each buffer 256-byte aligned); ``trees[i]`` views job i."""
+
+    def __init__(self, seqs: list[torch.Tensor], sigmas: list[int], stream=None):
+        if len(seqs) != len(sigmas):
+            raise ValueError("one sigma per sequence")
+        dev = seqs[0].device if seqs else torch.device("cuda")
+        shapes, total = [], 0
+        for q, sigma in zip(seqs, sigmas):
+            if not q.is_cuda or not q.is_contiguous() or q.data_ptr() % 16:
+                raise ValueError("sequences must be contiguous, 16-byte aligned device tensors")
+            lay, sh = WaveletTree.output_words(q.numel(), int(sigma), q.element_size())
+            offs = []
+            for shape in sh:
+                offs.append(total)
+                words = 1
+                for d in shape:
+                    words *= d
+                total += -(-words // 32) * 32
+            shapes.append((lay, sh, offs))
+        self.slab = torch.empty(max(total, 32), dtype=torch.int64, device=dev)
+        self.trees: list[WaveletTree] = []
+        jobs = []
+        for q, sigma, (lay, sh, offs) in zip(seqs, sigmas, shapes):
+            views = []
+            for shape, off in zip(sh, offs):
+                words = 1
+                for d in shape:
+                    words *= d
+                views.append(self.slab[off:off + words].view(*shape))
+            t = WaveletTree(n=q.numel(), sigma=int(sigma), L=lay.L, sym_bytes=q.element_size(), bits=views[0],
+                            C=views[1], rank=views[2], sel1=views[3], sel0=views[4], sel_counts=views[5],
+                            scratch=self.slab[:0], layout=lay)
+            self.trees.append(t)
+            jobs.append(Job(_ptr(q), q.numel(), int(sigma), q.element_size(), 0, t.outputs()))
+        self.seqs = list(seqs)
+        self.jobs = (Job * max(len(jobs), 1))(*jobs)
+        self.njobs = len(jobs)
+        self.layout = BatchLayout()
+        _check(lib().wt_batch_plan(self.jobs, self.njobs, ctypes.byref(self.layout)), "wt_batch_plan")
+        self.scratch = torch.empty(max(self.layout.scratch_bytes, 256), dtype=torch.uint8, device=dev)
+        rc = lib().wt_batch_prepare(self.jobs, self.njobs, ctypes.byref(self.layout), _ptr(self.scratch),
+                                    self.scratch.numel(), _stream(stream))
+        _check(rc, "wt_batch_prepare")
+
+    def run(self, tune: Tune | None = None, stream=None) -> "Batch":
+        t = tune if tune is not None else Tune()
+        _check(lib().wt_batch_run(ctypes.byref(self.layout), ctypes.byref(t), _ptr(self.scratch), _stream(stream)),
+               "wt_batch_run")
+        return self
+
+    def status(self, stream=None) -> tuple[int, list[int]]:
+        codes = (ctypes.c_int32 * max(self.njobs, 1))()
+        rc = lib().wt_batch_status(ctypes.byref(self.layout), _ptr(self.scratch), codes, _stream(stream))
+        return int(rc), [int(codes[i]) for i in range(self.njobs)]
 
 
 def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:

@@ -224,3 +224,17 @@ def test_lookback_fallback_forced(wtmod, oracle_mod):
         assert_same(got, want, keys=("rank", "sel1", "sel0", "sel_counts"), ctx="fallback standalone")
     finally:
         wtmod.set_lookback_spin_limit(8)
+
+
+def test_random_ragged_sweep(wtmod, oracle_mod):
+    """Many short and ragged inputs (tails inside a 16-byte group, a row and
+    a tile): every group past the end of a partial tile must leave the split
+    untouched."""
+    rng = np.random.default_rng(2024)
+    cases = [(int(rng.integers(1, 300)), int(rng.choice([2, 5, 17, 256]))) for _ in range(120)]
+    cases += [(int(rng.integers(16385, 16384 * 3)), int(rng.choice([4, 256]))) for _ in range(12)]
+    cases += [(int(rng.integers(1, 9000)), int(rng.choice([300, 70000]))) for _ in range(12)]
+    for n, sigma in cases:
+        S = rng.integers(0, sigma, n, dtype=np.uint64).astype(inputs.dtype_for_sigma(sigma))
+        t = gpu_build(wtmod, S, sigma)
+        assert_same(t.to_numpy(), oracle_mod.build_all(S, sigma), ctx=f"sweep n={n} sigma={sigma}")

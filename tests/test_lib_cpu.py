@@ -109,3 +109,53 @@ def test_build_argument_errors_are_synchronous():
     # empty batches are no-ops
     v.bits = v.rank = v.sel1 = v.sel0 = ctypes.c_void_p(4096)
     assert lib.wt_select(ctypes.byref(v), None, None, 0, None, None) == wt.WT_OK
+
+
+def _job(n, sigma, b):
+    return wt.Job(None, n, sigma, b, 0, wt.Outputs())
+
+
+def test_batch_plan_queue_shape():
+    """The queue holds every job's level-0 histogram tiles, one table item
+    per job, then level by level the tiles of every job that has that level
+    (tiles of 16 KiB at the level's width); phases split it in that order."""
+    spec = [(0, 4, 1), (1, 1, 1), (100000, 256, 1), (20000, 1 << 16, 2), (5000, 1 << 20, 4), (70000, 5, 1)]
+    lay = wt.batch_plan([_job(*s) for s in spec])
+    tiles = lambda n, w: -(-n // (16384 // w))
+    L = lambda s: 0 if s == 1 else (s - 1).bit_length()
+    mid = lambda l: 1 if l <= 8 else (2 if l <= 16 else 4)
+    hist = sum(tiles(n, b) for n, s, b in spec)
+    per_level = []
+    for l in range(max(L(s) for n, s, b in spec if n)):
+        per_level.append(sum(tiles(n, b if l == 0 else mid(L(s))) for n, s, b in spec if n and l < L(s)))
+    assert lay.njobs == len(spec)
+    assert lay.phases == 2 + len(per_level)
+    assert lay.items == hist + len(spec) + sum(per_level)
+    firsts = [0, hist, hist + len(spec)]
+    for c in per_level:
+        firsts.append(firsts[-1] + c)
+    assert list(lay.phase_first)[:lay.phases + 1] == firsts
+    assert lay.scratch_bytes % 256 == 0 and lay.clear_bytes <= lay.scratch_bytes
+    assert lay.off_jobs >= lay.clear_bytes
+
+
+@pytest.mark.parametrize("spec,rc", [([(1 << 32, 4, 1)], wt.WT_ERR_RANGE), ([(10, 300, 1)], wt.WT_ERR_ARG),
+                                     ([(10, 0, 1)], wt.WT_ERR_ARG), ([(10, 4, 3)], wt.WT_ERR_ARG),
+                                     ([(10, 4, 1), (10, 1 << 31, 4)], wt.WT_ERR_RANGE)])
+def test_batch_plan_rejects(spec, rc):
+    arr = (wt.Job * len(spec))(*[_job(*s) for s in spec])
+    lay = wt.BatchLayout()
+    assert wt.lib().wt_batch_plan(arr, len(spec), ctypes.byref(lay)) == rc
+
+
+def test_batch_prepare_rejects_bad_arguments():
+    """Rejected before any device work: NULL or misaligned scratch, a short
+    scratch, and a job without directory buffers."""
+    jobs = [_job(100, 4, 1)]
+    lay = wt.batch_plan(jobs)
+    arr = (wt.Job * 1)(*jobs)
+    prep = wt.lib().wt_batch_prepare
+    assert prep(arr, 1, ctypes.byref(lay), None, lay.scratch_bytes, None) == wt.WT_ERR_ARG
+    assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(16), lay.scratch_bytes, None) == wt.WT_ERR_ARG
+    assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(4096), lay.scratch_bytes - 1, None) == wt.WT_ERR_SCRATCH
+    assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(4096), lay.scratch_bytes, None) == wt.WT_ERR_ARG
