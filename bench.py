@@ -4,9 +4,14 @@ sequence already resident in HBM.
 
 Prints ONE JSON line.  Default workload: text-like n = 2^28 uint8, sigma = 256
 (Zipf(1.1) symbols over a permuted byte alphabet, geometric runs of mean 4).
+The line also carries a "batch" object: 4096 sequences (lengths
+log-uniform in [2^10, 2^20], sigma in {4, 256, 2^16}) built by one
+wt_batch_run (autotuned launch, replayed as a captured graph) against one
+wt_build per sequence on the same GPU, with the two outputs compared bit
+for bit.
 
   python bench.py [--steps K] [--warmup W] [--workload text256|uniform256|alpha16|alpha20]
-                  [--no-cpu-baseline]
+                  [--no-cpu-baseline] [--no-batch] [--batch-count N]
 """
 from __future__ import annotations
 
@@ -23,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "symbols*levels/s and % HBM peak; batched vs per-seq builds, bit-exact"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_pass.json")
-LEVEL_PASS_SOURCES = [os.path.join(ROOT, "paper_1407_8142_amd", "csrc", f) for f in ("wt_build.hip", "wt_device.hpp")]
+LEVEL_PASS_SOURCES = [os.path.join(ROOT, "paper_1407_8142_amd", "csrc", f)
+                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp")]
 
 WORKLOADS = {
     "text256": ("text-like: n=2^28 uint8, sigma=256, Zipf(1.1) over a permuted byte alphabet, geometric runs "
@@ -83,6 +89,110 @@ def cpu_baseline(S, sigma, L, sample_n):
                       f"{dt:.1f} s"}
 
 
+def batch_model_bytes(jobs) -> float:
+    """Algorithmic HBM bytes of one batched build: per job the histogram read
+    of S, every level pass (level_pass_bytes) and the C output."""
+    total = 0.0
+    for n, sigma, b in jobs:
+        L = 0 if sigma == 1 else (sigma - 1).bit_length()
+        mid = 1 if L <= 8 else (2 if L <= 16 else 4)
+        total += n * b + sum(level_pass_bytes(n, L, b, mid)) + 8 * (sigma + 1)
+    return total
+
+
+def batch_leg(count: int, steps: int):
+    """Batched build vs one wt_build per sequence, same outputs, same GPU."""
+    import ctypes
+
+    import torch
+
+    from paper_1407_8142_amd import autotune, inputs, wt
+
+    log(f"[batch] generating {count} sequences")
+    seqs = inputs.batch(count=count)
+    jobs = [(q.S.size, q.sigma, q.S.dtype.itemsize) for q in seqs]
+    sym_lvl = sum(n * (0 if s == 1 else (s - 1).bit_length()) for n, s, _ in jobs)
+    dev = [wt.to_device(q.S) for q in seqs]
+    b = wt.Batch(dev, [q.sigma for q in seqs])
+    b.slab.fill_(-1)  # padding between buffers is never written: keep it equal in both runs
+    log(f"[batch] {b.layout.items} work items, scratch {b.layout.scratch_bytes / 2**30:.2f} GiB, "
+        f"outputs {b.slab.numel() * 8 / 2**30:.2f} GiB; autotuning")
+    best, table = autotune.autotune(b)
+    log(f"[batch] best tune {best.as_dict()}: " + ", ".join(f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/"
+                                                           f"{r['tune']['chunk']}={r['ms']}" for r in table))
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        b.run(best, stream=stream)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            b.run(best, stream=stream)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    rc, codes = b.status()
+    if rc != wt.WT_OK:
+        raise SystemExit(f"batched build failed: {wt.STATUS_NAMES.get(rc, rc)}")
+    cur = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(cur)
+    for _ in range(steps):
+        g.replay()
+    e1.record(cur)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / steps
+    want = b.slab.clone()
+
+    # One wt_build per sequence into the same output buffers, one scratch
+    # buffer reused in stream order.
+    lib = wt.lib()
+    scratch_bytes = max(wt.plan(n, s, w).scratch_bytes for n, s, w in jobs)
+    scratch = torch.empty(scratch_bytes, dtype=torch.uint8, device="cuda")
+    outs = [t.outputs() for t in b.trees]
+    args = [(wt._ptr(q), n, s, w) for q, (n, s, w) in zip(dev, jobs)]
+    sp, sbytes = wt._ptr(scratch), scratch.numel()
+
+    def per_seq(stream_handle):
+        for (p, n, s, w), o in zip(args, outs):
+            rc = lib.wt_build(p, n, s, w, ctypes.byref(o), sp, sbytes, stream_handle)
+            if rc:
+                raise SystemExit(f"wt_build failed: {rc}")
+
+    per_seq(cur.cuda_stream)  # warm-up
+    torch.cuda.synchronize()
+    b.slab.fill_(-1)
+    torch.cuda.synchronize()
+    reps = max(1, min(steps, 3))
+    w0 = time.perf_counter()
+    e0.record(cur)
+    for _ in range(reps):
+        per_seq(cur.cuda_stream)
+    e1.record(cur)
+    torch.cuda.synchronize()
+    per_seq_ms = e0.elapsed_time(e1) / reps
+    per_seq_wall_ms = (time.perf_counter() - w0) * 1e3 / reps
+    identical = bool(torch.equal(b.slab, want))
+    model = batch_model_bytes(jobs)
+    log(f"[batch] batched {batch_ms:.3f} ms, per-sequence {per_seq_ms:.3f} ms (wall {per_seq_wall_ms:.3f}), "
+        f"identical={identical}")
+    return {
+        "config": {"workload": f"batched build: {count} sequences, lengths log-uniform in [2^10, 2^20], "
+                               "sigma uniform over {4, 256, 2^16} (u8/u8/u16), uniform symbols",
+                   "sequences": count, "symbols": sum(n for n, _, _ in jobs), "symbols_levels": sym_lvl},
+        "value": sym_lvl / (batch_ms / 1e3), "unit": "symbols*levels/s", "ms_per_step": batch_ms,
+        "steps": steps, "launch": "wt_batch_run captured in one graph (" + (
+            "one persistent work-queue launch" if best.mode == wt.BATCH_PERSISTENT else "one launch per phase")
+        + " + a clearing kernel)", "tune": best.as_dict(), "autotune": table,
+        "per_seq": {"value": sym_lvl / (per_seq_ms / 1e3), "ms_per_step": per_seq_ms,
+                    "wall_ms_per_step": per_seq_wall_ms, "launch": "one wt_build per sequence on one stream"},
+        "speedup_vs_per_seq": per_seq_ms / batch_ms, "bit_exact_vs_per_seq": identical,
+        "model_bytes": model, "model_gbs": model / (batch_ms / 1e3) / 1e9,
+        "model_frac_of_hbm_peak": model / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +202,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the sequence length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -162,6 +275,8 @@ def main():
         log(f"[bench] cpu baseline: oracle on {sample} symbols")
         cpu = cpu_baseline(S, sigma, L, sample)
 
+    batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
+
     line = {
         "metric": METRIC, "value": value, "unit": "symbols*levels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -171,6 +286,7 @@ def main():
                    "input_sha256": inputs.sha256(S)[:16]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

@@ -78,6 +78,7 @@ struct Args {
     uint32_t lo, hi;         // item range of this launch
     uint32_t chunk;          // items taken per queue access
     uint32_t spin_limit;
+    uint32_t fenced;         // items of one launch depend on each other's writes
 };
 
 struct LdsHistB {
@@ -112,17 +113,32 @@ __device__ __forceinline__ uint32_t ld_u32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Cross-block hand-off.  A barrier orders nothing in memory beyond the
-// workgroup (it does not even wait for the other waves' stores to leave),
-// so every wave releases its own writes at agent scope before the barrier
-// that precedes the signalling atomic, and every wave acquires after the
-// barrier that follows a successful wait.
-__device__ __forceinline__ void block_release() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Cross-block hand-off.
+//   One launch per phase: an item only reads what earlier launches wrote
+//   (kernel boundaries order it), except the count-ahead totals that the
+//   last tile of a level scans.  Those are atomics, performed where every
+//   XCD sees them; each wave waits for its own to complete before the block
+//   counts itself done, and the last block reads them with atomic loads.
+//   So no cache maintenance is needed.
+//   One persistent launch: items read other items' plain stores, which may
+//   sit dirty in another XCD's L2.  A barrier orders nothing beyond the
+//   workgroup (it does not even wait for the other waves' stores), so every
+//   wave releases its own writes at agent scope (L2 write-back) before the
+//   barrier that precedes the signalling atomic, and every wave acquires
+//   after the barrier that follows a successful wait.
+__device__ __forceinline__ void wait_own_stores() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt left free
+}
+
+__device__ __forceinline__ void block_release(bool fenced) {
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    else wait_own_stores();
     __syncthreads();
 }
 
-__device__ __forceinline__ void block_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void block_acquire(bool fenced) {
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
 
 // The block waits until *p >= target (thread 0 polls), then acquires.
 __device__ __forceinline__ void wait_for(const Args &b, const uint32_t *p, uint32_t target, uint32_t *status) {
@@ -139,23 +155,23 @@ __device__ __forceinline__ void wait_for(const Args &b, const uint32_t *p, uint3
         }
     }
     __syncthreads();
-    block_acquire();
+    block_acquire(b.fenced);
 }
 
 // Counts one finished item of a segment (after releasing the block's
 // writes); true in every thread of the block that finished the last one,
 // which has then acquired the other items' writes.
-__device__ __forceinline__ bool finish_item(uint32_t *done, uint32_t count, uint32_t *s_flag) {
-    block_release();
+__device__ __forceinline__ bool finish_item(const Args &b, uint32_t *done, uint32_t count, uint32_t *s_flag) {
+    block_release(b.fenced);
     if (threadIdx.x == 0) *s_flag = atomicAdd(done, 1u) == count - 1 ? 1u : 0u;
     __syncthreads();
     const bool last = *s_flag != 0;
-    if (last) block_acquire();
+    if (last) block_acquire(b.fenced);
     return last;
 }
 
-__device__ __forceinline__ void publish(uint32_t *flag) {
-    block_release();
+__device__ __forceinline__ void publish(const Args &b, uint32_t *flag) {
+    block_release(b.fenced);
     if (threadIdx.x == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -182,8 +198,7 @@ __device__ __forceinline__ void prep_item(const JobDev &j, BlockScanTmp &tmp) {
         j.sigma, tmp, [&](uint64_t g) -> uint64_t { return j.symcnt[g]; },
         [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
     if (threadIdx.x == 0) j.C[j.sigma] = total;
-    __threadfence();
-    __syncthreads();
+    __syncthreads();  // the block reads C back below (workgroup scope)
     if (j.L == 0) return;
     const TableOp top{j.C, j.D, j.sigma, j.L};
     for (uint32_t l = 0; l < j.L; ++l) {
@@ -192,7 +207,6 @@ __device__ __forceinline__ void prep_item(const JobDev &j, BlockScanTmp &tmp) {
             g0, tmp, [&](uint64_t i) -> uint64_t { return top.value(g0 + i); },
             [&](uint64_t i, uint64_t ex) { top.store(g0 + i, ex); });
     }
-    __threadfence();
     __syncthreads();
     for (uint32_t l = 0; l < j.L; ++l)
         dir_tail(l, j.D[(1ull << (l + 2)) - 3], j.n, j.L, j.rank, j.rank_len, j.sel1, j.sel0, j.cap, j.sel_counts,
@@ -244,18 +258,18 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LdsBatch &s
         if (j.in_bytes == 1) hist_item<uint8_t>(j, tile, s.hist);
         else if (j.in_bytes == 2) hist_item<uint16_t>(j, tile, s.hist);
         else hist_item<uint32_t>(j, tile, s.hist);
-        finish_item(ctl + kCtlDone, count, s_flag);
+        finish_item(b, ctl + kCtlDone, count, s_flag);
     } else if (kind == kKindPrep) {
         wait_for(b, ctl + kCtlDone, j.T0, ctl + kCtlStatus);
         prep_item(j, s.scan);
-        publish(ctl + kCtlReady);
+        publish(b, ctl + kCtlReady);
     } else {
         const uint32_t l = kind - kKindLevel;
         wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
         level_item(j, l, tile, s);
-        if (finish_item(ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
+        if (finish_item(b, ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
             tile_prefix_block(j.cnt + (uint64_t)(l + 1) * j.Tpad, j.pre + (uint64_t)(l + 1) * j.Tpad, j.Tm, s.scan);
-            publish(ctl + kCtlReady + 1 + l);
+            publish(b, ctl + kCtlReady + 1 + l);
         }
     }
 }
@@ -516,6 +530,7 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
     a.abort = (uint32_t *)sc + kAbortWord;
     a.chunk = chunk;
     a.spin_limit = spin;
+    a.fenced = t.mode == WT_BATCH_PERSISTENT ? 1u : 0u;
     auto launch = [&](uint32_t phase, uint32_t lo, uint32_t hi) {
         if (hi <= lo) return;
         a.head = (uint32_t *)sc + phase;

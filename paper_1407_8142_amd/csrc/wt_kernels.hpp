@@ -742,10 +742,13 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
 }
 
 // Exclusive prefix of per-tile zero counts by one block: pre[t] =
-// cnt[0] + ... + cnt[t-1] for t < T.
+// cnt[0] + ... + cnt[t-1] for t < T.  The counts were summed by atomics of
+// other blocks, so they are read with agent-scope atomic loads.
 __device__ __forceinline__ void tile_prefix_block(const uint32_t *cnt, uint64_t *pre, uint64_t T, BlockScanTmp &tmp) {
     block_scan_all<4>(
-        T, tmp, [&](uint64_t g) -> uint64_t { return cnt[g]; }, [&](uint64_t g, uint64_t ex) { pre[g] = ex; });
+        T, tmp,
+        [&](uint64_t g) -> uint64_t { return __hip_atomic_load(cnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
+        [&](uint64_t g, uint64_t ex) { pre[g] = ex; });
 }
 
 }  // namespace wt

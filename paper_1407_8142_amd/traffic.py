@@ -24,7 +24,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 PROBE = os.path.join(HERE, "bw_probe")
-LEVEL_PASS_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("wt_build.hip", "wt_device.hpp")]
+LEVEL_PASS_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp")]
 PROBE_MIB = 1024
 
 
@@ -61,7 +61,7 @@ def main():
     os.makedirs(args.out, exist_ok=True)
     probe_cmd = [PROBE, str(PROBE_MIB), "3"]
     bench_cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps", "2",
-                 "--warmup", "1", "--no-cpu-baseline"]
+                 "--warmup", "1", "--no-cpu-baseline", "--no-batch"]
     known = PROBE_MIB * 1024.0  # KiB read and written by one copy launch
     cf = run_pass("FETCH_SIZE", probe_cmd, args.out, "copy_fetch")
     cw = run_pass("WRITE_SIZE", probe_cmd, args.out, "copy_write")
