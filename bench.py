@@ -10,8 +10,14 @@ wt_batch_run (autotuned launch, replayed as a captured graph) against one
 wt_build per sequence on the same GPU, with the two outputs compared bit
 for bit.
 
+A "serve" object reports the serving loop on a Poisson trace (2000 build
+requests/s, n log-uniform in [2^12, 2^26], sigma log-uniform in [4, 2^20],
+Zipf(1.1) symbols; 100 query batches/s of 10^5 access/rank queries over
+the resident trees; 64 GB resident budget with LRU eviction): p50/p99
+build and query-batch latency beside throughput.
+
   python bench.py [--steps K] [--warmup W] [--workload text256|uniform256|alpha16|alpha20]
-                  [--no-cpu-baseline] [--no-batch] [--batch-count N]
+                  [--no-cpu-baseline] [--no-batch] [--batch-count N] [--no-serve] [--serve-seconds S]
 """
 from __future__ import annotations
 
@@ -193,6 +199,42 @@ def batch_leg(count: int, steps: int):
     }
 
 
+def serve_leg(seconds: float, budget_gb: float):
+    """Serving loop on a Poisson trace (payloads staged in HBM first)."""
+    import torch
+
+    from paper_1407_8142_amd import inputs, serve
+
+    def one(sec, index, max_requests=None):
+        reqs, qtimes = inputs.serving_arrivals(sec, index=index, max_requests=max_requests)
+        log(f"[serve] staging {len(reqs)} requests ({sum(r.n for r in reqs) / 1e9:.2f} G symbols), "
+            f"{len(qtimes)} query batches")
+        slab, layout, views = inputs.stage_requests(reqs)
+        torch.cuda.synchronize()
+        srv = serve.Server(budget_bytes=int(budget_gb * 2**30))
+        t0 = time.perf_counter()
+        stats = serve.run_trace(srv, reqs, views, qtimes, slab, layout, qsize=100_000, seed=index)
+        elapsed = time.perf_counter() - t0
+        out = serve.summary(stats, elapsed)
+        out["requests"] = len(reqs)
+        out["offered_symbols_levels"] = sum(r.n * (0 if r.sigma == 1 else (r.sigma - 1).bit_length()) for r in reqs)
+        del srv, slab, views
+        torch.cuda.empty_cache()
+        return out
+
+    one(0.05, 1, max_requests=60)  # warm-up: kernel loading, allocator growth
+    res = one(seconds, 0)
+    log(f"[serve] {res['builds']} builds in {res['elapsed_s']:.2f} s, build p50/p99 "
+        f"{res['build_latency_ms']['p50']}/{res['build_latency_ms']['p99']} ms, query batch p50/p99 "
+        f"{res['query_batch_latency_ms']['p50']}/{res['query_batch_latency_ms']['p99']} ms")
+    res["config"] = {"workload": "serving: Poisson build requests at 2000/s, n log-uniform in [2^12, 2^26], sigma "
+                                 "log-uniform in [2^2, 2^20], Zipf(1.1) symbols permuted; Poisson query batches at "
+                                 "100/s of 10^5 queries (half access, half rank with c = S[j]) over the resident "
+                                 f"trees; {budget_gb:g} GB resident budget, LRU eviction",
+                     "trace_seconds": seconds, "h2d": "excluded: payloads staged in HBM before their arrival"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +247,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=0.5)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -276,6 +321,7 @@ def main():
         cpu = cpu_baseline(S, sigma, L, sample)
 
     batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
+    served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb)
 
     line = {
         "metric": METRIC, "value": value, "unit": "symbols*levels/s", "n_gpus": 1, "steps": args.steps,
@@ -287,6 +333,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batch": batch,
+        "serve": served,
     }
     print(json.dumps(line), flush=True)
 

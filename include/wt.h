@@ -211,6 +211,22 @@ int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, void *d_scratc
  * WT_ERR_TIMEOUT if any job timed out, else the first error, else WT_OK. */
 int wt_batch_status(const wt_batch_layout *lay, const void *d_scratch, int32_t *codes, void *stream);
 
+/* Mixed queries over many built trees in one launch (the serving path:
+ * a batch of queries spread over the resident trees).
+ *   d_views: device array of ntrees wt_view (each as for wt_access).
+ *   query j: tree d_tree[j], kind d_kind[j], arguments (d_a[j], d_b[j]):
+ *     WT_Q_ACCESS  a = i            -> S[i], or 0xFFFFFFFF when i >= n
+ *     WT_Q_RANK    a = c, b = i     -> occurrences of c in S[0, min(i, n)); 0 when c >= sigma
+ *     WT_Q_SELECT  a = c, b = k     -> position of the k-th (1-based) c, or -1
+ *   d_out[j] (int64): the answer, or WT_Q_BAD for a tree index >= ntrees, a
+ *   view without C, or an unknown kind. */
+#define WT_Q_ACCESS 0
+#define WT_Q_RANK 1
+#define WT_Q_SELECT 2
+#define WT_Q_BAD (-2)
+int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tree, const uint8_t *d_kind,
+                   const uint64_t *d_a, const uint64_t *d_b, uint64_t m, int64_t *d_out, void *stream);
+
 /* Look-back tuning and testing hook.  Tiles of a level pass find their
  * prefix by looking back at earlier tiles; a tile whose predecessor has not
  * published after `polls` polls reduces that predecessor's input itself

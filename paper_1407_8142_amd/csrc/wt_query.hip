@@ -62,14 +62,8 @@ __device__ uint64_t select_b(const TreeDev &t, uint32_t l, uint32_t b, uint64_t 
     return t.n;  // unreachable for a well-formed tree
 }
 
-__global__ void access_kernel(TreeDev t, const uint64_t *qi, uint64_t m, uint32_t *out) {
-    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    uint64_t j = qi[q];
-    if (j >= t.n) {
-        out[q] = 0xFFFFFFFFu;
-        return;
-    }
+// access(j): the symbol at position j (j < n).
+__device__ __forceinline__ uint32_t access_one(const TreeDev &t, uint64_t j) {
     uint64_t p = 0;
     for (uint32_t l = 0; l < t.L; ++l) {
         uint32_t k = t.L - 1 - l;
@@ -81,22 +75,12 @@ __global__ void access_kernel(TreeDev t, const uint64_t *qi, uint64_t m, uint32_
         p = 2 * p + b;
         if (j >= t.n && l + 1 < t.L) break;  // unreachable for a well-formed tree
     }
-    out[q] = (uint32_t)p;
+    return (uint32_t)p;
 }
 
-__global__ void rank_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qi, uint64_t m, uint64_t *out) {
-    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    uint64_t c = qc[q], i = qi[q];
-    if (i > t.n) i = t.n;
-    if (c >= t.sigma) {
-        out[q] = 0;
-        return;
-    }
-    if (t.L == 0) {
-        out[q] = i;
-        return;
-    }
+// rank(c, i): occurrences of c < sigma in S[0, i), i <= n.
+__device__ __forceinline__ uint64_t rank_one(const TreeDev &t, uint64_t c, uint64_t i) {
+    if (t.L == 0) return i;
     uint64_t p = 0, r = i;  // r: elements of node p that precede the query position
     for (uint32_t l = 0; l < t.L; ++l) {
         if (r == 0) break;
@@ -108,17 +92,12 @@ __global__ void rank_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qi, u
         r = b ? ones : r - ones;
         p = 2 * p + b;
     }
-    out[q] = r;
+    return r;
 }
 
-__global__ void select_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qk, uint64_t m, int64_t *out) {
-    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= m) return;
-    uint64_t c = qc[q], kk = qk[q];
-    if (c >= t.sigma || kk == 0 || kk > t.C[c + 1] - t.C[c]) {
-        out[q] = -1;
-        return;
-    }
+// select(c, kk): position of the kk-th (1-based) c, or -1.
+__device__ __forceinline__ int64_t select_one(const TreeDev &t, uint64_t c, uint64_t kk) {
+    if (c >= t.sigma || kk == 0 || kk > t.C[c + 1] - t.C[c]) return -1;
     uint64_t r = kk - 1;  // 0-based index inside the current child
     for (uint32_t d = t.L; d-- > 0;) {
         uint32_t k = t.L - 1 - d;
@@ -126,13 +105,73 @@ __global__ void select_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qk,
         uint32_t b = (uint32_t)((c >> k) & 1u);
         uint64_t a = Cat(t, p << (k + 1));
         uint64_t j = select_b(t, d, b, rank_b(t, d, a, b) + r);
-        if (j >= t.n) {  // unreachable for a well-formed tree
-            out[q] = -1;
-            return;
-        }
+        if (j >= t.n) return -1;  // unreachable for a well-formed tree
         r = j - a;
     }
-    out[q] = (int64_t)r;
+    return (int64_t)r;
+}
+
+__global__ void access_kernel(TreeDev t, const uint64_t *qi, uint64_t m, uint32_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t j = qi[q];
+    out[q] = j >= t.n ? 0xFFFFFFFFu : access_one(t, j);
+}
+
+__global__ void rank_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qi, uint64_t m, uint64_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t c = qc[q], i = min(qi[q], t.n);
+    out[q] = c >= t.sigma ? 0 : rank_one(t, c, i);
+}
+
+__global__ void select_kernel(TreeDev t, const uint32_t *qc, const uint64_t *qk, uint64_t m, int64_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    out[q] = select_one(t, qc[q], qk[q]);
+}
+
+__device__ __forceinline__ bool tree_of(const wt_view &v, TreeDev &t) {
+    t.bits = v.bits;
+    t.C = v.C;
+    t.rank = v.rank;
+    t.sel1 = v.sel1;
+    t.sel0 = v.sel0;
+    t.sel_counts = v.sel_counts;
+    t.n = v.n;
+    t.sigma = v.sigma;
+    t.L = v.L;
+    t.W = (v.n + 63) / 64;
+    t.rank_len = (v.n + WT_RANK_BLOCK_BITS - 1) / WT_RANK_BLOCK_BITS + 1;
+    t.cap = (v.n + WT_SELECT_SAMPLE - 1) / WT_SELECT_SAMPLE + 1;
+    return v.C != nullptr;
+}
+
+// Mixed queries over many trees: query q names its tree, kind and arguments.
+__global__ void multi_kernel(const wt_view *views, uint32_t ntrees, const uint32_t *qt, const uint8_t *qkind,
+                             const uint64_t *qa, const uint64_t *qb, uint64_t m, int64_t *out) {
+    uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint32_t ti = qt[q];
+    TreeDev t;
+    if (ti >= ntrees || !tree_of(views[ti], t)) {
+        out[q] = WT_Q_BAD;
+        return;
+    }
+    const uint64_t a = qa[q], b = qb[q];
+    switch (qkind[q]) {
+        case WT_Q_ACCESS:
+            out[q] = a >= t.n ? (int64_t)0xFFFFFFFFu : (int64_t)access_one(t, a);
+            break;
+        case WT_Q_RANK:
+            out[q] = a >= t.sigma ? 0 : (int64_t)rank_one(t, a, min(b, t.n));
+            break;
+        case WT_Q_SELECT:
+            out[q] = select_one(t, a, b);
+            break;
+        default:
+            out[q] = WT_Q_BAD;
+    }
 }
 
 static bool make_tree(const wt_view *v, TreeDev &t) {
@@ -186,5 +225,14 @@ extern "C" int wt_select(const wt_view *v, const uint32_t *d_c, const uint64_t *
     if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
     select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_k, m,
                                                                                                  d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tree, const uint8_t *d_kind,
+                              const uint64_t *d_a, const uint64_t *d_b, uint64_t m, int64_t *d_out, void *stream) {
+    if (m == 0) return WT_OK;
+    if (!d_views || !d_tree || !d_kind || !d_a || !d_b || !d_out) return WT_ERR_ARG;
+    multi_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
+        d_views, ntrees, d_tree, d_kind, d_a, d_b, m, d_out);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }

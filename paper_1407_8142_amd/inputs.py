@@ -155,3 +155,83 @@ def workload(cfg: str, n: int | None = None):
     if cfg == "alpha20":
         return large_alphabet(n or (1 << 27), 1 << 20), 1 << 20
     raise KeyError(cfg)
+
+
+# ---------------------------------------------------------------------------
+# Serving trace.  Request payloads are generated on the device (the host
+# cannot produce ~10^10 symbols per second of trace), from per-request seeds
+# drawn by the host generator: Zipf(s) over sigma ranks by inverse CDF on
+# the float64 cumulative table, ranks mapped to symbols by a seeded
+# permutation -- the same recipe as zipf_symbols, with torch's generator.
+@dataclass
+class TraceRequest:
+    arrival_s: float
+    n: int
+    sigma: int
+    seed: int
+
+
+def serving_arrivals(seconds: float, rate: float = 2000.0, qrate: float = 100.0, n_exp=(12.0, 26.0),
+                     sigma_exp=(2.0, 20.0), index: int = 0, max_requests: int | None = None):
+    """Poisson build arrivals (mean rate/s) with n = floor(2^U(n_exp)) and
+    sigma = floor(2^U(sigma_exp)), and Poisson query-batch arrivals."""
+    rng = rng_for(5, index)
+    reqs, t = [], 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t > seconds or (max_requests is not None and len(reqs) >= max_requests):
+            break
+        n = int(np.floor(2.0 ** rng.uniform(*n_exp)))
+        sigma = max(2, int(np.floor(2.0 ** rng.uniform(*sigma_exp))))
+        reqs.append(TraceRequest(t, n, sigma, int(rng.integers(0, 2**62))))
+    qt, t = [], 0.0
+    horizon = reqs[-1].arrival_s if reqs else seconds
+    while qrate > 0:
+        t += float(rng.exponential(1.0 / qrate))
+        if t > horizon:
+            break
+        qt.append(t)
+    return reqs, qt
+
+
+def zipf_device(n: int, sigma: int, s: float, seed: int, out, device="cuda"):
+    """Fill `out` (n symbols of the width of `out`'s dtype, a device tensor)
+    with Zipf(s) symbols over sigma ranks, permuted, from `seed`."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    w = torch.arange(1, sigma + 1, dtype=torch.float64, device=device).pow_(-s)
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    perm = torch.randperm(sigma, generator=g, device=device)
+    step = 1 << 24
+    for o in range(0, n, step):
+        m = min(step, n - o)
+        u = torch.rand(m, dtype=torch.float64, generator=g, device=device)
+        r = torch.searchsorted(cdf, u).clamp_(max=sigma - 1)
+        v = perm[r]
+        esz = out.element_size()
+        if esz == 1:
+            out[o:o + m] = v.to(torch.uint8).view(out.dtype)
+        elif esz == 2:
+            out[o:o + m] = v.to(torch.int32).view(torch.int16)[::2].view(out.dtype)
+        else:
+            out[o:o + m] = v.to(torch.int32).view(out.dtype)
+
+
+def stage_requests(reqs, s: float = 1.1, device="cuda"):
+    """All request payloads in one device slab (each 256-byte aligned).
+    Returns (slab, [(offset, width)], [tensor view per request])."""
+    import torch
+    widths = [int(np.dtype(dtype_for_sigma(r.sigma)).itemsize) for r in reqs]
+    offs, total = [], 0
+    for r, w in zip(reqs, widths):
+        offs.append(total)
+        total += -(-(r.n * w) // 256) * 256
+    slab = torch.empty(max(total, 256), dtype=torch.uint8, device=device)
+    views = []
+    for r, w, o in zip(reqs, widths, offs):
+        v = slab[o:o + r.n * w].view({1: torch.uint8, 2: torch.int16, 4: torch.int32}[w])
+        zipf_device(r.n, r.sigma, s, r.seed, v, device)
+        views.append(v)
+    return slab, list(zip(offs, widths)), views

@@ -25,7 +25,8 @@ SELECT_SAMPLE = 4096
 
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
-           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status"]
+           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi"]
+Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
 class WTError(RuntimeError):
@@ -100,9 +101,10 @@ def lib() -> ctypes.CDLL:
         L.wt_batch_prepare.argtypes = [ctypes.POINTER(Job), u32, ctypes.POINTER(BatchLayout), vp, u64, vp]
         L.wt_batch_run.argtypes = [ctypes.POINTER(BatchLayout), ctypes.POINTER(Tune), vp, vp]
         L.wt_batch_status.argtypes = [ctypes.POINTER(BatchLayout), vp, ctypes.POINTER(ctypes.c_int32), vp]
+        L.wt_query_multi.argtypes = [vp, u32, vp, vp, vp, vp, u64, vp, vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
-                  "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status"):
+                  "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -301,6 +303,26 @@ class Batch:
         codes = (ctypes.c_int32 * max(self.njobs, 1))()
         rc = lib().wt_batch_status(ctypes.byref(self.layout), _ptr(self.scratch), codes, _stream(stream))
         return int(rc), [int(codes[i]) for i in range(self.njobs)]
+
+
+def views_tensor(trees: list, device="cuda") -> torch.Tensor:
+    """Device array of wt_view for `trees` (a uint8 tensor holding the structs)."""
+    arr = (View * max(len(trees), 1))(*[t.view() for t in trees])
+    host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+    return host.to(device)
+
+
+def query_multi(views: torch.Tensor, ntrees: int, tree: torch.Tensor, kind: torch.Tensor, a: torch.Tensor,
+                b: torch.Tensor, stream=None) -> torch.Tensor:
+    """Mixed access/rank/select over many trees (wt_query_multi); int64 answers."""
+    tree = tree.to(torch.int32).contiguous()
+    kind = kind.to(torch.uint8).contiguous()
+    a = a.to(torch.int64).contiguous()
+    b = b.to(torch.int64).contiguous()
+    out = torch.empty(tree.numel(), dtype=torch.int64, device=tree.device)
+    _check(lib().wt_query_multi(_ptr(views), ntrees, _ptr(tree), _ptr(kind), _ptr(a), _ptr(b), tree.numel(),
+                                _ptr(out), _stream(stream)), "wt_query_multi")
+    return out
 
 
 def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:

@@ -238,3 +238,48 @@ def test_random_ragged_sweep(wtmod, oracle_mod):
         S = rng.integers(0, sigma, n, dtype=np.uint64).astype(inputs.dtype_for_sigma(sigma))
         t = gpu_build(wtmod, S, sigma)
         assert_same(t.to_numpy(), oracle_mod.build_all(S, sigma), ctx=f"sweep n={n} sigma={sigma}")
+
+
+def test_query_multi_matches_single_tree_queries(wtmod):
+    """wt_query_multi over several trees answers exactly what the one-tree
+    kernels answer; a tree index out of range or an unknown kind gives
+    WT_Q_BAD."""
+    rng = np.random.default_rng(31)
+    trees, seqs = [], []
+    for n, sigma in [(1, 1), (5000, 3), (70000, 256), (20000, 1 << 16), (3000, (1 << 20) + 5), (0, 7)]:
+        S = rng.integers(0, sigma, n).astype(inputs.dtype_for_sigma(sigma))
+        trees.append(gpu_build(wtmod, S, sigma))
+        seqs.append(S)
+    views = wtmod.views_tensor(trees)
+    m = 20000
+    tix = rng.integers(0, len(trees) + 1, m)  # includes one bad index
+    kind = rng.integers(0, 4, m)              # includes one bad kind
+    a = np.zeros(m, np.int64)
+    b = np.zeros(m, np.int64)
+    for q in range(m):
+        if tix[q] >= len(trees):
+            continue
+        S, n = seqs[tix[q]], seqs[tix[q]].size
+        sig = trees[tix[q]].sigma
+        if kind[q] == 0:
+            a[q] = rng.integers(0, n + 2)
+        else:
+            a[q] = S[rng.integers(0, n)] if n and rng.random() < 0.8 else rng.integers(0, sig + 3)
+            b[q] = rng.integers(0, n + 2) if kind[q] == 1 else rng.integers(0, 12)
+    d = lambda x, dt: torch.from_numpy(x.astype(dt)).cuda()
+    got = wtmod.query_multi(views, len(trees), d(tix, np.int32), d(kind, np.uint8), d(a, np.int64), d(b, np.int64))
+    got = got.cpu().numpy()
+    for ti, t in enumerate(trees):
+        for kd in (0, 1, 2):
+            sel = np.flatnonzero((tix == ti) & (kind == kd))
+            if sel.size == 0:
+                continue
+            if kd == 0:
+                want = t.access(d(a[sel], np.int64)).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+            elif kd == 1:
+                want = t.rank_query(d(a[sel], np.int32), d(b[sel], np.int64)).cpu().numpy()
+            else:
+                want = t.select_query(d(a[sel], np.int32), d(b[sel], np.int64)).cpu().numpy()
+            assert np.array_equal(got[sel], want), (ti, kd)
+    bad = (tix >= len(trees)) | (kind == 3)
+    assert np.all(got[bad] == wtmod.Q_BAD)
