@@ -189,8 +189,8 @@ typedef struct {
     uint32_t njobs;
     uint32_t nsegs;           /* queue segments: (job, phase) pairs with work */
     uint32_t items;           /* work items in the queue */
-    uint32_t phases;          /* 2 + the most levels of any job with n > 0 */
-    uint32_t phase_first[33]; /* first item of each phase; phase_first[phases] = items */
+    uint32_t phases;          /* histograms, tables, one per level of the deepest job, fused tail levels */
+    uint32_t phase_first[40]; /* first item of each phase; phase_first[phases] = items */
 } wt_batch_layout;
 
 /* Host only.  WT_ERR_ARG / WT_ERR_RANGE as wt_plan (and n >= 2^32). */
@@ -226,6 +226,13 @@ int wt_batch_status(const wt_batch_layout *lay, const void *d_scratch, int32_t *
 #define WT_Q_BAD (-2)
 int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tree, const uint8_t *d_kind,
                    const uint64_t *d_a, const uint64_t *d_b, uint64_t m, int64_t *d_out, void *stream);
+
+/* Fused tail levels (on by default).  Once every node of a level fits in one
+ * block's LDS, wt_build and wt_batch_run run that level and all deeper ones
+ * in LDS, one node-aligned segment per block (no sequence traffic for those
+ * levels); outputs are identical either way.  0 turns it off for later
+ * launches (for comparisons). */
+int wt_set_fused_levels(int enable);
 
 /* Look-back tuning and testing hook.  Tiles of a level pass find their
  * prefix by looking back at earlier tiles; a tile whose predecessor has not

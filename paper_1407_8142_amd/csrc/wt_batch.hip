@@ -44,11 +44,13 @@ constexpr uint32_t kStatusTimeout = 4u;
 constexpr uint32_t kHistH = 2048;                         // hash slots of the batched histogram
 constexpr uint32_t kHistWords = HistHash<kHistH>::kWords;  // LDS words of its table (replicas or hash)
 constexpr uint32_t kKindHist = 0, kKindPrep = 1, kKindLevel = 2;  // level l is kind 2 + l
+constexpr uint32_t kKindFused = 64;                                 // a segment of the fused tail levels
+constexpr int kFusedBytes = 8192;                                   // per LDS buffer of a fused segment
 
 // Control words of one job (cleared by every run): status, done counters
 // (histogram, then one per level), ready flags (one per level).
 constexpr int kCtlWords = 64;
-constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32;
+constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32, kCtlFusedL0 = 63;
 constexpr int kMaxLevels = 30;
 constexpr uint64_t kHeaderBytes = 256;  // queue heads [0, 32), abort flag [32]
 constexpr int kAbortWord = 32;
@@ -79,6 +81,7 @@ struct Args {
     uint32_t chunk;          // items taken per queue access
     uint32_t spin_limit;
     uint32_t fenced;         // items of one launch depend on each other's writes
+    uint32_t fuse;           // run the tail levels of a job fused in LDS once its nodes fit
 };
 
 struct LdsHistB {
@@ -87,12 +90,21 @@ struct LdsHistB {
     uint32_t nused;
 };
 
+struct LdsPrep {
+    BlockScanTmp scan;
+    unsigned long long nmax[32];
+};
+
 union LdsBatch {
     LdsLevelU8 u8;
     LdsLevel<uint16_t> g16;
     LdsLevel<uint32_t> g32;
     LdsHistB hist;
     BlockScanTmp scan;
+    LdsPrep prep;
+    LdsFused<uint8_t, kFusedBytes> f8;
+    LdsFused<uint16_t, kFusedBytes> f16;
+    LdsFused<uint32_t, kFusedBytes> f32;
 };
 
 // A job or segment record: constant while the kernel runs and uniform
@@ -192,8 +204,15 @@ __device__ __forceinline__ void hist_item(const JobDev &j, uint32_t tile, LdsHis
     }
 }
 
-// C, node tables, directory tails and level-0 tile prefixes of one job.
-__device__ __forceinline__ void prep_item(const JobDev &j, BlockScanTmp &tmp) {
+__host__ __device__ inline uint64_t fused_half(uint32_t mid) {
+    return mid == 1 ? FusedCfg<uint8_t, kFusedBytes>::kHalf
+                    : (mid == 2 ? FusedCfg<uint16_t, kFusedBytes>::kHalf : FusedCfg<uint32_t, kFusedBytes>::kHalf);
+}
+
+// C, node tables, directory tails, level-0 tile prefixes and the first
+// fused level of one job.
+__device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fuse) {
+    BlockScanTmp &tmp = lp.scan;
     const uint64_t total = block_scan_all<4>(
         j.sigma, tmp, [&](uint64_t g) -> uint64_t { return j.symcnt[g]; },
         [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
@@ -212,6 +231,15 @@ __device__ __forceinline__ void prep_item(const JobDev &j, BlockScanTmp &tmp) {
         dir_tail(l, j.D[(1ull << (l + 2)) - 3], j.n, j.L, j.rank, j.rank_len, j.sel1, j.sel0, j.cap, j.sel_counts,
                  threadIdx.x, kBlock);
     tile_prefix_block(j.cnt, j.pre, j.T0, tmp);
+    uint32_t l0 = j.L;
+    if (fuse && j.L >= 2 && j.n > 0) {
+        if (threadIdx.x < 32) lp.nmax[threadIdx.x] = 0;
+        __syncthreads();
+        node_max_range(j.C, j.sigma, j.L, 1, 1ull << j.L, kBlock, lp.nmax, nullptr);
+        __syncthreads();
+        l0 = fused_from(reinterpret_cast<const uint64_t *>(lp.nmax), j.L, fused_half(j.mid_bytes));
+    }
+    if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
 }
 
 __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LdsBatch &s) {
@@ -232,6 +260,8 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
     a.sel0 = j.sel0 + (uint64_t)l * j.cap;
     a.n = j.n;
     a.k = j.L - 1 - l;
+    a.level = l;
+    a.fused_l0 = j.ctl + kCtlFusedL0;
     if (scatter) {
         if (win == 1) level_tile_u8<true, true>(a, tile, s.u8);
         else if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
@@ -261,8 +291,42 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LdsBatch &s
         finish_item(b, ctl + kCtlDone, count, s_flag);
     } else if (kind == kKindPrep) {
         wait_for(b, ctl + kCtlDone, j.T0, ctl + kCtlStatus);
-        prep_item(j, s.scan);
+        prep_item(j, s.prep, b.fuse != 0);
         publish(b, ctl + kCtlReady);
+    } else if (kind == kKindFused) {
+        wait_for(b, ctl + kCtlReady, 1u, ctl + kCtlStatus);  // tables and the fused level are known
+        const uint32_t l0 = ld_u32(ctl + kCtlFusedL0);
+        if (l0 >= j.L) return;
+        if (l0 > 0) wait_for(b, ctl + kCtlReady + l0, 1u, ctl + kCtlStatus);
+        FusedArgs f;
+        f.in0 = j.seq;
+        f.S0 = j.S0;
+        f.S1 = j.S1;
+        f.C = j.C;
+        f.D = j.D;
+        f.sigma = j.sigma;
+        f.n = j.n;
+        f.L = j.L;
+        f.bits = j.bits;
+        f.W = j.W;
+        f.rank = j.rank;
+        f.rank_len = j.rank_len;
+        f.sel1 = j.sel1;
+        f.sel0 = j.sel0;
+        f.cap = j.cap;
+        f.status = ctl + kCtlStatus;
+        f.l0 = ctl + kCtlFusedL0;
+        const uint32_t wi = j.in_bytes, wm = j.mid_bytes;
+        if (wm == 1) {
+            if (wi == 1) fused_segment<uint8_t, uint8_t, kFusedBytes>(f, tile, s.f8);
+            else if (wi == 2) fused_segment<uint16_t, uint8_t, kFusedBytes>(f, tile, s.f8);
+            else fused_segment<uint32_t, uint8_t, kFusedBytes>(f, tile, s.f8);
+        } else if (wm == 2) {
+            if (wi == 2) fused_segment<uint16_t, uint16_t, kFusedBytes>(f, tile, s.f16);
+            else fused_segment<uint32_t, uint16_t, kFusedBytes>(f, tile, s.f16);
+        } else {
+            fused_segment<uint32_t, uint32_t, kFusedBytes>(f, tile, s.f32);
+        }
     } else {
         const uint32_t l = kind - kKindLevel;
         wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
@@ -377,6 +441,12 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
         }
         if (items >= (1ull << 31)) return WT_ERR_RANGE;
     }
+    hp.phase_first.push_back((uint32_t)items);
+    for (uint32_t i = 0; i < njobs; ++i) {  // fused tail levels: one item per segment
+        const HostJob &h = hp.jobs[i];
+        if (h.n > 0 && h.L >= 2) add(i, kKindFused, (uint32_t)cdiv(h.n, fused_half(h.mid_bytes)));
+    }
+    if (items >= (1ull << 31)) return WT_ERR_RANGE;
     hp.phase_first.push_back((uint32_t)items);
     hp.items = items;
     o = align_up(o, 256);
@@ -531,6 +601,7 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
     a.chunk = chunk;
     a.spin_limit = spin;
     a.fenced = t.mode == WT_BATCH_PERSISTENT ? 1u : 0u;
+    a.fuse = fused_levels_enabled() ? 1u : 0u;
     auto launch = [&](uint32_t phase, uint32_t lo, uint32_t hi) {
         if (hi <= lo) return;
         a.head = (uint32_t *)sc + phase;

@@ -232,6 +232,34 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
 
 
 // ---------------------------------------------------------------------------
+// Fused tail levels (see fused_segment): the largest node of every level,
+// the first fused level, and the fused pass itself (segments strided over a
+// grid that exits at once when no level is fused).
+constexpr int kFusedBytes = 16384;
+
+__global__ __launch_bounds__(kBlock) void node_max_kernel(const uint64_t *C, uint64_t sigma, uint32_t L,
+                                                          unsigned long long *maxnode) {
+    __shared__ unsigned long long red[32];
+    if (threadIdx.x < 32) red[threadIdx.x] = 0;
+    __syncthreads();
+    node_max_range(C, sigma, L, 1 + (uint64_t)blockIdx.x * kBlock, 1ull << L, (uint64_t)gridDim.x * kBlock, red,
+                   maxnode);
+}
+
+__global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, uint64_t half, uint32_t *l0) {
+    if (threadIdx.x == 0) *l0 = fused_from(reinterpret_cast<const uint64_t *>(maxnode), L, half);
+}
+
+template <typename TIN0, typename T>
+__global__ __launch_bounds__(kBlock) void fused_pass(FusedArgs f, uint64_t nseg) {
+    __shared__ LdsFused<T, kFusedBytes> s;
+    for (uint64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+        fused_segment<TIN0, T, kFusedBytes>(f, seg, s);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Directory tails of every level (grid.y = level).  The level totals come
 // either from the node tables (zeros of a level = D_l's last entry) or from
 // an array of per-level totals.
@@ -337,7 +365,12 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
 }
 
 static bool g_timing = false;
+static bool g_fuse = true;
 static int g_spin_limit = 8;
+constexpr uint64_t kOffMaxNode = 8;   // in the status block: largest node per level (u64 x 30)
+constexpr uint64_t kOffFusedL0 = 248; // in the status block: first fused level (u32)
+
+
 static std::mutex g_timing_mu;
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;  // recorded, not yet collected
 static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_free;
@@ -408,6 +441,33 @@ static int num_cus() {
             cus = 256;
     }
     return cus;
+}
+
+template <typename TIN0, typename T>
+static void launch_fused_t(const FusedArgs &f, uint64_t n, hipStream_t s) {
+    const uint64_t nseg = cdiv(n, FusedCfg<T, kFusedBytes>::kHalf);
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(nseg, (uint64_t)num_cus() * 4));
+    fused_pass<TIN0, T><<<(unsigned)grid, kBlock, 0, s>>>(f, nseg);
+}
+
+static uint64_t fused_half(uint32_t mid) {
+    return mid == 1 ? FusedCfg<uint8_t, kFusedBytes>::kHalf
+                    : (mid == 2 ? FusedCfg<uint16_t, kFusedBytes>::kHalf : FusedCfg<uint32_t, kFusedBytes>::kHalf);
+}
+
+static void launch_fused(uint32_t in_w, uint32_t mid, const FusedArgs &f, uint64_t n, hipStream_t s) {
+#define WT_FU(I, O)                                \
+    if (in_w == sizeof(I) && mid == sizeof(O)) {   \
+        launch_fused_t<I, O>(f, n, s);             \
+        return;                                    \
+    }
+    WT_FU(uint8_t, uint8_t)
+    WT_FU(uint16_t, uint8_t)
+    WT_FU(uint32_t, uint8_t)
+    WT_FU(uint16_t, uint16_t)
+    WT_FU(uint32_t, uint16_t)
+    WT_FU(uint32_t, uint32_t)
+#undef WT_FU
 }
 
 template <typename T>
@@ -512,6 +572,16 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
                                             out->sel_counts);
         }
     }
+    // Fused tail levels need the directories (they write their entries) and
+    // at least one split to save.
+    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0;
+    uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
+    if (fuse) {
+        unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
+        const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << p.L, kBlock), 2048));
+        node_max_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(out->C, sigma, p.L, maxnode);
+        fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), fused_l0);
+    }
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     if (n == 0 || p.L == 0) return WT_OK;
 
@@ -538,6 +608,8 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
         a.n = n;
         a.k = p.L - 1 - l;
+        a.level = l;
+        a.fused_l0 = fuse ? fused_l0 : nullptr;
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (g_timing && (rc = timing_begin(s, ev))) return rc;
         launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);
@@ -545,6 +617,28 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
         cur = dst;
         cur_w = p.mid_bytes;
+    }
+    if (fuse) {
+        FusedArgs f;
+        f.in0 = d_seq;
+        f.S0 = sc + p.off_S0;
+        f.S1 = sc + p.off_S1;
+        f.C = out->C;
+        f.D = D;
+        f.sigma = sigma;
+        f.n = n;
+        f.L = p.L;
+        f.bits = out->bits;
+        f.W = p.W;
+        f.rank = out->rank;
+        f.rank_len = p.rank_len;
+        f.sel1 = out->sel1;
+        f.sel0 = out->sel0;
+        f.cap = p.cap;
+        f.status = status;
+        f.l0 = fused_l0;
+        launch_fused(p.in_bytes, p.mid_bytes, f, n, s);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     }
     return WT_OK;
 }
@@ -583,6 +677,13 @@ extern "C" int wt_status_get(const void *d_scratch, void *stream) {
         return WT_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return WT_ERR_HIP;
     return st == 0 ? WT_OK : (st == kStatusSymbol ? WT_ERR_SYMBOL : WT_ERR_HIP);
+}
+
+bool wt::fused_levels_enabled() { return g_fuse; }
+
+extern "C" int wt_set_fused_levels(int enable) {
+    g_fuse = enable != 0;
+    return WT_OK;
 }
 
 extern "C" int wt_set_lookback_spin_limit(int polls) {

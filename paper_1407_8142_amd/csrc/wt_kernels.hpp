@@ -20,6 +20,9 @@ constexpr int kScanChunk = kBlock * kItems;  // elements per block in the generi
 
 constexpr uint32_t kStatusSymbol = 2u;
 
+// Host switch of the fused tail levels (wt_set_fused_levels).
+bool fused_levels_enabled();
+
 __host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline uint64_t align_up(uint64_t a, uint64_t b) { return cdiv(a, b) * b; }
 
@@ -307,6 +310,8 @@ struct LevelArgs {
     uint64_t *rank, *sel1, *sel0;  // directory rows of level l
     uint64_t n;
     uint32_t k;              // bit examined at this level: L-1-l
+    uint32_t level;          // l
+    const uint32_t *fused_l0;  // levels >= *fused_l0 are done by the fused pass (NULL: none)
 };
 
 // Count-ahead: while level l scatters S_{l+1}, it also counts, for every tile
@@ -390,6 +395,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
     constexpr int V = 16 / sizeof(TIN);
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
+    if (a.fused_l0 && a.level >= *a.fused_l0) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint64_t t0 = tile * kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
@@ -485,7 +491,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
             uint32_t zl = s.zpre[r * kWaves + wave] + (uint32_t)__popcll(~w & lt);
             uint32_t slot = ((w >> lane) & 1ull) ? Zt + (e - zl) : zl;
             uint32_t sym = (pk[r / Cfg::kPer] >> (8 * sizeof(TIN) * (r % Cfg::kPer))) &
-                           (sizeof(TIN) == 4 ? 0xFFFFFFFFu : ((1u << (8 * sizeof(TIN))) - 1u));
+                           (uint32_t)((1ull << (8 * sizeof(TIN))) - 1ull);
             stage_out[slot] = (TOUT)sym;
         }
     }
@@ -574,6 +580,7 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     constexpr int kTile = LdsLevelU8::kTile, kRows = LdsLevelU8::kRows, kRowBytes = LdsLevelU8::kRowBytes;
 
     if (*a.status) return;  // uniform across the grid: the input was rejected
+    if (a.fused_l0 && a.level >= *a.fused_l0) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t t0 = tile * (uint32_t)kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
@@ -739,6 +746,226 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     lc.flush(s.ct, a.next_cnt);
     __syncthreads();
     count_flush(s.ct, a.next_cnt, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Fused tail levels: levels l0..L-1 of one node-aligned segment in LDS.
+//
+// Once every node of level l0 holds at most kHalf positions, the positions
+// from the first node boundary of level l0 at or after s*kHalf to the first
+// one at or after (s+1)*kHalf form segment s: at most 2*kHalf positions
+// (consecutive boundaries are at most kHalf apart) and no node of level l0
+// crosses it.  Deeper nodes refine those of level l0, so the segment stays
+// whole at every later level, and each block finds its own bounds by a
+// binary search over C.  One block loads its segment once and runs every
+// remaining level in LDS: the bits and directory entries of each level go
+// to HBM, the stable split goes from one LDS buffer to the other, and no
+// sequence traffic is left for those levels.  Destinations are those of
+// the global pass (the node tables), rebased to the segment; the zeros of a
+// level before the segment are the zeros before its first node, a table
+// entry.  A bit word shared with the neighbouring segment is cleared and
+// set over this segment's bit range only, with atomics (the two ranges are
+// disjoint, so the order of the two segments does not matter).
+template <typename T, int kBytes>
+struct FusedCfg {
+    static constexpr int kCap = kBytes / (int)sizeof(T);  // positions of a segment, at most
+    static constexpr int kHalf = kCap / 2;                // segment stride
+    static constexpr int kVWords = kCap / 64 + 2;         // words a segment touches (its start is not aligned)
+};
+
+template <typename T, int kBytes>
+struct LdsFused {
+    T buf[2][FusedCfg<T, kBytes>::kCap];
+    uint64_t words[FusedCfg<T, kBytes>::kVWords];
+    uint32_t zpre[FusedCfg<T, kBytes>::kVWords];  // zeros of the segment before each word
+    uint32_t red[kWaves];
+};
+
+struct FusedArgs {
+    const void *in0;        // S (level-0 input, TIN0)
+    const void *S0, *S1;    // sequences written by even / odd level passes (T)
+    const uint64_t *C;      // C[0..sigma]
+    const uint64_t *D;      // node tables of every level
+    uint64_t sigma, n;
+    uint32_t L;
+    uint64_t *bits, W;
+    uint64_t *rank, rank_len;
+    uint64_t *sel1, *sel0, cap;
+    const uint32_t *status;
+    const uint32_t *l0;     // first fused level (>= L: no fusion)
+};
+
+// Bits [lo, hi) of a word, 0 <= lo <= hi <= 64.
+__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi) {
+    const uint64_t h = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return h & ~((1ull << lo) - 1ull);
+}
+
+// First fused level from the largest node of each level: the first level
+// whose nodes all fit in kHalf positions, if it leaves a split to do
+// (l0 <= L-2); L otherwise.
+__device__ __forceinline__ uint32_t fused_from(const uint64_t *maxnode, uint32_t L, uint64_t half) {
+    for (uint32_t l = 0; l + 2 <= L; ++l)
+        if (maxnode[l] <= half) return l;
+    return L;
+}
+
+// Largest node of levels [0, L) over heap elements g in [g0, g1) (g in
+// [2^l, 2^(l+1)) is node g - 2^l of level l): block maxima per level into
+// `red` (L entries, LDS, zeroed), then, when maxnode is not NULL, one
+// atomicMax per level into it.
+__device__ __forceinline__ void node_max_range(const uint64_t *C, uint64_t sigma, uint32_t L, uint64_t g0,
+                                               uint64_t g1, uint64_t gstride, unsigned long long *red,
+                                               unsigned long long *maxnode) {
+    auto Cc = [&](uint64_t x) { return C[x < sigma ? x : sigma]; };
+    for (uint64_t g = g0 + threadIdx.x; g < g1; g += gstride) {
+        const uint32_t l = 63u - (uint32_t)__clzll((long long)g);
+        const uint64_t p = g - (1ull << l);
+        const uint64_t sz = Cc((p + 1) << (L - l)) - Cc(p << (L - l));
+        if (sz) atomicMax(red + l, (unsigned long long)sz);
+    }
+    __syncthreads();
+    if (maxnode && threadIdx.x < L && red[threadIdx.x]) atomicMax(maxnode + threadIdx.x, red[threadIdx.x]);
+}
+
+template <typename TIN0, typename T, int kBytes>
+__device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, LdsFused<T, kBytes> &s) {
+    using Cfg = FusedCfg<T, kBytes>;
+    if (*f.status) return;
+    const uint32_t L = f.L, l0 = *f.l0;
+    if (l0 >= L) return;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint64_t n = f.n, sigma = f.sigma;
+    auto Cc = [&](uint64_t x) { return f.C[x < sigma ? x : sigma]; };
+    const uint32_t shift = L - l0;  // node p of level l0 covers symbols [p << shift, (p+1) << shift)
+    auto boundary = [&](uint64_t target) -> uint64_t {
+        if (target >= n) return n;
+        uint64_t lo = 0, hi = 1ull << l0;  // C at node 2^l0 is n >= target
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (Cc(mid << shift) >= target) hi = mid;
+            else lo = mid + 1;
+        }
+        return Cc(lo << shift);
+    };
+    const uint64_t a = boundary(seg * Cfg::kHalf), e = boundary((seg + 1) * Cfg::kHalf);
+    if (a >= e || e - a > (uint64_t)Cfg::kCap) return;  // empty (or tables inconsistent with the input)
+    const uint32_t m = (uint32_t)(e - a);
+    if (l0 == 0) {
+        const TIN0 *src = reinterpret_cast<const TIN0 *>(f.in0) + a;
+        for (uint32_t j = tid; j < m; j += kBlock) s.buf[0][j] = (T)src[j];
+    } else {
+        const T *src = reinterpret_cast<const T *>((l0 - 1) % 2 == 0 ? f.S0 : f.S1) + a;
+        for (uint32_t j = tid; j < m; j += kBlock) s.buf[0][j] = src[j];
+    }
+    __syncthreads();
+    const uint32_t a63 = (uint32_t)(a & 63);
+    const uint32_t nvw = (a63 + m + 63) / 64;
+    const uint64_t gw0 = a >> 6;
+    // Positions of word vw inside the segment; the segment that ends the
+    // level also owns the padding bits of its last word (written as 0).
+    auto vmask_of = [&](uint32_t vw) {
+        const uint32_t lo = vw == 0 ? a63 : 0u;
+        const int32_t hi = (int32_t)(a63 + m) - (int32_t)(64 * vw);
+        return bit_range(lo, (uint32_t)min(max(hi, 0), 64));
+    };
+    auto wmask_of = [&](uint32_t vw) {
+        const uint32_t lo = vw == 0 ? a63 : 0u;
+        const int32_t hi = (int32_t)(a63 + m) - (int32_t)(64 * vw);
+        return bit_range(lo, e == n && hi > 0 ? 64u : (uint32_t)min(max(hi, 0), 64));
+    };
+    int cur = 0;
+    for (uint32_t l = l0; l < L; ++l) {
+        const uint32_t k = L - 1 - l;
+        const T *A = s.buf[cur];
+        const uint64_t *Dl = f.D + ((2ull << l) - 2);
+        // 1. Bit words, wave w taking words w, w + 4, ...; zeros per word.
+        for (uint32_t vw = wave; vw < nvw; vw += kWaves) {
+            const int32_t j = (int32_t)(vw * 64 + lane) - (int32_t)a63;
+            const bool valid = j >= 0 && j < (int32_t)m;
+            const uint32_t v = valid ? (uint32_t)A[j] : 0u;
+            const uint64_t wb = __ballot(valid && ((v >> k) & 1u));
+            const uint64_t vb = __ballot(valid);
+            if (lane == 0) {
+                s.words[vw] = wb;
+                s.zpre[vw] = (uint32_t)(__popcll(vb) - __popcll(wb));
+            }
+        }
+        __syncthreads();
+        // 2. Exclusive scan of the zero counts (two words per thread).
+        {
+            const uint32_t w0 = 2 * tid, w1 = 2 * tid + 1;
+            const uint32_t c0 = w0 < nvw ? s.zpre[w0] : 0u, c1 = w1 < nvw ? s.zpre[w1] : 0u;
+            const uint32_t own = c0 + c1;
+            const uint32_t inc = wave_incl_scan_u32(own, lane);
+            if (lane == kWave - 1) s.red[wave] = inc;
+            __syncthreads();
+            uint32_t before = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) before += w < wave ? s.red[w] : 0u;
+            const uint32_t ex = before + inc - own;
+            if (w0 < nvw) s.zpre[w0] = ex;
+            if (w1 < nvw) s.zpre[w1] = ex + c0;
+            __syncthreads();
+        }
+        const uint32_t Zseg = s.red[0] + s.red[1] + s.red[2] + s.red[3];
+        const uint64_t pa = (uint64_t)((uint32_t)A[0] >> (k + 1));  // node of the first position
+        const uint64_t Za = pa && pa < (1ull << l) ? Dl[2 * pa - 1] : 0;  // zeros of the level before the segment
+        const uint64_t Oa = a - Za;
+        uint64_t *B = f.bits + (uint64_t)l * f.W;
+        uint64_t *R = f.rank + (uint64_t)l * f.rank_len;
+        uint64_t *S1 = f.sel1 + (uint64_t)l * f.cap, *S0 = f.sel0 + (uint64_t)l * f.cap;
+        // 3. Bit words to HBM and rank entries (positions 512 j inside the segment).
+        for (uint32_t vw = tid; vw < nvw; vw += kBlock) {
+            const uint64_t gw = gw0 + vw, word = s.words[vw], wm = wmask_of(vw);
+            if (wm == ~0ull) {
+                B[gw] = word;
+            } else {
+                atomicAnd((unsigned long long *)(B + gw), (unsigned long long)~wm);
+                atomicOr((unsigned long long *)(B + gw), (unsigned long long)word);
+            }
+            if ((gw & 7) == 0 && (vmask_of(vw) & 1ull)) R[gw >> 3] = 64 * gw - (Za + s.zpre[vw]);
+        }
+        // 4. Select samples whose ordinal falls in the segment (targets
+        //    counted by their offset r inside the segment, so the loops run
+        //    at most m/4096 + 1 times whatever Za holds).
+        constexpr uint64_t SS = WT_SELECT_SAMPLE;
+        const uint64_t Oseg = m - Zseg;
+        for (uint64_t r = (SS - Oa % SS) % SS; r < Oseg; r += SS) {
+            const uint64_t t = (Oa + r) / SS;
+            for (uint32_t vw = tid; vw < nvw; vw += kBlock) {
+                const uint64_t word = s.words[vw];
+                const uint64_t ob = (vw == 0 ? 0 : 64 * vw - a63) - s.zpre[vw];
+                if (t < f.cap && ob <= r && r < ob + (uint64_t)__popcll(word))
+                    S1[t] = 64 * (gw0 + vw) + select_in_word(word, (uint32_t)(r - ob));
+            }
+        }
+        for (uint64_t r = (SS - Za % SS) % SS; r < Zseg; r += SS) {
+            const uint64_t t = (Za + r) / SS;
+            for (uint32_t vw = tid; vw < nvw; vw += kBlock) {
+                const uint64_t zword = ~s.words[vw] & vmask_of(vw);
+                const uint64_t zb = s.zpre[vw];
+                if (t < f.cap && zb <= r && r < zb + (uint64_t)__popcll(zword))
+                    S0[t] = 64 * (gw0 + vw) + select_in_word(zword, (uint32_t)(r - zb));
+            }
+        }
+        if (l + 1 == L) break;
+        // 5. Stable split into the other buffer (the global pass's
+        //    destinations minus the segment start).
+        T *Bn = s.buf[cur ^ 1];
+        for (uint32_t j = tid; j < m; j += kBlock) {
+            const uint32_t v = (uint32_t)A[j];
+            const uint32_t pos = a63 + j, vw = pos >> 6, ln = pos & 63;
+            const uint64_t before = vmask_of(vw) & ((1ull << ln) - 1ull);
+            const uint64_t zl = s.zpre[vw] + (uint64_t)__popcll(~s.words[vw] & before);
+            const uint64_t q = v >> k;
+            const uint64_t dq = q < (2ull << l) ? Dl[q] : ~0ull;
+            const uint64_t dest = (q & 1u) ? dq + j - Za - zl : dq + Za + zl - a;
+            if (dest < m) Bn[dest] = (T)v;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
 }
 
 // Exclusive prefix of per-tile zero counts by one block: pre[t] =

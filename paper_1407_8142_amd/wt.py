@@ -25,7 +25,7 @@ SELECT_SAMPLE = 4096
 
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
-           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi"]
+           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -71,7 +71,7 @@ class BatchLayout(ctypes.Structure):
     _fields_ = [("scratch_bytes", ctypes.c_uint64), ("clear_bytes", ctypes.c_uint64), ("off_jobs", ctypes.c_uint64),
                 ("off_segs", ctypes.c_uint64), ("off_seg_of", ctypes.c_uint64), ("njobs", ctypes.c_uint32),
                 ("nsegs", ctypes.c_uint32), ("items", ctypes.c_uint32), ("phases", ctypes.c_uint32),
-                ("phase_first", ctypes.c_uint32 * 33)]
+                ("phase_first", ctypes.c_uint32 * 40)]
 
 
 _lib = None
@@ -102,9 +102,11 @@ def lib() -> ctypes.CDLL:
         L.wt_batch_run.argtypes = [ctypes.POINTER(BatchLayout), ctypes.POINTER(Tune), vp, vp]
         L.wt_batch_status.argtypes = [ctypes.POINTER(BatchLayout), vp, ctypes.POINTER(ctypes.c_int32), vp]
         L.wt_query_multi.argtypes = [vp, u32, vp, vp, vp, vp, u64, vp, vp]
+        L.wt_set_fused_levels.argtypes = [i32]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
-                  "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi"):
+                  "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
+                  "wt_set_fused_levels"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -338,6 +340,10 @@ def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
                                     _ptr(counts), _ptr(scratch), scratch.numel(), _stream(stream))
     _check(rc, "wt_build_rank_select")
     return {"rank": rank, "sel1": sel1, "sel0": sel0, "sel_counts": counts, "_scratch": scratch}
+
+
+def set_fused_levels(on: bool):
+    _check(lib().wt_set_fused_levels(1 if on else 0), "wt_set_fused_levels")
 
 
 def set_lookback_spin_limit(polls: int):

@@ -283,3 +283,63 @@ def test_query_multi_matches_single_tree_queries(wtmod):
             assert np.array_equal(got[sel], want), (ti, kd)
     bad = (tix >= len(trees)) | (kind == 3)
     assert np.all(got[bad] == wtmod.Q_BAD)
+
+
+def _expected_fused_level(C, sigma, L, half):
+    """First level whose nodes all hold <= half positions, if <= L-2."""
+    C = np.asarray(C, dtype=np.int64)
+    for l in range(0, L - 1):
+        ends = np.minimum(np.arange(0, (1 << l) + 1, dtype=np.int64) << (L - l), sigma)
+        sizes = np.diff(C[ends])
+        if sizes.max(initial=0) <= half:
+            return l
+    return L
+
+
+@pytest.mark.parametrize("case", ["uniform_small", "uniform_mid", "uniform_deep", "sorted", "text", "u16",
+                                  "u32", "ragged_nodes", "all_equal", "u32_narrow"])
+def test_fused_levels_match_unfused(wtmod, oracle_mod, case):
+    """Levels run fused in LDS give the same buffers as level passes, and
+    fusion starts at the level the node sizes call for."""
+    rng = np.random.default_rng(77)
+    if case == "uniform_small":
+        S, sigma = rng.integers(0, 256, 5000).astype(np.uint8), 256
+    elif case == "uniform_mid":
+        S, sigma = rng.integers(0, 256, 70001).astype(np.uint8), 256
+    elif case == "uniform_deep":
+        S, sigma = rng.integers(0, 200, 300017).astype(np.uint8), 200
+    elif case == "sorted":
+        S, sigma = np.sort(rng.integers(0, 256, 100000)).astype(np.uint8), 256
+    elif case == "text":
+        S, sigma = inputs.text_like(1 << 20), 256
+    elif case == "u16":
+        S, sigma = rng.integers(0, 1 << 16, 200000).astype(np.uint16), 1 << 16
+    elif case == "u32":
+        S, sigma = rng.integers(0, (1 << 20) + 3, 150000).astype(np.uint32), (1 << 20) + 3
+    elif case == "ragged_nodes":
+        # node sizes of every magnitude: geometric symbol frequencies
+        S = np.minimum(rng.geometric(0.02, 120000) - 1, 255).astype(np.uint8)
+        S = rng.permutation(S)
+        sigma = 256
+    elif case == "all_equal":
+        S, sigma = np.full(9000, 77, np.uint8), 128
+    else:
+        S, sigma = rng.integers(0, 60, 90000).astype(np.uint32), 60
+    want = oracle_mod.build_all(S, sigma)
+    L = want["L"]
+    mid = 1 if L <= 8 else (2 if L <= 16 else 4)
+    half = 16384 // mid // 2
+    l0 = _expected_fused_level(want["C"], sigma, L, half) if L >= 2 else L
+    wtmod.set_fused_levels(True)
+    t = gpu_build(wtmod, S, sigma)
+    got_l0 = int(t.scratch[248:252].view(torch.int32).item()) if L >= 2 else L
+    assert got_l0 == l0, (case, got_l0, l0)
+    assert_same(t.to_numpy(), want, ctx=f"{case} fused from level {l0} of {L}")
+    wtmod.set_fused_levels(False)
+    try:
+        t2 = gpu_build(wtmod, S, sigma)
+        assert_same(t2.to_numpy(), want, ctx=f"{case} unfused")
+    finally:
+        wtmod.set_fused_levels(True)
+    if case in ("uniform_small", "uniform_mid", "u16", "u32", "sorted", "u32_narrow"):
+        assert l0 < L - 1, (case, l0, L)  # these inputs exercise the fused path

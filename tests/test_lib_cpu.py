@@ -118,7 +118,8 @@ def _job(n, sigma, b):
 def test_batch_plan_queue_shape():
     """The queue holds every job's level-0 histogram tiles, one table item
     per job, then level by level the tiles of every job that has that level
-    (tiles of 16 KiB at the level's width); phases split it in that order."""
+    (tiles of 16 KiB at the level's width), then the fused-segment items;
+    phases split it in that order."""
     spec = [(0, 4, 1), (1, 1, 1), (100000, 256, 1), (20000, 1 << 16, 2), (5000, 1 << 20, 4), (70000, 5, 1)]
     lay = wt.batch_plan([_job(*s) for s in spec])
     tiles = lambda n, w: -(-n // (16384 // w))
@@ -128,12 +129,15 @@ def test_batch_plan_queue_shape():
     per_level = []
     for l in range(max(L(s) for n, s, b in spec if n)):
         per_level.append(sum(tiles(n, b if l == 0 else mid(L(s))) for n, s, b in spec if n and l < L(s)))
+    # fused tail levels: one item per segment of 8 KiB / 2 at the job's narrowed width
+    fused = sum(-(-n // (4096 // mid(L(s)))) for n, s, b in spec if n and L(s) >= 2)
     assert lay.njobs == len(spec)
-    assert lay.phases == 2 + len(per_level)
-    assert lay.items == hist + len(spec) + sum(per_level)
+    assert lay.phases == 3 + len(per_level)
+    assert lay.items == hist + len(spec) + sum(per_level) + fused
     firsts = [0, hist, hist + len(spec)]
     for c in per_level:
         firsts.append(firsts[-1] + c)
+    firsts.append(firsts[-1] + fused)
     assert list(lay.phase_first)[:lay.phases + 1] == firsts
     assert lay.scratch_bytes % 256 == 0 and lay.clear_bytes <= lay.scratch_bytes
     assert lay.off_jobs >= lay.clear_bytes
