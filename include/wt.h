@@ -189,8 +189,9 @@ typedef struct {
     uint32_t njobs;
     uint32_t nsegs;           /* queue segments: (job, phase) pairs with work */
     uint32_t items;           /* work items in the queue */
-    uint32_t phases;          /* histograms, tables, one per level of the deepest job, fused tail levels */
-    uint32_t phase_first[40]; /* first item of each phase; phase_first[phases] = items */
+    uint32_t phases;          /* tile histograms, whole-job histograms, tables, then per level of the
+                                 deepest job byte-symbol and wider tiles, then fused tail levels */
+    uint32_t phase_first[72]; /* first item of each phase; phase_first[phases] = items */
 } wt_batch_layout;
 
 /* Host only.  WT_ERR_ARG / WT_ERR_RANGE as wt_plan (and n >= 2^32). */

@@ -45,12 +45,26 @@ constexpr uint32_t kHistH = 2048;                         // hash slots of the b
 constexpr uint32_t kHistWords = HistHash<kHistH>::kWords;  // LDS words of its table (replicas or hash)
 constexpr uint32_t kKindHist = 0, kKindPrep = 1, kKindLevel = 2;  // level l is kind 2 + l
 constexpr uint32_t kKindFused = 64;                                 // a segment of the fused tail levels
-constexpr int kFusedBytes = 8192;                                   // per LDS buffer of a fused segment
+constexpr uint32_t kKindJobHist = 65;                               // a whole job's histogram
+constexpr int kFusedBytes = 16384;                                  // per LDS buffer of a fused segment
+constexpr uint32_t kJobHistMaxSigma = 65536;  // packed 16-bit LDS bins of one block (128 KiB)
+
+// Item kinds a kernel is built for: each phase of the per-phase launch gets
+// a kernel with only its own kind (its own LDS and registers); the
+// persistent launch gets one with every kind.
+constexpr uint32_t kHasTileHist = 1, kHasJobHist = 2, kHasPrep = 4, kHasLevel8 = 8, kHasLevelWide = 16,
+                   kHasFused = 32, kHasAll = 63;
+constexpr uint32_t kHasLevel = kHasLevel8 | kHasLevelWide;
+
+// Waves per SIMD each kernel is compiled for (what its LDS lets reside).
+constexpr int waves_for(uint32_t kinds) {
+    return kinds == kHasJobHist ? 1 : ((kinds & kHasFused) != 0 ? 4 : 5);
+}
 
 // Control words of one job (cleared by every run): status, done counters
 // (histogram, then one per level), ready flags (one per level).
 constexpr int kCtlWords = 64;
-constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32, kCtlFusedL0 = 63;
+constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32, kCtlCDone = 62, kCtlFusedL0 = 63;
 constexpr int kMaxLevels = 30;
 constexpr uint64_t kHeaderBytes = 256;  // queue heads [0, 32), abort flag [32]
 constexpr int kAbortWord = 32;
@@ -59,7 +73,7 @@ struct JobDev {
     const void *seq;
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes, reps;
-    uint32_t T0, Tm, Tpad, pad0;
+    uint32_t T0, Tm, Tpad, hist_items;  // hist_items: T0 tile items, or 1 whole-job item
     uint64_t W, rank_len, cap;
     uint64_t *bits, *C, *rank, *sel1, *sel0, *sel_counts;
     uint32_t *ctl, *symcnt, *cnt;
@@ -95,16 +109,32 @@ struct LdsPrep {
     unsigned long long nmax[32];
 };
 
-union LdsBatch {
+// Whole-job histogram: two 16-bit counters per word.
+struct LdsJobHist {
+    uint32_t bins[kJobHistMaxSigma / 2];
+    uint32_t red[kWaves];
+    uint32_t overflow;
+    BlockScanTmp scan;
+};
+
+union LdsLevels {
     LdsLevelU8 u8;
     LdsLevel<uint16_t> g16;
     LdsLevel<uint32_t> g32;
-    LdsHistB hist;
     BlockScanTmp scan;
-    LdsPrep prep;
+};
+
+union LdsFusedAll {
     LdsFused<uint8_t, kFusedBytes> f8;
     LdsFused<uint16_t, kFusedBytes> f16;
     LdsFused<uint32_t, kFusedBytes> f32;
+};
+
+union LdsBatch {
+    LdsHistB hist;
+    LdsPrep prep;
+    LdsLevels lv;
+    LdsFusedAll fu;
 };
 
 // A job or segment record: constant while the kernel runs and uniform
@@ -204,25 +234,112 @@ __device__ __forceinline__ void hist_item(const JobDev &j, uint32_t tile, LdsHis
     }
 }
 
+// A whole job's histogram in one block (alphabets of up to 2^16 symbols
+// whose counters do not fit as LDS replicas): packed 16-bit counters in LDS,
+// so no global atomic is needed; the block then writes C itself.  A counter
+// that reaches 2^15 gives 2^15 to the job's global count of that symbol
+// (the thread whose add crossed the mark does it, so a half never carries
+// into its neighbour).  Also the per-tile zeros of the top bit.
+template <typename T>
+__device__ __forceinline__ void job_hist_big(const JobDev &j, LdsJobHist &s) {
+    const int tid = threadIdx.x;
+    const uint32_t nwords = (uint32_t)((j.sigma + 1) / 2);
+    for (uint32_t i = tid; i < nwords; i += kBlock) s.bins[i] = 0;
+    if (tid == 0) s.overflow = 0;
+    __syncthreads();
+    const T *S = reinterpret_cast<const T *>(j.seq);
+    const uint32_t shift = tile_shift_for(sizeof(T)), ktop = j.L ? j.L - 1 : 0u;
+    constexpr int V = 16 / sizeof(T);
+    bool bad = false, ovf = false;
+    auto count = [&](uint32_t x) -> uint32_t {
+        if (x >= j.sigma) {
+            bad = true;
+        } else {
+            const uint32_t hi = x & 1u, inc = hi ? 0x10000u : 1u;
+            const uint32_t old = atomicAdd(s.bins + (x >> 1), inc);
+            if (((old >> (16 * hi)) & 0xFFFFu) == 0x7FFFu) {
+                atomicSub(s.bins + (x >> 1), inc << 15);
+                atomicAdd(j.symcnt + x, 0x8000u);
+                ovf = true;
+            }
+        }
+        return ((x >> ktop) & 1u) ^ 1u;
+    };
+    for (uint32_t tile = 0; tile < j.T0; ++tile) {
+        const uint64_t base = (uint64_t)tile << shift;
+        const uint32_t len = (uint32_t)min(1ull << shift, j.n - base);
+        uint32_t zeros = 0;
+        if (len % V == 0) {
+            for (uint32_t v = tid; v < len / V; v += kBlock) {
+                union {
+                    uint4 q;
+                    T e[V];
+                } u;
+                u.q = *reinterpret_cast<const uint4 *>(S + base + (uint64_t)v * V);
+#pragma unroll
+                for (int e = 0; e < V; ++e) zeros += count((uint32_t)u.e[e]);
+            }
+        } else {
+            for (uint32_t e = tid; e < len; e += kBlock) zeros += count((uint32_t)S[base + e]);
+        }
+        if (j.L) {
+            const uint32_t t = block_sum_u32(zeros, s.red);
+            if (tid == 0) j.cnt[tile] = t;
+        }
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(j.ctl + kCtlStatus, kStatusSymbol);
+    if (__ballot(ovf) && lane_id() == 0) atomicOr(&s.overflow, 1u);
+    __syncthreads();
+    // C = exclusive prefix of the counts (plus what reached the global
+    // counters), written straight to the output.
+    const bool spill = s.overflow != 0;
+    const uint64_t total = block_scan_all<16>(
+        j.sigma, s.scan,
+        [&](uint64_t g) -> uint64_t {
+            const uint32_t w = s.bins[g >> 1];
+            return (uint64_t)((w >> (16 * (g & 1))) & 0xFFFFu) +
+                   (spill ? __hip_atomic_load(j.symcnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u);
+        },
+        [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
+    if (tid == 0) {
+        j.C[j.sigma] = total;
+        j.ctl[kCtlCDone] = 1;
+    }
+}
+
+// The same job with a small LDS (the persistent kernel): tile by tile
+// through the hashed counts of hist_count, flushed to the global counts.
+template <typename T>
+__device__ __forceinline__ void job_hist_small(const JobDev &j, LdsHistB &s) {
+    for (uint32_t tile = 0; tile < j.T0; ++tile) {
+        __syncthreads();
+        hist_item<T>(j, tile, s);
+    }
+}
+
 __host__ __device__ inline uint64_t fused_half(uint32_t mid) {
     return mid == 1 ? FusedCfg<uint8_t, kFusedBytes>::kHalf
                     : (mid == 2 ? FusedCfg<uint16_t, kFusedBytes>::kHalf : FusedCfg<uint32_t, kFusedBytes>::kHalf);
 }
 
-// C, node tables, directory tails, level-0 tile prefixes and the first
-// fused level of one job.
+// C (unless the job's histogram already wrote it), node tables, directory
+// tails, level-0 tile prefixes and the first fused level of one job.  N:
+// values per thread in the block scans (more is faster, and costs registers).
+template <int N>
 __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fuse) {
     BlockScanTmp &tmp = lp.scan;
-    const uint64_t total = block_scan_all<4>(
-        j.sigma, tmp, [&](uint64_t g) -> uint64_t { return j.symcnt[g]; },
-        [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
-    if (threadIdx.x == 0) j.C[j.sigma] = total;
-    __syncthreads();  // the block reads C back below (workgroup scope)
+    if (!__hip_atomic_load(j.ctl + kCtlCDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        const uint64_t total = block_scan_all<N>(
+            j.sigma, tmp, [&](uint64_t g) -> uint64_t { return j.symcnt[g]; },
+            [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
+        if (threadIdx.x == 0) j.C[j.sigma] = total;
+        __syncthreads();  // the block reads C back below (workgroup scope)
+    }
     if (j.L == 0) return;
     const TableOp top{j.C, j.D, j.sigma, j.L};
     for (uint32_t l = 0; l < j.L; ++l) {
         const uint64_t g0 = 1ull << l;
-        block_scan_all<4>(
+        block_scan_all<N>(
             g0, tmp, [&](uint64_t i) -> uint64_t { return top.value(g0 + i); },
             [&](uint64_t i, uint64_t ex) { top.store(g0 + i, ex); });
     }
@@ -242,7 +359,8 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
     if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
 }
 
-__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LdsBatch &s) {
+template <uint32_t KINDS>
+__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LdsLevels &s) {
     const bool scatter = l + 1 < j.L;
     const uint32_t win = l == 0 ? j.in_bytes : j.mid_bytes, wout = j.mid_bytes;
     LevelArgs a;
@@ -262,21 +380,63 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
     a.k = j.L - 1 - l;
     a.level = l;
     a.fused_l0 = j.ctl + kCtlFusedL0;
-    if (scatter) {
-        if (win == 1) level_tile_u8<true, true>(a, tile, s.u8);
-        else if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
-        else if (win == 2) level_tile<uint16_t, uint16_t, true, true>(a, tile, s.g16);
-        else if (wout == 1) level_tile<uint32_t, uint8_t, true, true>(a, tile, s.g32);
-        else if (wout == 2) level_tile<uint32_t, uint16_t, true, true>(a, tile, s.g32);
-        else level_tile<uint32_t, uint32_t, true, true>(a, tile, s.g32);
-    } else {
-        if (win == 1) level_tile_u8<false, true>(a, tile, s.u8);
-        else if (win == 2) level_tile<uint16_t, uint16_t, false, true>(a, tile, s.g16);
-        else level_tile<uint32_t, uint32_t, false, true>(a, tile, s.g32);
+    if (win == 1) {
+        if constexpr ((KINDS & kHasLevel8) != 0) {
+            if (scatter) level_tile_u8<true, true>(a, tile, s.u8);
+            else level_tile_u8<false, true>(a, tile, s.u8);
+        }
+        return;
+    }
+    if constexpr ((KINDS & kHasLevelWide) != 0) {
+        if (scatter) {
+            if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
+            else if (win == 2) level_tile<uint16_t, uint16_t, true, true>(a, tile, s.g16);
+            else if (wout == 1) level_tile<uint32_t, uint8_t, true, true>(a, tile, s.g32);
+            else if (wout == 2) level_tile<uint32_t, uint16_t, true, true>(a, tile, s.g32);
+            else level_tile<uint32_t, uint32_t, true, true>(a, tile, s.g32);
+        } else {
+            if (win == 2) level_tile<uint16_t, uint16_t, false, true>(a, tile, s.g16);
+            else level_tile<uint32_t, uint32_t, false, true>(a, tile, s.g32);
+        }
     }
 }
 
-__device__ __forceinline__ void run_item(const Args &b, uint32_t it, LdsBatch &s, uint32_t *s_flag) {
+__device__ __forceinline__ void fused_item(const JobDev &j, uint32_t seg, LdsFusedAll &s) {
+    FusedArgs f;
+    f.in0 = j.seq;
+    f.S0 = j.S0;
+    f.S1 = j.S1;
+    f.C = j.C;
+    f.D = j.D;
+    f.sigma = j.sigma;
+    f.n = j.n;
+    f.L = j.L;
+    f.bits = j.bits;
+    f.W = j.W;
+    f.rank = j.rank;
+    f.rank_len = j.rank_len;
+    f.sel1 = j.sel1;
+    f.sel0 = j.sel0;
+    f.cap = j.cap;
+    f.status = j.ctl + kCtlStatus;
+    f.l0 = j.ctl + kCtlFusedL0;
+    const uint32_t wi = j.in_bytes, wm = j.mid_bytes;
+    if (wm == 1) {
+        if (wi == 1) fused_segment<uint8_t, uint8_t, kFusedBytes>(f, seg, s.f8);
+        else if (wi == 2) fused_segment<uint16_t, uint8_t, kFusedBytes>(f, seg, s.f8);
+        else fused_segment<uint32_t, uint8_t, kFusedBytes>(f, seg, s.f8);
+    } else if (wm == 2) {
+        if (wi == 2) fused_segment<uint16_t, uint16_t, kFusedBytes>(f, seg, s.f16);
+        else fused_segment<uint32_t, uint16_t, kFusedBytes>(f, seg, s.f16);
+    } else {
+        fused_segment<uint32_t, uint32_t, kFusedBytes>(f, seg, s.f32);
+    }
+}
+
+// One work item.  KINDS: the item kinds this kernel is built for; LDS: its
+// shared-memory type (one of the Lds* types above).
+template <uint32_t KINDS, typename LDS>
+__device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uint32_t *s_flag) {
     const uint32_t si = __builtin_amdgcn_readfirstlane(b.seg_of[it]);
     const Seg sg = load_const(b.segs + si);
     const uint32_t jid = __builtin_amdgcn_readfirstlane(sg.job), kind = __builtin_amdgcn_readfirstlane(sg.kind);
@@ -285,62 +445,79 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LdsBatch &s
     const JobDev j = load_const(b.jobs + jid);
     uint32_t *ctl = j.ctl;
     if (kind == kKindHist) {
-        if (j.in_bytes == 1) hist_item<uint8_t>(j, tile, s.hist);
-        else if (j.in_bytes == 2) hist_item<uint16_t>(j, tile, s.hist);
-        else hist_item<uint32_t>(j, tile, s.hist);
-        finish_item(b, ctl + kCtlDone, count, s_flag);
+        if constexpr ((KINDS & kHasTileHist) != 0) {
+            LdsHistB &h = [&]() -> LdsHistB & {
+                if constexpr (KINDS == kHasAll) return s.hist;
+                else return s;
+            }();
+            if (j.in_bytes == 1) hist_item<uint8_t>(j, tile, h);
+            else if (j.in_bytes == 2) hist_item<uint16_t>(j, tile, h);
+            else hist_item<uint32_t>(j, tile, h);
+            finish_item(b, ctl + kCtlDone, count, s_flag);
+        }
+    } else if (kind == kKindJobHist) {
+        if constexpr (KINDS == kHasJobHist) {
+            if (j.in_bytes == 2) job_hist_big<uint16_t>(j, s);
+            else job_hist_big<uint32_t>(j, s);
+            finish_item(b, ctl + kCtlDone, count, s_flag);
+        } else if constexpr (KINDS == kHasAll) {
+            if (j.in_bytes == 2) job_hist_small<uint16_t>(j, s.hist);
+            else job_hist_small<uint32_t>(j, s.hist);
+            finish_item(b, ctl + kCtlDone, count, s_flag);
+        }
     } else if (kind == kKindPrep) {
-        wait_for(b, ctl + kCtlDone, j.T0, ctl + kCtlStatus);
-        prep_item(j, s.prep, b.fuse != 0);
-        publish(b, ctl + kCtlReady);
+        if constexpr ((KINDS & kHasPrep) != 0) {
+            wait_for(b, ctl + kCtlDone, j.hist_items, ctl + kCtlStatus);
+            if constexpr (KINDS == kHasAll) prep_item<4>(j, s.prep, b.fuse != 0);
+            else prep_item<16>(j, s, b.fuse != 0);
+            publish(b, ctl + kCtlReady);
+        }
     } else if (kind == kKindFused) {
-        wait_for(b, ctl + kCtlReady, 1u, ctl + kCtlStatus);  // tables and the fused level are known
-        const uint32_t l0 = ld_u32(ctl + kCtlFusedL0);
-        if (l0 >= j.L) return;
-        if (l0 > 0) wait_for(b, ctl + kCtlReady + l0, 1u, ctl + kCtlStatus);
-        FusedArgs f;
-        f.in0 = j.seq;
-        f.S0 = j.S0;
-        f.S1 = j.S1;
-        f.C = j.C;
-        f.D = j.D;
-        f.sigma = j.sigma;
-        f.n = j.n;
-        f.L = j.L;
-        f.bits = j.bits;
-        f.W = j.W;
-        f.rank = j.rank;
-        f.rank_len = j.rank_len;
-        f.sel1 = j.sel1;
-        f.sel0 = j.sel0;
-        f.cap = j.cap;
-        f.status = ctl + kCtlStatus;
-        f.l0 = ctl + kCtlFusedL0;
-        const uint32_t wi = j.in_bytes, wm = j.mid_bytes;
-        if (wm == 1) {
-            if (wi == 1) fused_segment<uint8_t, uint8_t, kFusedBytes>(f, tile, s.f8);
-            else if (wi == 2) fused_segment<uint16_t, uint8_t, kFusedBytes>(f, tile, s.f8);
-            else fused_segment<uint32_t, uint8_t, kFusedBytes>(f, tile, s.f8);
-        } else if (wm == 2) {
-            if (wi == 2) fused_segment<uint16_t, uint16_t, kFusedBytes>(f, tile, s.f16);
-            else fused_segment<uint32_t, uint16_t, kFusedBytes>(f, tile, s.f16);
-        } else {
-            fused_segment<uint32_t, uint32_t, kFusedBytes>(f, tile, s.f32);
+        if constexpr ((KINDS & kHasFused) != 0) {
+            wait_for(b, ctl + kCtlReady, 1u, ctl + kCtlStatus);  // tables and the fused level are known
+            const uint32_t l0 = ld_u32(ctl + kCtlFusedL0);
+            if (l0 >= j.L) return;
+            if (l0 > 0) wait_for(b, ctl + kCtlReady + l0, 1u, ctl + kCtlStatus);
+            if constexpr (KINDS == kHasAll) fused_item(j, tile, s.fu);
+            else fused_item(j, tile, s);
         }
     } else {
-        const uint32_t l = kind - kKindLevel;
-        wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
-        level_item(j, l, tile, s);
-        if (finish_item(b, ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
-            tile_prefix_block(j.cnt + (uint64_t)(l + 1) * j.Tpad, j.pre + (uint64_t)(l + 1) * j.Tpad, j.Tm, s.scan);
-            publish(b, ctl + kCtlReady + 1 + l);
+        if constexpr ((KINDS & kHasLevel) != 0) {
+            LdsLevels &lv = [&]() -> LdsLevels & {
+                if constexpr (KINDS == kHasAll) return s.lv;
+                else return s;
+            }();
+            const uint32_t l = kind - kKindLevel;
+            wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
+            level_item<KINDS>(j, l, tile, lv);
+            if (finish_item(b, ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
+                tile_prefix_block(j.cnt + (uint64_t)(l + 1) * j.Tpad, j.pre + (uint64_t)(l + 1) * j.Tpad, j.Tm,
+                                  lv.scan);
+                publish(b, ctl + kCtlReady + 1 + l);
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void work_kernel(Args b) {
-    __shared__ LdsBatch s;
+template <uint32_t KINDS, typename LDS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_for(KINDS)))) void
+work_kernel(Args b) {
+    __shared__ LDS s;
     __shared__ uint32_t s_first, s_flag;
+    if (!b.fenced) {
+        // One launch per phase: no item waits for another of the same
+        // launch, so blocks take their chunks by index (no shared queue head,
+        // whose atomics would serialise the launch).
+        for (uint64_t first = b.lo + (uint64_t)blockIdx.x * b.chunk; first < b.hi;
+             first += (uint64_t)gridDim.x * b.chunk) {
+            const uint32_t last = (uint32_t)min(first + b.chunk, (uint64_t)b.hi);
+            for (uint32_t it = (uint32_t)first; it < last; ++it) {
+                __syncthreads();  // the previous item's LDS is free
+                run_item<KINDS, LDS>(b, it, s, &s_flag);
+            }
+        }
+        return;
+    }
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -353,7 +530,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         const uint32_t last = min(first + b.chunk, b.hi);
         for (uint32_t it = first; it < last; ++it) {
             __syncthreads();  // the previous item's LDS is free
-            run_item(b, it, s, &s_flag);
+            run_item<KINDS, LDS>(b, it, s, &s_flag);
         }
     }
 }
@@ -368,6 +545,7 @@ __global__ void clear_kernel(uint64_t *a, uint64_t na) {
 struct HostJob {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes, reps, T0, Tm, Tpad;
+    bool job_hist;  // counted by one whole-job item (large alphabet that fits packed LDS bins)
     uint64_t off_ctl, off_symcnt, off_cnt, off_pre, off_D, off_S0, off_S1;
 };
 
@@ -404,6 +582,7 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
         h.T0 = (uint32_t)cdiv(q.n, 1ull << tile_shift_for(h.in_bytes));
         h.Tm = (uint32_t)cdiv(q.n, 1ull << tile_shift_for(h.mid_bytes));
         h.Tpad = (uint32_t)align_up(std::max<uint32_t>(std::max(h.T0, h.Tm), 1), 4);
+        h.job_hist = h.reps == 0 && q.sigma <= kJobHistMaxSigma && q.n > 0;
         maxL = std::max(maxL, h.n ? h.L : 0u);
     }
     // Clear region: header, control words of every job, then every job's
@@ -429,15 +608,24 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
         hp.segs.push_back(Seg{job, kind, (uint32_t)items, count});
         items += count;
     };
+    // Phases: tile histograms, whole-job histograms, tables, level 0, 1, ...,
+    // fused tail levels.
     hp.phase_first.push_back(0);
-    for (uint32_t i = 0; i < njobs; ++i) add(i, kKindHist, hp.jobs[i].T0);
+    for (uint32_t i = 0; i < njobs; ++i)
+        if (!hp.jobs[i].job_hist) add(i, kKindHist, hp.jobs[i].T0);
+    hp.phase_first.push_back((uint32_t)items);
+    for (uint32_t i = 0; i < njobs; ++i)
+        if (hp.jobs[i].job_hist) add(i, kKindJobHist, 1);
     hp.phase_first.push_back((uint32_t)items);
     for (uint32_t i = 0; i < njobs; ++i) add(i, kKindPrep, 1);
     for (uint32_t l = 0; l < maxL; ++l) {
-        hp.phase_first.push_back((uint32_t)items);
-        for (uint32_t i = 0; i < njobs; ++i) {
-            const HostJob &h = hp.jobs[i];
-            if (h.n > 0 && l < h.L) add(i, kKindLevel + l, l == 0 ? h.T0 : h.Tm);
+        for (int wide = 0; wide < 2; ++wide) {  // byte-symbol tiles, then wider ones
+            hp.phase_first.push_back((uint32_t)items);
+            for (uint32_t i = 0; i < njobs; ++i) {
+                const HostJob &h = hp.jobs[i];
+                const uint32_t win = l == 0 ? h.in_bytes : h.mid_bytes;
+                if (h.n > 0 && l < h.L && (win > 1) == (wide != 0)) add(i, kKindLevel + l, l == 0 ? h.T0 : h.Tm);
+            }
         }
         if (items >= (1ull << 31)) return WT_ERR_RANGE;
     }
@@ -481,7 +669,9 @@ static int residency(uint32_t &per_cu, uint32_t &cus) {
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
             return WT_ERR_HIP;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, work_kernel, kBlock, 0) != hipSuccess || b <= 0) b = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, work_kernel<kHasAll, LdsBatch>, kBlock, 0) != hipSuccess ||
+            b <= 0)
+            b = 1;
         s_cus = c;
         s_per_cu = b;
     }
@@ -545,6 +735,7 @@ extern "C" int wt_batch_prepare(const wt_job *jobs, uint32_t njobs, const wt_bat
         d.T0 = h.T0;
         d.Tm = h.Tm;
         d.Tpad = h.Tpad;
+        d.hist_items = h.job_hist ? 1u : h.T0;
         d.W = cdiv(h.n, 64);
         d.rank_len = cdiv(h.n, WT_RANK_BLOCK_BITS) + 1;
         d.cap = cdiv(h.n, WT_SELECT_SAMPLE) + 1;
@@ -607,8 +798,19 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
         a.head = (uint32_t *)sc + phase;
         a.lo = lo;
         a.hi = hi;
-        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(resident, cdiv(hi - lo, chunk)));
-        work_kernel<<<(unsigned)grid, kBlock, 0, s>>>(a);
+        // Persistent launch: resident blocks take items from the queue.  One
+        // launch per phase: one block per chunk unless blocks_per_cu caps it.
+        const uint64_t chunks = cdiv(hi - lo, chunk);
+        const uint64_t cap = (a.fenced || t.blocks_per_cu) ? resident : (1ull << 31) - 1;
+        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(cap, chunks));
+        const uint32_t last = lay->phases - 1;
+        if (a.fenced) work_kernel<kHasAll, LdsBatch><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (phase == 0) work_kernel<kHasTileHist, LdsHistB><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (phase == 1) work_kernel<kHasJobHist, LdsJobHist><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (phase == 2) work_kernel<kHasPrep, LdsPrep><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (phase == last) work_kernel<kHasFused, LdsFusedAll><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if ((phase - 3) % 2 == 0) work_kernel<kHasLevel8, LdsLevels><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else work_kernel<kHasLevelWide, LdsLevels><<<(unsigned)grid, kBlock, 0, s>>>(a);
     };
     if (t.mode == WT_BATCH_PERSISTENT) {
         launch(0, 0, lay->items);

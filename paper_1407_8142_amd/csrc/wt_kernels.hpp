@@ -92,14 +92,18 @@ __device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t
     const uint32_t smax = (uint32_t)min(sigma, (uint64_t)0xFFFFFFFFu);
     const bool need_check = sigma < (1ull << (8 * sizeof(T)));
     constexpr int V = 16 / sizeof(T);
+    // Replica path: `c` occurrences of symbol s at once.
+    auto add_run = [&](uint32_t s, uint32_t c) {
+        uint32_t bin = s;
+        if (need_check) {
+            bad |= s >= smax;
+            bin = min(s, smax);
+        }
+        atomicAdd(s_hist + bin, c);
+    };
     auto visit = [&](uint32_t s) -> uint32_t {
         if (lds) {
-            uint32_t bin = s;
-            if (need_check) {
-                bad |= s >= smax;
-                bin = min(s, smax);
-            }
-            atomicAdd(s_hist + bin, 1u);
+            add_run(s, 1u);
         } else if ((uint64_t)s >= sigma) {
             bad = true;
         } else {
@@ -131,8 +135,28 @@ __device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t
                     T e[V];
                 } u;
                 u.q = *reinterpret_cast<const uint4 *>(S + base + c0 + (uint64_t)v * V);
+                if (lds) {
+                    // Runs of equal symbols in the group take one atomic each
+                    // (text has many short runs).
+                    uint32_t prev = (uint32_t)u.e[0], run = 1;
+                    zeros += ((prev >> ktop) & 1u) ^ 1u;
 #pragma unroll
-                for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+                    for (int j = 1; j < V; ++j) {
+                        const uint32_t x = (uint32_t)u.e[j];
+                        zeros += ((x >> ktop) & 1u) ^ 1u;
+                        if (x == prev) {
+                            ++run;
+                        } else {
+                            add_run(prev, run);
+                            prev = x;
+                            run = 1;
+                        }
+                    }
+                    add_run(prev, run);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+                }
             }
         } else {
             for (uint32_t e = tid; e < clen; e += kBlock) zeros += visit((uint32_t)S[base + c0 + e]);
@@ -773,11 +797,14 @@ struct FusedCfg {
     static constexpr int kVWords = kCap / 64 + 2;         // words a segment touches (its start is not aligned)
 };
 
+constexpr int kFusedDCache = 512;  // node-table entries of a segment's key range kept in LDS
+
 template <typename T, int kBytes>
 struct LdsFused {
     T buf[2][FusedCfg<T, kBytes>::kCap];
     uint64_t words[FusedCfg<T, kBytes>::kVWords];
     uint32_t zpre[FusedCfg<T, kBytes>::kVWords];  // zeros of the segment before each word
+    uint64_t dcache[kFusedDCache];                // D_l[qlo + i]
     uint32_t red[kWaves];
 };
 
@@ -838,15 +865,22 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
     const uint64_t n = f.n, sigma = f.sigma;
     auto Cc = [&](uint64_t x) { return f.C[x < sigma ? x : sigma]; };
     const uint32_t shift = L - l0;  // node p of level l0 covers symbols [p << shift, (p+1) << shift)
+    // First node boundary of level l0 at or after `target`: a 64-way search
+    // by each wave (one probe per lane and round, so about three dependent
+    // loads instead of one per halving).
     auto boundary = [&](uint64_t target) -> uint64_t {
         if (target >= n) return n;
-        uint64_t lo = 0, hi = 1ull << l0;  // C at node 2^l0 is n >= target
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (Cc(mid << shift) >= target) hi = mid;
-            else lo = mid + 1;
+        uint64_t lo = 0, hi = 1ull << l0;  // the answer is a node index in [lo, hi]; C at node 2^l0 is n
+        while (hi - lo > 1) {
+            const uint64_t step = (hi - lo + kWave - 1) / kWave;
+            const uint64_t p = min(lo + (uint64_t)(lane + 1) * step, hi);
+            const uint64_t ge = __ballot(Cc(p << shift) >= target);  // lane 63 probes hi: always set
+            const int f = __ffsll((unsigned long long)ge) - 1;
+            hi = min(lo + (uint64_t)(f + 1) * step, hi);
+            lo = f == 0 ? lo : lo + (uint64_t)f * step;
+            if (f == 0 && Cc(lo << shift) >= target) hi = lo;
         }
-        return Cc(lo << shift);
+        return Cc(lo << shift) >= target ? Cc(lo << shift) : Cc(hi << shift);
     };
     const uint64_t a = boundary(seg * Cfg::kHalf), e = boundary((seg + 1) * Cfg::kHalf);
     if (a >= e || e - a > (uint64_t)Cfg::kCap) return;  // empty (or tables inconsistent with the input)
@@ -911,6 +945,15 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         const uint32_t Zseg = s.red[0] + s.red[1] + s.red[2] + s.red[3];
         const uint64_t pa = (uint64_t)((uint32_t)A[0] >> (k + 1));  // node of the first position
         const uint64_t Za = pa && pa < (1ull << l) ? Dl[2 * pa - 1] : 0;  // zeros of the level before the segment
+        // Table entries of the segment's key range [2 pa, 2 pz + 1] into LDS
+        // (a key past the cached window reads the table in HBM).
+        const uint64_t qlo = 2 * pa;
+        uint64_t nq = 0;  // cached entries
+        if (l + 1 < L) {
+            const uint64_t qhi = min(2 * (uint64_t)((uint32_t)A[m - 1] >> (k + 1)) + 1, (2ull << l) - 1);
+            nq = qhi >= qlo ? min(qhi - qlo + 1, (uint64_t)kFusedDCache) : 0;
+            for (uint32_t i = tid; i < nq; i += kBlock) s.dcache[i] = Dl[qlo + i];
+        }
         const uint64_t Oa = a - Za;
         uint64_t *B = f.bits + (uint64_t)l * f.W;
         uint64_t *R = f.rank + (uint64_t)l * f.rank_len;
@@ -953,13 +996,14 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         // 5. Stable split into the other buffer (the global pass's
         //    destinations minus the segment start).
         T *Bn = s.buf[cur ^ 1];
+        __syncthreads();  // the table cache is filled
         for (uint32_t j = tid; j < m; j += kBlock) {
             const uint32_t v = (uint32_t)A[j];
             const uint32_t pos = a63 + j, vw = pos >> 6, ln = pos & 63;
             const uint64_t before = vmask_of(vw) & ((1ull << ln) - 1ull);
             const uint64_t zl = s.zpre[vw] + (uint64_t)__popcll(~s.words[vw] & before);
             const uint64_t q = v >> k;
-            const uint64_t dq = q < (2ull << l) ? Dl[q] : ~0ull;
+            const uint64_t dq = q - qlo < nq ? s.dcache[q - qlo] : (q < (2ull << l) ? Dl[q] : ~0ull);
             const uint64_t dest = (q & 1u) ? dq + j - Za - zl : dq + Za + zl - a;
             if (dest < m) Bn[dest] = (T)v;
         }

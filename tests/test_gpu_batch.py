@@ -56,6 +56,12 @@ def mixed_jobs(seed=11):
     out.append((rng.integers(0, 200, 20000).astype(np.uint32), 200))
     # u16 input with sigma <= 256
     out.append((rng.integers(0, 100, 33333).astype(np.uint16), 100))
+    # whole-job histogram (5120 <= sigma <= 2^16) from a u32 input
+    out.append((rng.integers(0, 40000, 20000).astype(np.uint32), 40000))
+    # whole-job histogram with one symbol far past 2^15 occurrences (its
+    # packed LDS counter hands 2^15 to the global count many times)
+    heavy = np.where(rng.random(150001) < 0.8, 7, rng.integers(0, 6000, 150001)).astype(np.uint16)
+    out.append((heavy, 6000))
     return out
 
 

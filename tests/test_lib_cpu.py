@@ -116,26 +116,32 @@ def _job(n, sigma, b):
 
 
 def test_batch_plan_queue_shape():
-    """The queue holds every job's level-0 histogram tiles, one table item
-    per job, then level by level the tiles of every job that has that level
-    (tiles of 16 KiB at the level's width), then the fused-segment items;
-    phases split it in that order."""
-    spec = [(0, 4, 1), (1, 1, 1), (100000, 256, 1), (20000, 1 << 16, 2), (5000, 1 << 20, 4), (70000, 5, 1)]
+    """The queue holds, in phases: level-0 histogram tiles of the jobs
+    counted tile by tile, one whole-job histogram item per job whose
+    alphabet needs packed LDS bins (5120 <= sigma <= 2^16), one table item
+    per job, then per level the byte-symbol tiles and the wider tiles of
+    every job that has that level (16 KiB tiles), then one fused-segment item
+    per 8 KiB of positions at the job's narrowed width."""
+    spec = [(0, 4, 1), (1, 1, 1), (100000, 256, 1), (20000, 1 << 16, 2), (5000, 1 << 20, 4), (70000, 5, 1),
+            (30000, 6000, 2), (9000, 200, 4)]
     lay = wt.batch_plan([_job(*s) for s in spec])
     tiles = lambda n, w: -(-n // (16384 // w))
     L = lambda s: 0 if s == 1 else (s - 1).bit_length()
     mid = lambda l: 1 if l <= 8 else (2 if l <= 16 else 4)
-    hist = sum(tiles(n, b) for n, s, b in spec)
-    per_level = []
+    job_hist = lambda n, s: n > 0 and s + 1 > 5120 and s <= 65536
+    hist = sum(tiles(n, b) for n, s, b in spec if not job_hist(n, s))
+    jh = sum(1 for n, s, b in spec if job_hist(n, s))
+    per_phase = []
     for l in range(max(L(s) for n, s, b in spec if n)):
-        per_level.append(sum(tiles(n, b if l == 0 else mid(L(s))) for n, s, b in spec if n and l < L(s)))
-    # fused tail levels: one item per segment of 8 KiB / 2 at the job's narrowed width
-    fused = sum(-(-n // (4096 // mid(L(s)))) for n, s, b in spec if n and L(s) >= 2)
+        for wide in (False, True):
+            per_phase.append(sum(tiles(n, b if l == 0 else mid(L(s))) for n, s, b in spec
+                                 if n and l < L(s) and ((b if l == 0 else mid(L(s))) > 1) == wide))
+    fused = sum(-(-n // (8192 // mid(L(s)))) for n, s, b in spec if n and L(s) >= 2)
     assert lay.njobs == len(spec)
-    assert lay.phases == 3 + len(per_level)
-    assert lay.items == hist + len(spec) + sum(per_level) + fused
-    firsts = [0, hist, hist + len(spec)]
-    for c in per_level:
+    assert lay.phases == 3 + len(per_phase) + 1
+    assert lay.items == hist + jh + len(spec) + sum(per_phase) + fused
+    firsts = [0, hist, hist + jh, hist + jh + len(spec)]
+    for c in per_phase:
         firsts.append(firsts[-1] + c)
     firsts.append(firsts[-1] + fused)
     assert list(lay.phase_first)[:lay.phases + 1] == firsts
