@@ -573,8 +573,13 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         }
     }
     // Fused tail levels need the directories (they write their entries) and
-    // at least one split to save.
-    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0;
+    // at least one split to save.  The 2^l nodes of level l share n symbols,
+    // so its largest node holds at least ceil(n / 2^l): no level below
+    // `lmin` can fuse, and when lmin > L-2 none can, which leaves the level
+    // passes without the per-tile check of the fused level.
+    uint32_t lmin = 0;
+    while (lmin < 63 && cdiv(n, 1ull << lmin) > fused_half(p.mid_bytes)) ++lmin;
+    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
     uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
     if (fuse) {
         unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
@@ -609,7 +614,7 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         a.n = n;
         a.k = p.L - 1 - l;
         a.level = l;
-        a.fused_l0 = fuse ? fused_l0 : nullptr;
+        a.fused_l0 = (fuse && l >= lmin) ? fused_l0 : nullptr;
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (g_timing && (rc = timing_begin(s, ev))) return rc;
         launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);

@@ -187,7 +187,6 @@ __device__ __forceinline__ void emit_directories(const uint64_t (&word)[WPL], co
 #pragma unroll
         for (int m = 0; m < WPL; ++m) {
             const uint32_t w = (uint32_t)lane * WPL + m;
-            const bool has = w * 64u < len;
             const uint32_t nb = clamp_count(len, w * 64u, 64u);
             const uint64_t vmask = nb >= 64u ? ~0ull : ((1ull << nb) - 1ull);
             const uint64_t zword = ~word[m] & vmask;

@@ -418,8 +418,6 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
     constexpr int kTile = Cfg::kTile, kIt = Cfg::kItems, kWPL = Cfg::kWPL;
     constexpr int V = 16 / sizeof(TIN);
 
-    if (*a.status) return;  // uniform across the grid: the input was rejected
-    if (a.fused_l0 && a.level >= *a.fused_l0) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint64_t t0 = tile * kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
@@ -441,6 +439,11 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
     } else {
         for (uint32_t e = tid; e < len; e += kBlock) stage_in[e] = in[e];
     }
+    // Flags uniform across the grid, tested once the tile's loads are in
+    // flight (nothing has been written to global memory yet): the input was
+    // rejected, or this level is left to the fused pass.
+    if (*a.status) return;
+    if (a.fused_l0 && a.level >= *a.fused_l0) return;
     __syncthreads();
 
     // 2. Striped view: item r of wave w, lane j is position r*256 + 64w + j,
@@ -603,8 +606,6 @@ template <bool SCATTER, bool DIRS>
 __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile, LdsLevelU8 &s) {
     constexpr int kTile = LdsLevelU8::kTile, kRows = LdsLevelU8::kRows, kRowBytes = LdsLevelU8::kRowBytes;
 
-    if (*a.status) return;  // uniform across the grid: the input was rejected
-    if (a.fused_l0 && a.level >= *a.fused_l0) return;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t t0 = tile * (uint32_t)kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
@@ -633,6 +634,10 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
             d[r] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
+    // Grid-uniform flags, tested with the loads in flight and before any
+    // global write: the input was rejected, or the fused pass owns this level.
+    if (*a.status) return;
+    if (a.fused_l0 && a.level >= *a.fused_l0) return;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
