@@ -235,6 +235,15 @@ int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tr
  * launches (for comparisons). */
 int wt_set_fused_levels(int enable);
 
+/* Wide-alphabet histogram (on by default).  For sigma > 8192, wt_build counts
+ * symbols in 2^16-symbol slices of packed 16-bit LDS counters, one row of
+ * counts per input chunk, summed by a second kernel (the rows use the
+ * sequence ping-pong of the scratch, idle at that point); inputs too short
+ * for that use per-block LDS hashing with global atomics.  C is the same
+ * either way.  0 selects the hashing path for later launches (for
+ * comparisons). */
+int wt_set_sliced_histogram(int enable);
+
 /* Look-back tuning and testing hook.  Tiles of a level pass find their
  * prefix by looking back at earlier tiles; a tile whose predecessor has not
  * published after `polls` polls reduces that predecessor's input itself

@@ -71,6 +71,120 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
 }
 
 
+// Wide alphabets (sigma > 8192): block (chunk, slice) counts, over a chunk
+// of whole level-0 tiles, the symbols of slice [slice*2^16, slice*2^16+2^16)
+// in packed 16-bit LDS counters (128 KiB: one block per CU, 16 waves), then
+// stores them as its row of `part` (chunk-major, sigma entries per row).  A
+// counter that reaches 2^15 hands 2^15 to Cp1 (the thread whose add crossed
+// the mark does it, so a half never carries into its neighbour).  Every
+// slice of one chunk has the same blockIdx % 8 and so runs on one XCD:
+// after the first of them fetched a tile, the others read it from that
+// XCD's L2.  Slice 0 also checks the symbols and counts the zeros of the top
+// bit per tile.
+constexpr int kSliceThreads = 1024;
+constexpr uint32_t kSliceBins = 1u << 16;
+constexpr int kSliceUnroll = 4;  // tiles loaded before counting
+
+template <typename T>
+__global__ __launch_bounds__(kSliceThreads) void hist_slices(const T *__restrict__ S, uint64_t n, uint64_t sigma,
+                                                             uint32_t nslices, uint64_t nchunks,
+                                                             uint64_t tiles_per_chunk, uint32_t tile_shift,
+                                                             uint32_t ktop, uint32_t *cnt0,
+                                                             unsigned long long *Cp1, uint32_t *part,
+                                                             uint32_t *status) {
+    __shared__ uint32_t bins[kSliceBins / 2];
+    __shared__ uint32_t red[2][kSliceUnroll][kSliceThreads / kWave];
+    constexpr int V = 16 / sizeof(T);
+    static_assert(kSliceThreads * 16 == 16384, "one 16-byte load per thread covers a level-0 tile");
+    const uint32_t per = 8u * nslices;
+    const uint64_t chunk = (uint64_t)(blockIdx.x / per) * 8u + blockIdx.x % 8u;
+    const uint32_t slice = (blockIdx.x % per) / 8u;
+    if (chunk >= nchunks) return;  // the grid is padded to whole groups of 8 chunks
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    for (int i = tid; i < (int)(kSliceBins / 2); i += kSliceThreads) bins[i] = 0;
+    __syncthreads();
+    const uint32_t lo = slice * kSliceBins;
+    const bool lead = slice == 0;
+    bool bad = false;
+    auto count = [&](uint32_t x) -> uint32_t {
+        bad |= x >= sigma;
+        const uint32_t r = x - lo;  // below the slice: wraps past kSliceBins
+        if (r < kSliceBins && x < sigma) {
+            const uint32_t hi = r & 1u, inc = hi ? 0x10000u : 1u;
+            const uint32_t old = atomicAdd(bins + (r >> 1), inc);
+            if (((old >> (16 * hi)) & 0xFFFFu) == 0x7FFFu) {
+                atomicSub(bins + (r >> 1), inc << 15);
+                atomicAdd(Cp1 + x, 0x8000ull);
+            }
+        }
+        return ((x >> ktop) & 1u) ^ 1u;
+    };
+    const uint64_t ntiles = cdiv(n, 1ull << tile_shift);
+    const uint64_t t0 = chunk * tiles_per_chunk;
+    const uint64_t t1 = min(ntiles, t0 + tiles_per_chunk);
+    uint32_t buf = 0;
+    for (uint64_t g = t0; g < t1; g += kSliceUnroll) {
+        uint4 q[kSliceUnroll];
+        uint32_t z[kSliceUnroll];
+#pragma unroll
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            const uint64_t base = (g + u) << tile_shift;
+            q[u] = make_uint4(0, 0, 0, 0);
+            if (g + u < t1 && base + (1ull << tile_shift) <= n)
+                q[u] = reinterpret_cast<const uint4 *>(S + base)[tid];
+        }
+#pragma unroll
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            z[u] = 0;
+            const uint64_t base = (g + u) << tile_shift;
+            if (g + u >= t1) continue;
+            if (base + (1ull << tile_shift) <= n) {
+                union {
+                    uint4 q;
+                    T e[V];
+                } v;
+                v.q = q[u];
+#pragma unroll
+                for (int e = 0; e < V; ++e) z[u] += count((uint32_t)v.e[e]);
+            } else {  // the last, partial tile of the input
+                const uint32_t len = (uint32_t)(n - base);
+                for (uint32_t e = tid; e < len; e += kSliceThreads) z[u] += count((uint32_t)S[base + e]);
+            }
+        }
+        if (lead && cnt0) {
+#pragma unroll
+            for (int u = 0; u < kSliceUnroll; ++u) {
+                const uint32_t w = (uint32_t)wave_sum_u64(z[u]);
+                if (lane == 0) red[buf][u][wave] = w;
+            }
+            __syncthreads();
+            if (tid < kSliceUnroll && g + tid < t1) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int w = 0; w < kSliceThreads / kWave; ++w) t += red[buf][tid][w];
+                cnt0[g + tid] = t;
+            }
+            buf ^= 1u;  // the next group writes the other half: one barrier per group suffices
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicMax(status, kStatusSymbol);
+    __syncthreads();
+    const uint64_t row = chunk * sigma + lo;
+    const uint32_t nb = (uint32_t)min((uint64_t)kSliceBins, sigma - lo);
+    for (uint32_t i = tid; i < nb; i += kSliceThreads) part[row + i] = (bins[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+}
+
+// Cp1[c] += sum of the chunk rows of `part` at c.
+__global__ __launch_bounds__(kBlock) void hist_reduce(const uint32_t *__restrict__ part, uint64_t nchunks,
+                                                      uint64_t sigma, uint64_t *Cp1) {
+    for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < sigma; c += (uint64_t)gridDim.x * kBlock) {
+        uint64_t t = Cp1[c];
+        for (uint64_t k = 0; k < nchunks; ++k) t += part[k * sigma + c];
+        Cp1[c] = t;
+    }
+}
+
+
 // Exclusive prefix of per-tile zero counts (one block of 1024 threads, 16
 // counts per thread; `cnt` and `pre` are 64-entry aligned).
 constexpr int kScanThreads = 1024;
@@ -366,6 +480,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
 
 static bool g_timing = false;
 static bool g_fuse = true;
+static bool g_slices = true;  // sliced LDS histogram for wide alphabets
 static int g_spin_limit = 8;
 constexpr uint64_t kOffMaxNode = 8;   // in the status block: largest node per level (u64 x 30)
 constexpr uint64_t kOffFusedL0 = 248; // in the status block: first fused level (u32)
@@ -470,9 +585,37 @@ static void launch_fused(uint32_t in_w, uint32_t mid, const FusedArgs &f, uint64
 #undef WT_FU
 }
 
+// Wide alphabets: the sliced histogram when the S ping-pong (idle until
+// level 0 scatters) holds one row of counts per chunk and the input is long
+// enough to fill a chunk per slice; the LDS-hash histogram otherwise.
+template <typename T>
+static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
+                               void *rows, hipStream_t s) {
+    constexpr uint64_t kMinChunkTiles = 16;
+    if (p.sigma <= 8192 || p.L < 2) return false;
+    const uint32_t shift = tile_shift_for(sizeof(T));
+    const uint64_t ntiles = cdiv(p.n, 1ull << shift);
+    const uint32_t nslices = (uint32_t)cdiv(p.sigma, kSliceBins);
+    const uint64_t row_room = align_up(p.n * p.mid_bytes, 256) / (4 * p.sigma);
+    uint64_t nchunks = std::max<uint64_t>(1, (uint64_t)num_cus() / nslices);
+    nchunks = std::min(nchunks, row_room);
+    nchunks = std::min(nchunks, cdiv(ntiles, kMinChunkTiles));
+    if (nchunks == 0) return false;
+    const uint64_t per_chunk = cdiv(ntiles, nchunks);
+    nchunks = cdiv(ntiles, per_chunk);
+    const uint64_t grid = cdiv(nchunks, 8) * 8 * nslices;
+    hist_slices<T><<<(unsigned)grid, kSliceThreads, 0, s>>>((const T *)seq, p.n, p.sigma, nslices, nchunks, per_chunk,
+                                                            shift, p.L - 1, cnt0, (unsigned long long *)Cp1,
+                                                            (uint32_t *)rows, status);
+    const uint64_t rblocks = std::min<uint64_t>(cdiv(p.sigma, kBlock), 4096);
+    hist_reduce<<<(unsigned)rblocks, kBlock, 0, s>>>((const uint32_t *)rows, nchunks, p.sigma, Cp1);
+    return true;
+}
+
 template <typename T>
 static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
-                        hipStream_t s) {
+                        void *rows, hipStream_t s) {
+    if (g_slices && launch_hist_slices<T>(seq, p, Cp1, status, cnt0, rows, s)) return;
     uint32_t reps = 0;  // LDS replicas (64 lanes share them), 0 = global atomics
     if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / (p.sigma + 1)));
     const uint32_t shift = tile_shift_for(sizeof(T));
@@ -540,9 +683,10 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
     }
     if (n > 0) {
-        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, s);
-        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, s);
-        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, cnt, s);
+        void *rows = sc + p.off_S0;
+        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
+        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
+        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
         // C: prefix sums of the counts.
         CScanOp cop{out->C + 1};
         uint64_t chunks = cdiv(sigma, kScanChunk);
@@ -688,6 +832,11 @@ bool wt::fused_levels_enabled() { return g_fuse; }
 
 extern "C" int wt_set_fused_levels(int enable) {
     g_fuse = enable != 0;
+    return WT_OK;
+}
+
+extern "C" int wt_set_sliced_histogram(int enable) {
+    g_slices = enable != 0;
     return WT_OK;
 }
 

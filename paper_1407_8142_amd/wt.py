@@ -25,7 +25,8 @@ SELECT_SAMPLE = 4096
 
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
-           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels"]
+           "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
+           "wt_set_sliced_histogram"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -103,10 +104,11 @@ def lib() -> ctypes.CDLL:
         L.wt_batch_status.argtypes = [ctypes.POINTER(BatchLayout), vp, ctypes.POINTER(ctypes.c_int32), vp]
         L.wt_query_multi.argtypes = [vp, u32, vp, vp, vp, vp, u64, vp, vp]
         L.wt_set_fused_levels.argtypes = [i32]
+        L.wt_set_sliced_histogram.argtypes = [i32]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
                   "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
-                  "wt_set_fused_levels"):
+                  "wt_set_fused_levels", "wt_set_sliced_histogram"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -344,6 +346,10 @@ def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
 
 def set_fused_levels(on: bool):
     _check(lib().wt_set_fused_levels(1 if on else 0), "wt_set_fused_levels")
+
+
+def set_sliced_histogram(on: bool):
+    _check(lib().wt_set_sliced_histogram(1 if on else 0), "wt_set_sliced_histogram")
 
 
 def set_lookback_spin_limit(polls: int):
