@@ -1,32 +1,42 @@
 // Batched construction: many sequences of uneven length and alphabet built
-// by one kernel that takes work items from a queue (levelWT, Fig. 1 of
-// "Parallel Wavelet Tree Construction", applied to every sequence).
+// together from a list of work items (levelWT, Fig. 1 of "Parallel Wavelet
+// Tree Construction", applied to every sequence).
 //
-// Work items, in queue order (level-major, so that the items one item waits
-// for were all taken from the queue long before it):
+// Work items, in queue order (phase-major, so that the items one item waits
+// for were all handed out long before it):
 //   histogram tile (job, t)   counts of one tile of S into the job's symbol
-//                             counts, the symbol check, the zeros of the top
-//                             bit in the tile
-//   tables (job)              after the job's last histogram tile: C, the
-//                             node tables D_l, the directory tails and the
-//                             tile prefixes of level 0
-//   level tile (job, l, t)    after the job's level l-1 (or its tables): one
-//                             tile of the level pass (bits, directories,
-//                             stable split and scatter, count-ahead of l+1)
+//                             counts (LDS replicas or hash, global atomics),
+//                             the symbol check, the zeros of the top bit
+//   job histogram (job)       a whole job with 8192 < sigma <= 2^16 in one
+//                             block: packed 16-bit LDS counters, C written
+//                             by the block itself
+//   tables (job)              C (unless its histogram wrote it), the node
+//                             tables D_l, the directory tails, the tile
+//                             prefixes of level 0, the first fused level
+//   level tile (job, l, t)    one tile of the level pass (bits, directories,
+//                             stable split and scatter, count-ahead of l+1);
+//                             byte-symbol and wider tiles are separate phases
+//   fused segment (job, s)    the job's tail levels in LDS on one
+//                             node-aligned segment, once every node fits
 // The block that finishes the last tile of a level scans the count-ahead
 // totals into the next level's tile prefixes and marks that level ready.
 //
-// Progress: a block only waits on items that precede its own in the queue,
-// and items are handed out in queue order to blocks that are running, so
-// every wait ends whatever the residency (induction on queue position).  A
-// wait is still bounded: after `spin_limit` polls it raises the batch's
-// abort flag and the job's timeout status and goes on (outputs are then
-// unspecified); later waits return at once once the flag is up.
-//
-// The same kernel also runs one phase per launch (histograms, tables, level
-// 0, level 1, ...): kernel boundaries then order the phases and the waits
-// return at once.  Either form is a fixed sequence of kernel launches with
-// no host work in between, so it can be captured in a HIP graph.
+// Two launch forms, same items and outputs:
+//  * one launch per phase (the default): a kernel built for that phase's
+//    kind only, items assigned statically (chunk per block); kernel
+//    boundaries order the phases, so no wait ever spins and no cross-XCD
+//    write-back is needed between items;
+//  * one persistent launch over the whole queue: blocks take chunks of items
+//    from a global head counter and wait, with release/acquire fences, for
+//    the items their own depends on.  A block only waits on items that
+//    precede its own in the queue, and items are handed out in queue order to
+//    blocks that are running, so every wait ends whatever the residency
+//    (induction on queue position).  A wait is still bounded: after
+//    `spin_limit` polls it raises the batch's abort flag and the job's
+//    timeout status and goes on (outputs are then unspecified); later waits
+//    return at once once the flag is up.
+// Either form is a fixed sequence of kernel launches with no host work in
+// between, so it can be captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
