@@ -35,7 +35,7 @@ METRIC = "symbols*levels/s and % HBM peak; batched vs per-seq builds, bit-exact"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_pass.json")
 LEVEL_PASS_SOURCES = [os.path.join(ROOT, "paper_1407_8142_amd", "csrc", f)
-                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp")]
+                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp")]
 
 WORKLOADS = {
     "text256": ("text-like: n=2^28 uint8, sigma=256, Zipf(1.1) over a permuted byte alphabet, geometric runs "
@@ -57,16 +57,32 @@ def source_sha() -> str:
     return h.hexdigest()
 
 
-def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int) -> list[float]:
-    """Algorithmic HBM bytes of each level-pass launch: read the level's
-    sequence, write the next one (not on the last level), write the level
-    bits (n/8), the rank directory (8 B per 512 bits) and select samples
-    (8 B per 4096 ones and per 4096 zeros)."""
+def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int, passes: int) -> list[float]:
+    """Algorithmic HBM bytes of each level-pass launch.  One level per pass:
+    read the level's sequence, write the next one (not on the last level),
+    write the level bits (n/8), the rank directory (8 B per 512 bits) and
+    select samples (8 B per 4096 ones and per 4096 zeros).  Two levels per
+    pass (byte alphabets): read S_l once, write S_{l+2} (not from the last
+    pair), and two levels of bits and directories; an odd last level alone."""
+    dirs = n / 8 + n / 64 + n / 256
     out = []
-    for l in range(L):
+    if passes == L:
+        for l in range(L):
+            rd = in_bytes if l == 0 else mid_bytes
+            wr = mid_bytes if l + 1 < L else 0
+            out.append(n * (rd + wr) + dirs)
+        return out
+    l = 0
+    while l < L:
         rd = in_bytes if l == 0 else mid_bytes
-        wr = mid_bytes if l + 1 < L else 0
-        out.append(n * (rd + wr) + n / 8 + n / 64 + n / 256)
+        if l + 1 < L:
+            wr = mid_bytes if l + 2 < L else 0
+            out.append(n * (rd + wr) + 2 * dirs)
+            l += 2
+        else:
+            out.append(n * rd + dirs)
+            l += 1
+    assert len(out) == passes, (len(out), passes)
     return out
 
 
@@ -102,7 +118,7 @@ def batch_model_bytes(jobs) -> float:
     for n, sigma, b in jobs:
         L = 0 if sigma == 1 else (sigma - 1).bit_length()
         mid = 1 if L <= 8 else (2 if L <= 16 else 4)
-        total += n * b + sum(level_pass_bytes(n, L, b, mid)) + 8 * (sigma + 1)
+        total += n * b + sum(level_pass_bytes(n, L, b, mid, L)) + 8 * (sigma + 1)
     return total
 
 
@@ -298,19 +314,23 @@ def main():
     log(f"[bench] {ms_per_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step), {value:.3e} sym*lvl/s")
 
     mid = 1 if L <= 8 else (2 if L <= 16 else 4)
-    per_level = level_pass_bytes(n, L, S.dtype.itemsize, mid)
-    assert len(launches) == L * args.steps, (len(launches), L, args.steps)
+    passes = len(launches) // args.steps
+    assert passes * args.steps == len(launches) and passes in (L, (L + 1) // 2), (len(launches), L, args.steps)
+    per_pass = level_pass_bytes(n, L, S.dtype.itemsize, mid, passes)
     lp_ms = sum(launches)
-    lp_bytes = sum(per_level) * args.steps
+    lp_bytes = sum(per_pass) * args.steps
     avg_launch_ms = lp_ms / len(launches)
     avg_bytes = lp_bytes / len(launches)
     achieved = avg_bytes / (avg_launch_ms / 1e3) / 1e9
-    per_level_ms = [sum(launches[l::L]) / args.steps for l in range(L)]
-    log("[bench] level-pass ms per level: " + " ".join(f"{x:.4f}" for x in per_level_ms))
+    per_pass_ms = [sum(launches[i::passes]) / args.steps for i in range(passes)]
+    log(f"[bench] {'levels per pass: 1' if passes == L else 'levels per pass: 2'}; ms per pass: "
+        + " ".join(f"{x:.4f}" for x in per_pass_ms))
     traffic = traffic_per_launch(args.workload if n == n_default else "")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "level_pass (all levels)", "avg_launch_ms": round(avg_launch_ms, 5),
+            "kernel": "level_pass (all levels)" if passes == L else
+                      "pair_pass (two levels per launch; an odd last level by level_pass)",
+            "passes_per_build": passes, "avg_launch_ms": round(avg_launch_ms, 5),
             "algorithmic_bytes_per_launch": round(avg_bytes), "level_pass_share_of_step":
                 round(lp_ms / ms_total, 3)}
 

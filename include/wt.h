@@ -244,6 +244,18 @@ int wt_set_fused_levels(int enable);
  * comparisons). */
 int wt_set_sliced_histogram(int enable);
 
+/* Two levels per pass (off by default).  When on, for byte symbols
+ * (sym_bytes = 1, sigma <= 256) with n < 2^32 and no fused levels, wt_build
+ * runs levels l and l+1 in one pass over S_l: both bit levels, both levels'
+ * directory entries and S_{l+2} (a stable split of every node by two bits at
+ * once; see the levelWT construction, Fig. 1, and the sortWT view of its
+ * levels).  It halves the sequence traffic, but on gfx950 the byte level pass
+ * is bound by its ALU and LDS work rather than by HBM, and the two splits of
+ * a pair cost more than two single passes, so one level per pass is the
+ * default.  Outputs are identical either way.  Returns the previous setting
+ * (0 or 1); applies to later launches. */
+int wt_set_level_pairs(int enable);
+
 /* Look-back tuning and testing hook.  Tiles of a level pass find their
  * prefix by looking back at earlier tiles; a tile whose predecessor has not
  * published after `polls` polls reduces that predecessor's input itself

@@ -26,6 +26,7 @@
 #include "../../include/wt.h"
 #include "wt_device.hpp"
 #include "wt_kernels.hpp"
+#include "wt_pair.hpp"
 
 namespace wt {
 
@@ -46,24 +47,33 @@ __global__ void zero_fill(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb) {
 // zeros of the top bit per level-0 tile.  Blocks take whole tiles of level 0
 // (grid-stride); the LDS table (replicas or hash, see hist_count) lives
 // across the block's tiles and is flushed once at the end.
-template <typename T>
+// With DIG, the per-tile output is the packed counts of the top two bits'
+// digit (the prefixes a first pass over two levels needs) instead of the
+// zeros of the top bit.
+template <typename T, bool DIG>
 __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
                                                     unsigned long long *Cp1, uint32_t *status, uint32_t reps,
-                                                    uint32_t ktop, uint32_t *cnt0, uint32_t tile_shift,
+                                                    uint32_t ktop, void *cnt0, uint32_t tile_shift,
                                                     uint64_t ntiles) {
     constexpr uint32_t kH = 4096;
     extern __shared__ uint32_t s_dyn[];
-    __shared__ uint32_t s_red[kWaves];
+    __shared__ uint64_t s_red[kWaves];
     __shared__ uint32_t s_nused;
     hist_init<kH>(s_dyn, &s_nused, reps, sigma);
     bool bad = false;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = tile << tile_shift;
         const uint32_t len = (uint32_t)min(1ull << tile_shift, n - base);
-        const uint32_t zeros = hist_count<T, kH>(S, base, len, sigma, reps, ktop, s_dyn, &s_nused, Cp1, bad);
+        const auto zeros = hist_count<T, kH, unsigned long long, DIG>(S, base, len, sigma, reps, ktop, s_dyn,
+                                                                       &s_nused, Cp1, bad);
         if (cnt0) {
-            const uint32_t t = block_sum_u32(zeros, s_red);
-            if (threadIdx.x == 0) cnt0[tile] = t;
+            if constexpr (DIG) {
+                const uint64_t t = block_sum_u64(zeros, s_red);
+                if (threadIdx.x == 0) reinterpret_cast<uint64_t *>(cnt0)[tile] = t;
+            } else {
+                const uint32_t t = block_sum_u32(zeros, reinterpret_cast<uint32_t *>(s_red));
+                if (threadIdx.x == 0) reinterpret_cast<uint32_t *>(cnt0)[tile] = t;
+            }
         }
     }
     if (__ballot(bad) && lane_id() == 0) atomicMax(status, kStatusSymbol);
@@ -374,6 +384,80 @@ __global__ __launch_bounds__(kBlock) void fused_pass(FusedArgs f, uint64_t nseg)
 }
 
 // ---------------------------------------------------------------------------
+// Two levels per pass (byte alphabets, see pair_tile_u8).
+constexpr uint64_t kPairTableBytes = 4 * 256 * 4;  // E_l of the pairs at l = 0, 2, 4, 6
+
+template <bool SCATTER, bool NEXT_PAIR, bool DIRS>
+__global__ __launch_bounds__(kBlock) void pair_pass(PairArgs a) {
+    __shared__ LdsPair s;
+    pair_tile_u8<SCATTER, NEXT_PAIR, DIRS>(a, blockIdx.x, s);
+}
+
+// E_l[4p+d] = C[(4p+d) 2^(k-1)] - (symbols of digit d in the nodes before
+// p), for the pair that starts at level l = 2 * blockIdx.x (256 entries
+// each).
+__global__ __launch_bounds__(kBlock) void pair_tables(const uint64_t *C, uint64_t sigma, uint32_t L, uint32_t *E) {
+    const uint32_t l = 2u * blockIdx.x, k = L - 1u - l;
+    uint32_t *El = E + 256u * blockIdx.x;
+    auto Cc = [&](uint64_t x) { return C[x < sigma ? x : sigma]; };
+    for (uint32_t t = threadIdx.x; t < (4u << l); t += kBlock) {
+        const uint32_t p = t >> 2, d = t & 3u;
+        uint64_t before = 0;
+        for (uint32_t q = 0; q < p; ++q)
+            before += Cc((uint64_t)(4u * q + d + 1u) << (k - 1u)) - Cc((uint64_t)(4u * q + d) << (k - 1u));
+        El[t] = (uint32_t)(Cc((uint64_t)t << (k - 1u)) - before);
+    }
+}
+
+// Exclusive prefixes (G_0, G_1, G_2) of per-tile packed digit counts (one
+// block of 1024 threads, 16 tiles per thread per round; n < 2^32).
+__global__ __launch_bounds__(kScanThreads) void pair_prefix_scan(const uint64_t *cnt, uint4 *pre, uint64_t T) {
+    __shared__ uint32_t s_w[3][kScanThreads / kWave];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    uint32_t carry[3] = {0, 0, 0};
+    for (uint64_t c0 = 0; c0 < T; c0 += (uint64_t)kScanThreads * 16) {
+        const uint64_t base = c0 + (uint64_t)tid * 16;
+        uint64_t v[16];
+        uint32_t own[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            v[j] = base + j < T ? cnt[base + j] : 0ull;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) own[c] += (uint32_t)(v[j] >> (16 * c)) & 0xFFFFu;
+        }
+        uint32_t inc[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            inc[c] = wave_incl_scan_u32(own[c], lane);
+            if (lane == kWave - 1) s_w[c][wave] = inc[c];
+        }
+        __syncthreads();
+        uint32_t run[3], total[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uint32_t before = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kScanThreads / kWave; ++w) {
+                const uint32_t x = s_w[c][w];
+                before += w < wave ? x : 0u;
+                tot += x;
+            }
+            run[c] = carry[c] + before + inc[c] - own[c];
+            total[c] = tot;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (base + j < T) pre[base + j] = make_uint4(run[0], run[1], run[2], 0u);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) run[c] += (uint32_t)(v[j] >> (16 * c)) & 0xFFFFu;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) carry[c] += total[c];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Directory tails of every level (grid.y = level).  The level totals come
 // either from the node tables (zeros of a level = D_l's last entry) or from
 // an array of per-level totals.
@@ -428,7 +512,7 @@ struct Plan {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
-    uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_S0, off_S1, total;
+    uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_S0, off_S1, total;
     uint64_t n_part;
 };
 
@@ -469,6 +553,8 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     o = align_up(o + 8ull * D_len, 256);
     p.off_part = o;
     o = align_up(o + 8ull * p.n_part, 256);
+    p.off_E = o;  // two-level pass tables (byte alphabets: at most 4 x 256 u32)
+    o += p.L >= 2 && p.L <= 8 ? kPairTableBytes : 0;
     p.off_S0 = o;
     const uint64_t sbytes = p.L >= 2 ? align_up(n * p.mid_bytes, 256) : 0;
     o += sbytes;
@@ -481,6 +567,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
 static bool g_timing = false;
 static bool g_fuse = true;
 static bool g_slices = true;  // sliced LDS histogram for wide alphabets
+static bool g_pairs = false;  // two levels per pass for byte alphabets (measured slower: see wt_set_level_pairs)
 static int g_spin_limit = 8;
 constexpr uint64_t kOffMaxNode = 8;   // in the status block: largest node per level (u64 x 30)
 constexpr uint64_t kOffFusedL0 = 248; // in the status block: first fused level (u32)
@@ -506,6 +593,17 @@ static int timing_end(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
     g_events.push_back(ev);
     return WT_OK;
+}
+
+static int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
 }
 
 template <typename TIN, typename TOUT>
@@ -547,16 +645,6 @@ static void launch_level_any(uint32_t tin, uint32_t tout, bool scatter, bool dir
 #undef WT_LV
 }
 
-static int num_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
-    return cus;
-}
 
 template <typename TIN0, typename T>
 static void launch_fused_t(const FusedArgs &f, uint64_t n, hipStream_t s) {
@@ -612,19 +700,27 @@ static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, ui
     return true;
 }
 
+// `digits`: the per-tile output is the packed digit counts of the top two
+// bits (uint64 per tile) that a first pass over two levels reads.
 template <typename T>
 static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
-                        void *rows, hipStream_t s) {
-    if (g_slices && launch_hist_slices<T>(seq, p, Cp1, status, cnt0, rows, s)) return;
+                        void *rows, bool digits, hipStream_t s) {
+    if (!digits && g_slices && launch_hist_slices<T>(seq, p, Cp1, status, cnt0, rows, s)) return;
     uint32_t reps = 0;  // LDS replicas (64 lanes share them), 0 = global atomics
     if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / (p.sigma + 1)));
     const uint32_t shift = tile_shift_for(sizeof(T));
     const uint64_t ntiles = cdiv(p.n, 1ull << shift);
     uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)num_cus() * 8));
     const size_t shm = reps ? (size_t)reps * (p.sigma + 1) * 4 : (size_t)HistHash<4096>::kWords * 4;
-    histogram<T><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma, (unsigned long long *)Cp1,
-                                                       status, reps,
-                                                       p.L ? p.L - 1 : 0u, p.L ? cnt0 : nullptr, shift, ntiles);
+    if (digits)
+        histogram<T, true><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma,
+                                                                 (unsigned long long *)Cp1, status, reps, p.L - 1,
+                                                                 cnt0, shift, ntiles);
+    else
+        histogram<T, false><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma,
+                                                                  (unsigned long long *)Cp1, status, reps,
+                                                                  p.L ? p.L - 1 : 0u, p.L ? cnt0 : nullptr, shift,
+                                                                  ntiles);
 }
 
 }  // namespace wt
@@ -657,6 +753,101 @@ extern "C" uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L) {
     return align_up(8ull * std::max<uint32_t>(L, 1u), 256) + align_up(8ull * L * T, 256);
 }
 
+static void launch_pair(bool scatter, bool next_pair, bool dirs, uint32_t tiles, hipStream_t s, const PairArgs &a) {
+#define WT_PAIR(SC, NP, DI) \
+    if (scatter == SC && next_pair == NP && dirs == DI) return pair_pass<SC, NP, DI><<<tiles, kBlock, 0, s>>>(a);
+    WT_PAIR(true, true, true)
+    WT_PAIR(true, false, true)
+    WT_PAIR(false, false, true)
+    WT_PAIR(true, true, false)
+    WT_PAIR(true, false, false)
+    WT_PAIR(false, false, false)
+#undef WT_PAIR
+}
+
+// The levels of a byte alphabet two at a time (a last odd level alone),
+// after the histogram left the level-0 digit counts per tile.  Pair l reads
+// S_l, writes B_l, B_{l+1}, their directory entries and S_{l+2}, and counts
+// ahead for the next pass.
+static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, unsigned char *sc, bool dirs,
+                     hipStream_t s) {
+    const uint64_t n = p.n;
+    uint32_t *status = (uint32_t *)(sc + p.off_status);
+    uint32_t *cnt = (uint32_t *)(sc + p.off_cnt);
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
+    uint64_t *D = (uint64_t *)(sc + p.off_D);
+    uint32_t *E = (uint32_t *)(sc + p.off_E);
+    pair_tables<<<p.L / 2, kBlock, 0, s>>>(out->C, p.sigma, p.L, E);
+    const uint32_t shift = tile_shift_for(1);
+    const uint64_t Tl = cdiv(n, 1ull << shift);
+    const void *cur = d_seq;
+    int buf = 0;
+    int rc;
+    for (uint32_t l = 0; l < p.L; l += 2) {
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (l + 1 < p.L) {
+            const bool scatter = l + 2 < p.L, next_pair = l + 3 < p.L;
+            pair_prefix_scan<<<1, kScanThreads, 0, s>>>((const uint64_t *)(cnt + (uint64_t)l * p.T),
+                                                        (uint4 *)(pre + (uint64_t)l * p.T), Tl);
+            void *dst = buf == 0 ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+            PairArgs a;
+            a.in = (const uint8_t *)cur;
+            a.out = scatter ? (uint8_t *)dst : nullptr;
+            a.bits0 = out->bits + (uint64_t)l * p.W;
+            a.bits1 = out->bits + (uint64_t)(l + 1) * p.W;
+            a.C = out->C;
+            a.sigma = p.sigma;
+            a.D0 = D + ((2ull << l) - 2);
+            a.D1 = D + ((4ull << l) - 2);
+            a.E = E + 256u * (l / 2);
+            a.pre = (const uint4 *)(pre + (uint64_t)l * p.T);
+            a.next_cnt = scatter ? (void *)(cnt + (uint64_t)(l + 2) * p.T) : nullptr;
+            a.next_shift = shift;
+            a.status = status;
+            a.rank0 = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
+            a.sel10 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
+            a.sel00 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
+            a.rank1 = dirs ? out->rank + (uint64_t)(l + 1) * p.rank_len : nullptr;
+            a.sel11 = dirs ? out->sel1 + (uint64_t)(l + 1) * p.cap : nullptr;
+            a.sel01 = dirs ? out->sel0 + (uint64_t)(l + 1) * p.cap : nullptr;
+            a.n = (uint32_t)n;
+            a.k = p.L - 1 - l;
+            a.level = l;
+            if (g_timing && (rc = timing_begin(s, ev))) return rc;
+            launch_pair(scatter, next_pair, dirs, (uint32_t)Tl, s, a);
+            if (g_timing && (rc = timing_end(s, ev))) return rc;
+            if (scatter) {
+                cur = dst;
+                buf ^= 1;
+            }
+        } else {
+            tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
+            LevelArgs a;
+            a.in = cur;
+            a.out = nullptr;
+            a.bits = out->bits + (uint64_t)l * p.W;
+            a.D = D + ((2ull << l) - 2);
+            a.nD = 2ull << l;
+            a.tile_prefix = pre + (uint64_t)l * p.T;
+            a.next_cnt = nullptr;
+            a.next_shift = shift;
+            a.status = status;
+            a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
+            a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
+            a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
+            a.n = n;
+            a.k = 0;
+            a.level = l;
+            a.fused_l0 = nullptr;
+            if (g_timing && (rc = timing_begin(s, ev))) return rc;
+            launch_level_any(1, 1, false, dirs, s, a);
+            if (g_timing && (rc = timing_end(s, ev))) return rc;
+        }
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+    }
+    return WT_OK;
+}
+
 extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
                         void *d_scratch, uint64_t scratch_bytes, void *stream) {
     Plan p;
@@ -676,6 +867,19 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint64_t *part = (uint64_t *)(sc + p.off_part);
 
+    // Fused tail levels need the directories (they write their entries) and
+    // at least one split to save.  The 2^l nodes of level l share n symbols,
+    // so its largest node holds at least ceil(n / 2^l): no level below
+    // `lmin` can fuse, and when lmin > L-2 none can, which leaves the level
+    // passes without the per-tile check of the fused level.
+    uint32_t lmin = 0;
+    while (lmin < 63 && cdiv(n, 1ull << lmin) > fused_half(p.mid_bytes)) ++lmin;
+    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
+    // Two levels per pass: byte symbols in and between levels, nothing fused
+    // (inputs too small for that are the fused pass's), 32-bit positions.
+    const bool pairs = g_pairs && !fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
+                       n < (1ull << 32);
+
     // Zero: status + per-tile zero counts (one contiguous range), and C.
     {
         uint64_t na = p.off_pre / 8, nb = sigma + 1;
@@ -684,9 +888,9 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     }
     if (n > 0) {
         void *rows = sc + p.off_S0;
-        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
-        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
-        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, cnt, rows, s);
+        if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, rows, pairs, s);
+        else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, rows, false, s);
+        else launch_hist<uint32_t>(d_seq, p, out->C + 1, status, cnt, rows, false, s);
         // C: prefix sums of the counts.
         CScanOp cop{out->C + 1};
         uint64_t chunks = cdiv(sigma, kScanChunk);
@@ -716,14 +920,6 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
                                             out->sel_counts);
         }
     }
-    // Fused tail levels need the directories (they write their entries) and
-    // at least one split to save.  The 2^l nodes of level l share n symbols,
-    // so its largest node holds at least ceil(n / 2^l): no level below
-    // `lmin` can fuse, and when lmin > L-2 none can, which leaves the level
-    // passes without the per-tile check of the fused level.
-    uint32_t lmin = 0;
-    while (lmin < 63 && cdiv(n, 1ull << lmin) > fused_half(p.mid_bytes)) ++lmin;
-    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
     uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
     if (fuse) {
         unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
@@ -733,6 +929,7 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     }
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     if (n == 0 || p.L == 0) return WT_OK;
+    if (pairs) return run_pairs(d_seq, p, out, sc, dirs, s);
 
     const void *cur = d_seq;
     uint32_t cur_w = p.in_bytes;
@@ -838,6 +1035,12 @@ extern "C" int wt_set_fused_levels(int enable) {
 extern "C" int wt_set_sliced_histogram(int enable) {
     g_slices = enable != 0;
     return WT_OK;
+}
+
+extern "C" int wt_set_level_pairs(int enable) {
+    const int prev = g_pairs ? 1 : 0;
+    g_pairs = enable != 0;
+    return prev;
 }
 
 extern "C" int wt_set_lookback_spin_limit(int polls) {

@@ -6,6 +6,8 @@
 // kernel that runs several kinds of steps can overlay them in one union.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include "../../include/wt.h"
@@ -45,6 +47,18 @@ __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red) {
     return t;
 }
 
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *red) {
+    const int lane = lane_id(), wave = (int)threadIdx.x / kWave;
+    const uint64_t w = wave_sum_u64(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) t += red[i];
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // Histogram of one tile: the counts behind C (C[c] = #{S[i] < c}), the
 // symbol check, and the zeros of the top bit in the tile (the count-ahead
@@ -78,10 +92,19 @@ __device__ __forceinline__ void hist_init(uint32_t *tab, uint32_t *nused, uint32
     __syncthreads();
 }
 
+// Digit counts packed as (c0 | c1 << 16 | c2 << 32), digit = (x >> lo) & 3
+// (bit lo+1 high, bit lo low); the fourth count is implied by the total.
+// A tile holds at most 2^14 symbols, so per-tile sums never carry.
+__device__ __forceinline__ uint64_t digit_inc(uint32_t x, uint32_t lo) {
+    const uint32_t d = (x >> lo) & 3u;
+    return d < 3u ? 1ull << (16u * d) : 0ull;
+}
+
 // Counts S[base, base+len) into the LDS table (hash path: flushed to
-// `counts` every kH/2 symbols).  Returns this thread's zeros of bit ktop.
-template <typename T, uint32_t kH, typename CNT>
-__device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t base, uint32_t len, uint64_t sigma,
+// `counts` every kH/2 symbols).  Returns this thread's zeros of bit ktop,
+// or with DIG its packed counts of the digit (bit ktop, bit ktop-1).
+template <typename T, uint32_t kH, typename CNT, bool DIG = false>
+__device__ __forceinline__ std::conditional_t<DIG, uint64_t, uint32_t> hist_count(const T *__restrict__ S, uint64_t base, uint32_t len, uint64_t sigma,
                                                uint32_t reps, uint32_t ktop, uint32_t *tab, uint32_t *nused,
                                                CNT *counts, bool &bad) {
     using H = HistHash<kH>;
@@ -101,7 +124,11 @@ __device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t
         }
         atomicAdd(s_hist + bin, c);
     };
-    auto visit = [&](uint32_t s) -> uint32_t {
+    auto tally = [&](uint32_t x) -> std::conditional_t<DIG, uint64_t, uint32_t> {
+        if constexpr (DIG) return digit_inc(x, ktop - 1u);
+        else return ((x >> ktop) & 1u) ^ 1u;
+    };
+    auto visit = [&](uint32_t s) -> std::conditional_t<DIG, uint64_t, uint32_t> {
         if (lds) {
             add_run(s, 1u);
         } else if ((uint64_t)s >= sigma) {
@@ -122,9 +149,9 @@ __device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t
             }
             if (!done) atomicAdd(counts + s, (CNT)1);
         }
-        return ((s >> ktop) & 1u) ^ 1u;
+        return tally(s);
     };
-    uint32_t zeros = 0;
+    std::conditional_t<DIG, uint64_t, uint32_t> zeros = 0;
     const uint32_t chunk = lds ? len : H::kChunk;  // hash path: at most kH/2 symbols per flush
     for (uint32_t c0 = 0; c0 < len; c0 += chunk) {
         const uint32_t clen = clamp_count(len, c0, chunk);
@@ -139,11 +166,11 @@ __device__ __forceinline__ uint32_t hist_count(const T *__restrict__ S, uint64_t
                     // Runs of equal symbols in the group take one atomic each
                     // (text has many short runs).
                     uint32_t prev = (uint32_t)u.e[0], run = 1;
-                    zeros += ((prev >> ktop) & 1u) ^ 1u;
+                    zeros += tally(prev);
 #pragma unroll
                     for (int j = 1; j < V; ++j) {
                         const uint32_t x = (uint32_t)u.e[j];
-                        zeros += ((x >> ktop) & 1u) ^ 1u;
+                        zeros += tally(x);
                         if (x == prev) {
                             ++run;
                         } else {

@@ -1,4 +1,5 @@
-"""Measure HBM traffic of the level-pass kernels with rocprofv3 counters.
+"""Measure HBM traffic of the level-pass kernels (one or two levels per launch)
+with rocprofv3 counters.
 
 Runs four counter passes, each its own rocprofv3 process (one counter group
 per run): FETCH_SIZE and WRITE_SIZE of the streaming-copy probe (known bytes:
@@ -24,7 +25,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 PROBE = os.path.join(HERE, "bw_probe")
-LEVEL_PASS_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp")]
+LEVEL_PASS_SOURCES = [os.path.join(HERE, "csrc", f)
+                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp")]
 PROBE_MIB = 1024
 
 
@@ -52,6 +54,11 @@ def run_pass(counter: str, cmd: list[str], out_dir: str, tag: str) -> dict:
     return per_kernel
 
 
+def is_level_pass(kernel: str) -> bool:
+    """One level per launch (level_pass*) or two (pair_pass)."""
+    return "level_pass" in kernel or "pair_pass" in kernel
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="text256")
@@ -73,13 +80,13 @@ def main():
     bw = run_pass("WRITE_SIZE", bench_cmd, args.out, "lp_write")
     kernels = {}
     for k in sorted(set(bf) | set(bw)):
-        if "level_pass" not in k and "histogram" not in k:
+        if not is_level_pass(k) and "histogram" not in k:
             continue
         f = bf.get(k, [0.0])
         w = bw.get(k, [0.0])
         kernels[k] = {"launches": len(f), "fetch_kib_raw": sum(f) / len(f), "write_kib_raw": sum(w) / len(w),
                       "fetch_bytes": sum(f) / len(f) * f_scale * 1024, "write_bytes": sum(w) / len(w) * w_scale * 1024}
-    lp = [(v["launches"], v["fetch_bytes"] + v["write_bytes"]) for k, v in kernels.items() if "level_pass" in k]
+    lp = [(v["launches"], v["fetch_bytes"] + v["write_bytes"]) for k, v in kernels.items() if is_level_pass(k)]
     total_launches = sum(c for c, _ in lp)
     per_launch = sum(c * b for c, b in lp) / total_launches if total_launches else None
     entry = {"source_sha256": source_sha(), "calibration": {"fetch_scale": f_scale, "write_scale": w_scale,

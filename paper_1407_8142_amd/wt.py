@@ -26,7 +26,7 @@ SELECT_SAMPLE = 4096
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
            "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
-           "wt_set_sliced_histogram"]
+           "wt_set_sliced_histogram", "wt_set_level_pairs"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -105,10 +105,11 @@ def lib() -> ctypes.CDLL:
         L.wt_query_multi.argtypes = [vp, u32, vp, vp, vp, vp, u64, vp, vp]
         L.wt_set_fused_levels.argtypes = [i32]
         L.wt_set_sliced_histogram.argtypes = [i32]
+        L.wt_set_level_pairs.argtypes = [i32]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
                   "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
-                  "wt_set_fused_levels", "wt_set_sliced_histogram"):
+                  "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -350,6 +351,11 @@ def set_fused_levels(on: bool):
 
 def set_sliced_histogram(on: bool):
     _check(lib().wt_set_sliced_histogram(1 if on else 0), "wt_set_sliced_histogram")
+
+
+def set_level_pairs(on: bool) -> bool:
+    """Two levels per pass for byte alphabets on or off; returns the previous setting."""
+    return lib().wt_set_level_pairs(1 if on else 0) != 0
 
 
 def set_lookback_spin_limit(polls: int):
