@@ -136,12 +136,18 @@ __global__ __launch_bounds__(kSliceThreads) void hist_slices(const T *__restrict
     for (uint64_t g = t0; g < t1; g += kSliceUnroll) {
         uint4 q[kSliceUnroll];
         uint32_t z[kSliceUnroll];
+        if (g + kSliceUnroll <= t1 && ((g + kSliceUnroll) << tile_shift) <= n) {
+            // all whole tiles: no branch between the loads, so they overlap
 #pragma unroll
-        for (int u = 0; u < kSliceUnroll; ++u) {
-            const uint64_t base = (g + u) << tile_shift;
-            q[u] = make_uint4(0, 0, 0, 0);
-            if (g + u < t1 && base + (1ull << tile_shift) <= n)
-                q[u] = reinterpret_cast<const uint4 *>(S + base)[tid];
+            for (int u = 0; u < kSliceUnroll; ++u) q[u] = reinterpret_cast<const uint4 *>(S + ((g + u) << tile_shift))[tid];
+        } else {
+#pragma unroll
+            for (int u = 0; u < kSliceUnroll; ++u) {
+                const uint64_t base = (g + u) << tile_shift;
+                q[u] = make_uint4(0, 0, 0, 0);
+                if (g + u < t1 && base + (1ull << tile_shift) <= n)
+                    q[u] = reinterpret_cast<const uint4 *>(S + base)[tid];
+            }
         }
 #pragma unroll
         for (int u = 0; u < kSliceUnroll; ++u) {

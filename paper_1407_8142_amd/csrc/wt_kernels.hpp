@@ -156,33 +156,49 @@ __device__ __forceinline__ std::conditional_t<DIG, uint64_t, uint32_t> hist_coun
     for (uint32_t c0 = 0; c0 < len; c0 += chunk) {
         const uint32_t clen = clamp_count(len, c0, chunk);
         if (clen % V == 0 && ((base + c0) % V) == 0) {
-            for (uint32_t v = tid; v < clen / V; v += kBlock) {
+            // kU 16-byte loads per thread are issued before any is counted,
+            // so that their HBM latencies overlap.
+            constexpr int kU = 4;
+            const uint32_t nvec = clen / V;
+            for (uint32_t v0 = tid; v0 < nvec; v0 += kBlock * kU) {
                 union {
                     uint4 q;
                     T e[V];
-                } u;
-                u.q = *reinterpret_cast<const uint4 *>(S + base + c0 + (uint64_t)v * V);
-                if (lds) {
-                    // Runs of equal symbols in the group take one atomic each
-                    // (text has many short runs).
-                    uint32_t prev = (uint32_t)u.e[0], run = 1;
-                    zeros += tally(prev);
+                } u[kU];
+                const uint4 *src = reinterpret_cast<const uint4 *>(S + base + c0) + v0;
+                if (v0 + (uint32_t)((kU - 1) * kBlock) < nvec) {  // all in range: no branch between the loads
 #pragma unroll
-                    for (int j = 1; j < V; ++j) {
-                        const uint32_t x = (uint32_t)u.e[j];
-                        zeros += tally(x);
-                        if (x == prev) {
-                            ++run;
-                        } else {
-                            add_run(prev, run);
-                            prev = x;
-                            run = 1;
-                        }
-                    }
-                    add_run(prev, run);
+                    for (int k = 0; k < kU; ++k) u[k].q = src[k * kBlock];
                 } else {
 #pragma unroll
-                    for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u.e[j]);
+                    for (int k = 0; k < kU; ++k)
+                        u[k].q = v0 + (uint32_t)(k * kBlock) < nvec ? src[k * kBlock] : make_uint4(0, 0, 0, 0);
+                }
+#pragma unroll
+                for (int k = 0; k < kU; ++k) {
+                    if (v0 + (uint32_t)(k * kBlock) >= nvec) continue;
+                    if (lds) {
+                        // Runs of equal symbols in the group take one atomic
+                        // each (text has many short runs).
+                        uint32_t prev = (uint32_t)u[k].e[0], run = 1;
+                        zeros += tally(prev);
+#pragma unroll
+                        for (int j = 1; j < V; ++j) {
+                            const uint32_t x = (uint32_t)u[k].e[j];
+                            zeros += tally(x);
+                            if (x == prev) {
+                                ++run;
+                            } else {
+                                add_run(prev, run);
+                                prev = x;
+                                run = 1;
+                            }
+                        }
+                        add_run(prev, run);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < V; ++j) zeros += visit((uint32_t)u[k].e[j]);
+                    }
                 }
             }
         } else {
@@ -450,22 +466,38 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
     const bool d_lds = SCATTER && a.nD <= (uint64_t)kSmallD;
-    if (d_lds)
-        for (int i = tid; i < (int)a.nD; i += kBlock) s.D[i] = a.D[i];
-    if (SCATTER) count_init(s.ct, tid);
 
-    // 1. Coalesced 16-byte loads of the tile into LDS.
+    // 1. Coalesced 16-byte loads of the tile into LDS (a whole tile's loads
+    //    back to back, the node table after them, so the latencies overlap).
     TIN *stage_in = reinterpret_cast<TIN *>(s.stage);
     const TIN *in = reinterpret_cast<const TIN *>(a.in) + t0;
     if (len == (uint32_t)kTile) {
-#pragma unroll
-        for (int r = 0; r < kIt / V; ++r) {
-            int e = (r * kBlock + tid) * V;
-            *reinterpret_cast<uint4 *>(stage_in + e) = *reinterpret_cast<const uint4 *>(in + e);
+        // The node table's two loads (indices clamped into the table; LDS
+        // entries past nD are unused) go out first and land in LDS only after
+        // the tile's loads are issued: one wait covers all six.
+        // No branch around them (s.D is read only when the table is cached).
+        static_assert(kSmallD == 2 * kBlock, "node table fill is two steps");
+        uint64_t d0 = 0, d1 = 0;
+        if (SCATTER) {
+            const uint64_t last = a.nD - 1;
+            d0 = a.D[min((uint64_t)tid, last)];
+            d1 = a.D[min((uint64_t)(tid + kBlock), last)];
         }
+        uint4 q[kIt / V];
+#pragma unroll
+        for (int r = 0; r < kIt / V; ++r) q[r] = *reinterpret_cast<const uint4 *>(in + (r * kBlock + tid) * V);
+        if (SCATTER) {
+            s.D[tid] = d0;
+            s.D[tid + kBlock] = d1;
+        }
+#pragma unroll
+        for (int r = 0; r < kIt / V; ++r) *reinterpret_cast<uint4 *>(stage_in + (r * kBlock + tid) * V) = q[r];
     } else {
         for (uint32_t e = tid; e < len; e += kBlock) stage_in[e] = in[e];
+        if (d_lds)
+            for (int i = tid; i < (int)a.nD; i += kBlock) s.D[i] = a.D[i];
     }
+    if (SCATTER) count_init(s.ct, tid);
     // Flags uniform across the grid, tested once the tile's loads are in
     // flight (nothing has been written to global memory yet): the input was
     // rejected, or this level is left to the fused pass.
@@ -638,28 +670,35 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
     const uint32_t Z0 = (uint32_t)a.tile_prefix[tile];  // zeros of the level before this tile
-    if (SCATTER) {
-        for (int i = tid; i < (int)a.nD; i += kBlock) s.D[i] = (uint32_t)a.D[i];
-        count_init(s.ct, tid);
-    }
 
-    // Load: thread t, row r holds positions r*4096 + 16t .. +15.
+    // Load: thread t, row r holds positions r*4096 + 16t .. +15.  A whole
+    // tile's four loads are issued back to back (no branch between them),
+    // so their latencies overlap; the node table follows them.
     const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
     uint4 d[kRows];
     uint32_t m[kRows], z[kRows];
+    if (len == (uint32_t)kTile) {
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
-        if (p + 16 <= len) {
-            d[r] = *reinterpret_cast<const uint4 *>(in + p);
-        } else {
-            const uint32_t nv = clamp_count(len, p, 16u);
-            uint32_t w[4] = {0, 0, 0, 0};
+        for (int r = 0; r < kRows; ++r) d[r] = *reinterpret_cast<const uint4 *>(in + r * kRowBytes + 16 * tid);
+    } else {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
-            d[r] = make_uint4(w[0], w[1], w[2], w[3]);
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+            if (p + 16 <= len) {
+                d[r] = *reinterpret_cast<const uint4 *>(in + p);
+            } else {
+                const uint32_t nv = clamp_count(len, p, 16u);
+                uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+                d[r] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
         }
+    }
+    if (SCATTER) {  // byte symbols: at most 256 nodes' entries, one per thread
+        if ((uint64_t)tid < a.nD) s.D[tid] = (uint32_t)a.D[tid];
+        count_init(s.ct, tid);
     }
     // Grid-uniform flags, tested with the loads in flight and before any
     // global write: the input was rejected, or the fused pass owns this level.

@@ -220,6 +220,30 @@ __device__ __forceinline__ void pair_tile_u8(const PairArgs &a, uint32_t tile, L
     const uint32_t G0t = P.x, G1t = P.y, G2t = P.z, G3t = t0 - P.x - P.y - P.z;
     const uint32_t Z0 = G0t + G1t, O0 = t0 - Z0;
     const uint32_t nnodes = 1u << l;
+
+    // Load: thread t, row r holds positions r*4096 + 16t .. +15 (a whole
+    // tile's loads back to back, then the tables).
+    const uint8_t *in = a.in + t0;
+    uint4 d[kRows];
+    if (len == (uint32_t)kTile) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) d[r] = *reinterpret_cast<const uint4 *>(in + r * kRowBytes + 16 * tid);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+            if (p + 16 <= len) {
+                d[r] = *reinterpret_cast<const uint4 *>(in + p);
+            } else {
+                const uint32_t nv = clamp_count(len, p, 16u);
+                uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+                d[r] = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+    }
     for (int i = tid; i < (int)(2u * nnodes); i += kBlock) s.D0[i] = (uint32_t)a.D0[i];
     if (DIRS)
         for (int i = tid; i < (int)(4u * nnodes); i += kBlock) s.D1[i] = (uint32_t)a.D1[i];
@@ -229,24 +253,6 @@ __device__ __forceinline__ void pair_tile_u8(const PairArgs &a, uint32_t tile, L
         s.NS[i] = (uint32_t)a.C[c < a.sigma ? c : a.sigma];
     }
     if (SCATTER) count_init_t(ct, tid);
-
-    // Load: thread t, row r holds positions r*4096 + 16t .. +15.
-    const uint8_t *in = a.in + t0;
-    uint4 d[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
-        if (p + 16 <= len) {
-            d[r] = *reinterpret_cast<const uint4 *>(in + p);
-        } else {
-            const uint32_t nv = clamp_count(len, p, 16u);
-            uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
-            d[r] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-    }
     if (*a.status) return;  // grid-uniform: the input was rejected (nothing written yet)
 
     uint32_t m[kRows], z[kRows], zl[kRows];
