@@ -57,6 +57,17 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_select_tree.restype = ctypes.c_int64
     lib.oracle_select_tree.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_uint64]
+    lib.oracle_build_matrix.restype = ctypes.c_int
+    lib.oracle_build_matrix.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                        _u64p, _u64p]
+    lib.oracle_access_matrix.restype = ctypes.c_uint64
+    lib.oracle_access_matrix.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.oracle_rank_matrix.restype = ctypes.c_uint64
+    lib.oracle_rank_matrix.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                       ctypes.c_uint64]
+    lib.oracle_select_matrix.restype = ctypes.c_int64
+    lib.oracle_select_matrix.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64]
     return lib
 
 
@@ -165,3 +176,54 @@ def rank_tree(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
 def select_tree(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
     bits, C = _tree_args(t)
     return int(load(lib_path).oracle_select_tree(_ptr(bits), _ptr(C), t["n"], t["sigma"], c, k))
+
+
+# ---- wavelet matrix ----------------------------------------------------------
+
+def build_matrix(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """Wavelet matrix bits and per-level zero counts:
+    {'L', 'W', 'n', 'sigma', 'bits' (L, W) uint64, 'zeros' (L,) uint64}."""
+    lib = load(lib_path)
+    S = np.ascontiguousarray(S)
+    n = int(S.shape[0])
+    L = int(lib.oracle_levels(sigma))
+    W = (n + 63) // 64
+    bits = np.zeros(max(L * W, 1), dtype=np.uint64)
+    zeros = np.zeros(max(L, 1), dtype=np.uint64)
+    rc = lib.oracle_build_matrix(S.ctypes.data_as(ctypes.c_void_p), n, sigma, sym_bytes_of(S), _ptr(bits),
+                                 _ptr(zeros))
+    if rc != 0:
+        raise OracleError(f"oracle_build_matrix returned {rc}")
+    return {"L": L, "W": W, "n": n, "sigma": sigma, "bits": bits[: L * W].reshape(L, W), "zeros": zeros[:L]}
+
+
+def build_matrix_all(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """Wavelet matrix with the directories of its level bitmaps."""
+    t = build_matrix(S, sigma, lib_path)
+    t.update(rank_select(t["bits"], t["n"], t["L"], lib_path))
+    return t
+
+
+def _matrix_args(t: dict):
+    bits = np.ascontiguousarray(t["bits"], dtype=np.uint64).reshape(-1)
+    if bits.size == 0:
+        bits = np.zeros(1, dtype=np.uint64)
+    zeros = np.ascontiguousarray(t["zeros"], dtype=np.uint64)
+    if zeros.size == 0:
+        zeros = np.zeros(1, dtype=np.uint64)
+    return bits, zeros
+
+
+def access_matrix(t: dict, i: int, lib_path: str = LIB) -> int:
+    bits, zeros = _matrix_args(t)
+    return int(load(lib_path).oracle_access_matrix(_ptr(bits), _ptr(zeros), t["n"], t["sigma"], i))
+
+
+def rank_matrix(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
+    bits, zeros = _matrix_args(t)
+    return int(load(lib_path).oracle_rank_matrix(_ptr(bits), _ptr(zeros), t["n"], t["sigma"], c, i))
+
+
+def select_matrix(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
+    bits, zeros = _matrix_args(t)
+    return int(load(lib_path).oracle_select_matrix(_ptr(bits), _ptr(zeros), t["n"], t["sigma"], c, k))

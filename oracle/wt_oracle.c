@@ -18,6 +18,10 @@
  *   - directories against a naive Python popcount / scan;
  *   - tree-walking access/rank/select against naive counting over S;
  *   - hand-derived fixtures under tests/golden/;
+ *   - wavelet matrix: its sort view (level l is S stably sorted by the
+ *     reverse of its top l bits), per-level zero counts by numpy, equality
+ *     with the tree for sigma <= 2, and matrix-walking queries against
+ *     naive counting;
  *   - planted mutants of this file (ORACLE_MUTANT) must fail those pins.
  *
  * Readings where the paper is silent are listed next to the code below.
@@ -413,4 +417,146 @@ int64_t oracle_select_tree(const uint64_t *bits, const uint64_t *C, uint64_t n,
         r = j - a;
     }
     return (int64_t)r;
+}
+
+/* ---- wavelet matrix (the variant described with the paper's extensions) ---
+ * One bitmap per level and no nodes.  Level 0 lists the symbols in input
+ * order.  Level l+1 lists level l's symbols with those whose bit (L-1-l) is
+ * 0 first and those whose bit is 1 after, each group in its level-l order.
+ * The bitmap of level l holds bit (L-1-l) of level l's symbols, and level l
+ * keeps its number of 0s, zeros[l].  Written from that definition: one pass
+ * to set the bits and count the 0s, two passes for the stable split. */
+int oracle_build_matrix(const void *S, uint64_t n, uint64_t sigma, int sym_bytes,
+                        uint64_t *bits, uint64_t *zeros)
+{
+    uint32_t L;
+    uint64_t W = (n + 63) / 64;
+    uint64_t *cur, *nxt;
+    if (sigma == 0 || (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4))
+        return OR_ERR_ARG;
+    L = oracle_levels(sigma);
+    cur = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    nxt = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!cur || !nxt) {
+        free(cur);
+        free(nxt);
+        return OR_ERR_NOMEM;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        cur[i] = sym_at(S, sym_bytes, i);
+        if (cur[i] >= sigma) {
+            free(cur);
+            free(nxt);
+            return OR_ERR_SYMBOL;
+        }
+    }
+    if (L && W)
+        memset(bits, 0, (size_t)(L * W) * sizeof(uint64_t));
+    for (uint32_t l = 0; l < L; l++) {
+        uint32_t k = L - 1 - l;
+        uint64_t *B = bits + (uint64_t)l * W;
+        uint64_t z = 0, o = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            if ((cur[i] >> k) & 1)
+                set_bit(B, i);
+            else
+                z++;
+        }
+        zeros[l] = z;
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 6
+        /* planted mistake: the 1s of the level placed first */
+        for (uint64_t i = 0; i < n; i++)
+            if ((cur[i] >> k) & 1)
+                nxt[o++] = cur[i];
+        for (uint64_t i = 0; i < n; i++)
+            if (!((cur[i] >> k) & 1))
+                nxt[o++] = cur[i];
+#else
+        for (uint64_t i = 0; i < n; i++)
+            if (!((cur[i] >> k) & 1))
+                nxt[o++] = cur[i];
+        for (uint64_t i = 0; i < n; i++)
+            if ((cur[i] >> k) & 1)
+                nxt[o++] = cur[i];
+#endif
+        { uint64_t *t = cur; cur = nxt; nxt = t; }
+    }
+    free(cur);
+    free(nxt);
+    return OR_OK;
+}
+
+/* Matrix-walking queries over the oracle's own bits and zeros, counting bits
+ * one at a time.  A position p of level l moves to level l+1 as the number
+ * of 0s before it (its bit is 0) or zeros[l] + the number of 1s before it. */
+static uint64_t matrix_next(const uint64_t *B, uint64_t z, uint64_t p, int b)
+{
+    uint64_t ones = count_ones(B, 0, p);
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 7
+    /* planted mistake: a 1 moves to its rank among the 1s, without zeros[l] */
+    (void)z;
+    return b ? ones : p - ones;
+#else
+    return b ? z + ones : p - ones;
+#endif
+}
+
+uint64_t oracle_access_matrix(const uint64_t *bits, const uint64_t *zeros, uint64_t n,
+                              uint64_t sigma, uint64_t i)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64, c = 0, p = i;
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        int b = get_bit(B, p);
+        c = (c << 1) | (uint64_t)b;
+        p = matrix_next(B, zeros[l], p, b);
+    }
+    return c;
+}
+
+/* [s, e) is, at every level, the run of positions holding the symbols whose
+ * top bits so far match c's (s: where that run starts, e: just past the ones
+ * that came from S[0, i)). */
+uint64_t oracle_rank_matrix(const uint64_t *bits, const uint64_t *zeros, uint64_t n,
+                            uint64_t sigma, uint64_t c, uint64_t i)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64, s = 0, e;
+    if (c >= sigma)
+        return 0;
+    e = i > n ? n : i;
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        int b = (int)((c >> (L - 1 - l)) & 1);
+        s = matrix_next(B, zeros[l], s, b);
+        e = matrix_next(B, zeros[l], e, b);
+    }
+    return e - s;
+}
+
+/* Descend to the run of c on the last level, take its k-th position, and
+ * climb back with the k-th 0 or 1 of each level. */
+int64_t oracle_select_matrix(const uint64_t *bits, const uint64_t *zeros, uint64_t n,
+                             uint64_t sigma, uint64_t c, uint64_t k)
+{
+    uint32_t L = oracle_levels(sigma);
+    uint64_t W = (n + 63) / 64, s = 0, e = n, p;
+    if (c >= sigma || k == 0)
+        return -1;
+    for (uint32_t l = 0; l < L; l++) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        int b = (int)((c >> (L - 1 - l)) & 1);
+        s = matrix_next(B, zeros[l], s, b);
+        e = matrix_next(B, zeros[l], e, b);
+    }
+    if (k > e - s)
+        return -1;
+    p = s + k - 1;
+    for (uint32_t l = L; l-- > 0;) {
+        const uint64_t *B = bits + (uint64_t)l * W;
+        int b = (int)((c >> (L - 1 - l)) & 1);
+        p = scan_select(B, 0, n, b, b ? p - zeros[l] : p);
+    }
+    return (int64_t)p;
 }

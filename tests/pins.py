@@ -11,6 +11,11 @@ paper or the mathematics fixes.
                   the left child's zeros end.
   directories     rank/select samples by a cumulative count over the bits.
   queries         naive counting over S.
+  matrix levels   the wavelet matrix's sort view (the paper's extensions):
+                  level l lists S stably sorted by the reverse of its top l
+                  bits, and its bitmap holds bit L-1-l of that order.
+  matrix zeros    the zeros of matrix level l = number of symbols whose bit
+                  L-1-l is 0.
 """
 from __future__ import annotations
 
@@ -144,3 +149,60 @@ def naive_select(S: np.ndarray, c: int, k: int) -> int:
         return -1
     pos = np.flatnonzero(S == c)
     return int(pos[k - 1]) if k <= pos.size else -1
+
+
+def matrix_key(s: int, l: int, L: int) -> int:
+    """The top l bits of s read in reverse: bit L-1 weighs 1, bit L-l weighs 2^(l-1)."""
+    return sum(((s >> (L - 1 - j)) & 1) << j for j in range(l))
+
+
+def matrix_levels_py(S, sigma: int):
+    """Wavelet matrix levels by pure-Python stable ``sorted`` (tiny inputs)."""
+    L = levels(sigma)
+    out = []
+    for l in range(L):
+        T = sorted(S, key=lambda s: matrix_key(s, l, L))
+        out.append([(s >> (L - 1 - l)) & 1 for s in T])
+    return out
+
+
+def matrix_levels_np(S: np.ndarray, sigma: int) -> list[np.ndarray]:
+    """The same with numpy: the key is built bit by bit, then stably argsorted."""
+    L = levels(sigma)
+    S64 = S.astype(np.uint64)
+    out = []
+    for l in range(L):
+        key = np.zeros(S.shape[0], dtype=np.uint64)
+        for j in range(l):
+            key |= ((S64 >> np.uint64(L - 1 - j)) & np.uint64(1)) << np.uint64(j)
+        order = np.argsort(key, kind="stable")
+        out.append(((S64[order] >> np.uint64(L - 1 - l)) & np.uint64(1)).astype(np.uint8))
+    return out
+
+
+def check_matrix(t: dict, S: np.ndarray, sigma: int, expected_levels=None) -> list[str]:
+    """Names of the pins that the wavelet matrix ``t`` ({'bits','zeros',...}) fails."""
+    fails = []
+    n = S.shape[0]
+    L = levels(sigma)
+    if expected_levels is None:
+        expected_levels = matrix_levels_np(S, sigma) if n > 64 else matrix_levels_py(list(map(int, S)), sigma)
+    bits = np.asarray(t["bits"]).reshape(L, -1) if L else np.zeros((0, 0), dtype=np.uint64)
+    for l in range(L):
+        if not np.array_equal(bits[l], pack(expected_levels[l], n)):
+            fails.append(f"matrix_level{l}")
+            break
+    S64 = S.astype(np.uint64)
+    zeros = np.asarray(t["zeros"], dtype=np.uint64).reshape(-1)[:L]
+    for l in range(L):
+        want = int(np.count_nonzero(((S64 >> np.uint64(L - 1 - l)) & np.uint64(1)) == 0))
+        if int(zeros[l]) != want:
+            fails.append(f"matrix_zeros{l}")
+            break
+    if "rank" in t:
+        want = naive_dirs([unpack(bits[l], n) for l in range(L)], n)
+        for key in ("rank", "sel1", "sel0", "sel_counts"):
+            got = np.asarray(t[key], dtype=np.uint64).reshape(want[key].shape)
+            if not np.array_equal(got, want[key]):
+                fails.append(f"matrix_dirs_{key}")
+    return fails

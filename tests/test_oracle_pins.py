@@ -178,3 +178,99 @@ def test_pins_catch_planted_mutants(tmp_path):
         path = str(tmp_path / f"liboracle_m{m}.so")
         oracle.compile_oracle(path, mutant=m)
         assert _pin_failures(path), f"mutant {m} passed every pin"
+
+
+# ---- wavelet matrix -----------------------------------------------------------
+
+def matrix_query_failures(t, S, sigma, lib_path=oracle.LIB):
+    """Exhaustive matrix-walking queries against naive counting over S."""
+    n = S.shape[0]
+    for i in range(n):
+        if oracle.access_matrix(t, i, lib_path) != int(S[i]):
+            return ["access_matrix"]
+    for c in range(sigma + 1):
+        for i in range(n + 1):
+            if oracle.rank_matrix(t, c, i, lib_path) != pins.naive_rank(S, c, i):
+                return ["rank_matrix"]
+        for k in range(n + 2):
+            if oracle.select_matrix(t, c, k, lib_path) != pins.naive_select(S, c, k):
+                return ["select_matrix"]
+    return []
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 3, 4, 5])
+def test_matrix_exhaustive_tiny(sigma):
+    """Every sequence of length <= 4 (<= 5 for sigma <= 3): the sort view,
+    the zero counts, the directories and every query."""
+    for n in range(0, 6 if sigma <= 3 else 5):
+        for seq in itertools.product(range(sigma), repeat=n):
+            S = np.asarray(seq, dtype=np.uint8)
+            t = oracle.build_matrix_all(S, sigma)
+            assert pins.check_matrix(t, S, sigma) == [], (seq, sigma)
+            assert matrix_query_failures(t, S, sigma) == [], (seq, sigma)
+
+
+@pytest.mark.parametrize("sigma", [6, 7, 8, 9, 16, 17])
+def test_matrix_exhaustive_short_wider(sigma):
+    for n in range(0, 4):
+        for seq in itertools.product(range(sigma), repeat=n):
+            S = np.asarray(seq, dtype=np.uint8)
+            t = oracle.build_matrix_all(S, sigma)
+            assert pins.check_matrix(t, S, sigma) == [], (seq, sigma)
+            assert matrix_query_failures(t, S, sigma) == [], (seq, sigma)
+
+
+@pytest.mark.parametrize("n,sigma,seed", [(1000, 256, 1), (70000, 256, 2), (33333, 5, 3), (20000, 1 << 16, 4),
+                                          (9000, (1 << 20) + 7, 5), (4097, 300, 6)])
+def test_matrix_random_medium(n, sigma, seed):
+    rng = np.random.default_rng(seed)
+    S = rng.integers(0, sigma, n).astype(_dtype(sigma))
+    t = oracle.build_matrix_all(S, sigma)
+    assert pins.check_matrix(t, S, sigma) == []
+    for _ in range(40):
+        i = int(rng.integers(0, n))
+        assert oracle.access_matrix(t, i) == int(S[i])
+        c = int(S[int(rng.integers(0, n))])
+        j = int(rng.integers(0, n + 1))
+        assert oracle.rank_matrix(t, c, j) == pins.naive_rank(S, c, j)
+        k = int(rng.integers(1, pins.naive_rank(S, c, n) + 2))
+        assert oracle.select_matrix(t, c, k) == pins.naive_select(S, c, k)
+
+
+def test_matrix_equals_tree_for_binary_alphabets():
+    """With one level (sigma = 2) the matrix and the tree hold the same bits;
+    sigma = 1 has no levels at all."""
+    rng = np.random.default_rng(21)
+    for n in (0, 1, 63, 64, 65, 5000):
+        S = rng.integers(0, 2, n).astype(np.uint8)
+        m, tr = oracle.build_matrix(S, 2), oracle.build(S, 2)
+        assert np.array_equal(m["bits"], tr["bits"])
+        assert int(m["zeros"][0]) == int(n - S.sum())
+        m1 = oracle.build_matrix(np.zeros(n, np.uint8), 1)
+        assert m1["L"] == 0 and m1["bits"].size == 0
+
+
+def test_matrix_rejects_symbols():
+    with pytest.raises(oracle.OracleError):
+        oracle.build_matrix(np.asarray([0, 5], dtype=np.uint8), 5)
+
+
+def _matrix_pin_failures(lib_path):
+    fails = set()
+    rng = np.random.default_rng(14)
+    cases = [(np.asarray(c, dtype=np.uint8), s) for c, s in [([3, 1, 0, 2, 3, 0, 1, 2], 4), ([4, 0, 3, 1, 4, 2], 5)]]
+    cases.append((rng.integers(0, 256, 5000).astype(np.uint8), 256))
+    for S, sigma in cases:
+        t = oracle.build_matrix_all(S, sigma, lib_path)
+        fails.update(pins.check_matrix(t, S, sigma))
+        if S.size <= 8:
+            fails.update(matrix_query_failures(t, S, sigma, lib_path))
+    return fails
+
+
+def test_matrix_pins_catch_planted_mutants(tmp_path):
+    assert _matrix_pin_failures(oracle.LIB) == set()
+    for m in (6, 7):
+        path = str(tmp_path / f"liboracle_m{m}.so")
+        oracle.compile_oracle(path, mutant=m)
+        assert _matrix_pin_failures(path), f"mutant {m} passed every matrix pin"
