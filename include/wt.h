@@ -143,6 +143,40 @@ int wt_select(const wt_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64
               int64_t *d_out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Wavelet matrix (the variant described with the paper's extensions to
+ * levelWT): one bitmap per level and no nodes.  Level 0 lists S in input
+ * order; level l+1 lists level l's symbols with bit L-1-l equal to 0 first
+ * and equal to 1 after, each group in its level-l order (a stable split of
+ * the whole level).  The bitmap of level l holds bit L-1-l of level l's
+ * symbols (LSB-first 64-bit words, levels contiguous, as for the tree), and
+ * zeros[l] is its number of 0s.
+ *
+ * wt_build_matrix takes the arguments of wt_build (the same wt_plan layout
+ * and scratch; out->C receives C as well, which the matrix queries do not
+ * need) plus d_zeros (device, L uint64; may be NULL only when L = 0).  The
+ * directories, when requested, are those of the tree's format over the
+ * matrix's bitmaps.  Data errors as for wt_build (wt_status_get). */
+int wt_build_matrix(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                    uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream);
+
+typedef struct {
+    const uint64_t *bits, *zeros, *rank, *sel1, *sel0, *sel_counts;  /* device */
+    uint64_t n, sigma;
+    uint32_t L;
+} wt_matrix_view;
+
+/* Queries on a wavelet matrix built with directories; the same conventions
+ * as wt_access / wt_rank / wt_select (rank counts [0, i); select is 1-based
+ * and gives -1 when there is no such occurrence; access of i >= n gives
+ * 0xFFFFFFFF).  A position p of level l continues on level l+1 at the number
+ * of 0s before it (bit 0) or at zeros[l] plus the number of 1s before it. */
+int wt_matrix_access(const wt_matrix_view *m, const uint64_t *d_i, uint64_t count, uint32_t *d_sym, void *stream);
+int wt_matrix_rank(const wt_matrix_view *m, const uint32_t *d_c, const uint64_t *d_i, uint64_t count,
+                   uint64_t *d_out, void *stream);
+int wt_matrix_select(const wt_matrix_view *m, const uint32_t *d_c, const uint64_t *d_k, uint64_t count,
+                     int64_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched construction: many sequences of uneven length and alphabet, each
  * built exactly as wt_build builds it (levelWT, Fig. 1), by one kernel that
  * takes work items from a per-level queue: histogram tiles of every job,

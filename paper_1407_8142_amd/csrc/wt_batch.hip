@@ -390,6 +390,7 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
     a.k = j.L - 1 - l;
     a.level = l;
     a.fused_l0 = j.ctl + kCtlFusedL0;
+    a.qmask = ~0u;
     if (win == 1) {
         if constexpr ((KINDS & kHasLevel8) != 0) {
             if (scatter) level_tile_u8<true, true>(a, tile, s.u8);

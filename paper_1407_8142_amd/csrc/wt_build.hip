@@ -464,6 +464,20 @@ __global__ __launch_bounds__(kScanThreads) void pair_prefix_scan(const uint64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Wavelet matrix tables: every level is one node, so its table is {0 ones
+// before the node, the level's zeros}.  A level's zeros are those of the
+// tree's same level (the same bit of the same symbols): the last entry of
+// the tree table D_l.
+__global__ void matrix_tables(const uint64_t *D, uint32_t L, uint64_t *Dm, uint64_t *zeros) {
+    const uint32_t l = threadIdx.x;
+    if (l >= L) return;
+    const uint64_t z = D[(2ull << l) - 2 + (2ull << l) - 1];
+    Dm[2 * l] = 0;
+    Dm[2 * l + 1] = z;
+    zeros[l] = z;
+}
+
+// ---------------------------------------------------------------------------
 // Directory tails of every level (grid.y = level).  The level totals come
 // either from the node tables (zeros of a level = D_l's last entry) or from
 // an array of per-level totals.
@@ -518,7 +532,7 @@ struct Plan {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
-    uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_S0, off_S1, total;
+    uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_M, off_S0, off_S1, total;
     uint64_t n_part;
 };
 
@@ -561,6 +575,8 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     o = align_up(o + 8ull * p.n_part, 256);
     p.off_E = o;  // two-level pass tables (byte alphabets: at most 4 x 256 u32)
     o += p.L >= 2 && p.L <= 8 ? kPairTableBytes : 0;
+    p.off_M = o;  // wavelet matrix: {0, zeros of level l} per level
+    o = align_up(o + 16ull * p.L, 256);
     p.off_S0 = o;
     const uint64_t sbytes = p.L >= 2 ? align_up(n * p.mid_bytes, 256) : 0;
     o += sbytes;
@@ -845,6 +861,7 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
             a.k = 0;
             a.level = l;
             a.fused_l0 = nullptr;
+            a.qmask = ~0u;
             if (g_timing && (rc = timing_begin(s, ev))) return rc;
             launch_level_any(1, 1, false, dirs, s, a);
             if (g_timing && (rc = timing_end(s, ev))) return rc;
@@ -854,8 +871,11 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
     return WT_OK;
 }
 
-extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
-                        void *d_scratch, uint64_t scratch_bytes, void *stream) {
+// The wavelet tree (matrix = false) or the wavelet matrix (matrix = true:
+// every level one node, split with D_l = {0, zeros of the level}; no fused
+// or paired levels; the zero counts also go to d_zeros).
+static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                      bool matrix, uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream) {
     Plan p;
     int rc = make_plan(n, sigma, sym_bytes, p);
     if (rc) return rc;
@@ -872,6 +892,7 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     uint64_t *pre = (uint64_t *)(sc + p.off_pre);
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint64_t *part = (uint64_t *)(sc + p.off_part);
+    uint64_t *Dm = (uint64_t *)(sc + p.off_M);
 
     // Fused tail levels need the directories (they write their entries) and
     // at least one split to save.  The 2^l nodes of level l share n symbols,
@@ -880,10 +901,10 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
     // passes without the per-tile check of the fused level.
     uint32_t lmin = 0;
     while (lmin < 63 && cdiv(n, 1ull << lmin) > fused_half(p.mid_bytes)) ++lmin;
-    const bool fuse = g_fuse && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
+    const bool fuse = g_fuse && !matrix && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
     // Two levels per pass: byte symbols in and between levels, nothing fused
     // (inputs too small for that are the fused pass's), 32-bit positions.
-    const bool pairs = g_pairs && !fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
+    const bool pairs = g_pairs && !matrix && !fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
                        n < (1ull << 32);
 
     // Zero: status + per-tile zero counts (one contiguous range), and C.
@@ -925,6 +946,7 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
             dir_finish<<<g, kBlock, 0, s>>>(D, nullptr, n, p.L, out->rank, p.rank_len, out->sel1, out->sel0, p.cap,
                                             out->sel_counts);
         }
+        if (matrix) matrix_tables<<<1, kWave, 0, s>>>(D, p.L, Dm, d_zeros);
     }
     uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
     if (fuse) {
@@ -949,8 +971,8 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         a.in = cur;
         a.out = scatter ? dst : nullptr;
         a.bits = out->bits + (uint64_t)l * p.W;
-        a.D = D + ((2ull << l) - 2);
-        a.nD = 2ull << l;
+        a.D = matrix ? Dm + 2ull * l : D + ((2ull << l) - 2);
+        a.nD = matrix ? 2ull : 2ull << l;
         a.tile_prefix = pre + (uint64_t)l * p.T;
         a.next_cnt = scatter ? cnt + (uint64_t)(l + 1) * p.T : nullptr;
         a.next_shift = tile_shift_for(p.mid_bytes);
@@ -962,6 +984,7 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         a.k = p.L - 1 - l;
         a.level = l;
         a.fused_l0 = (fuse && l >= lmin) ? fused_l0 : nullptr;
+        a.qmask = matrix ? 1u : ~0u;
         std::pair<hipEvent_t, hipEvent_t> ev;
         if (g_timing && (rc = timing_begin(s, ev))) return rc;
         launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);
@@ -993,6 +1016,17 @@ extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_b
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     }
     return WT_OK;
+}
+
+extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                        void *d_scratch, uint64_t scratch_bytes, void *stream) {
+    return build_impl(d_seq, n, sigma, sym_bytes, out, false, nullptr, d_scratch, scratch_bytes, stream);
+}
+
+extern "C" int wt_build_matrix(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                               uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream) {
+    if (!d_zeros && levels_of(sigma) > 0) return WT_ERR_ARG;
+    return build_impl(d_seq, n, sigma, sym_bytes, out, true, d_zeros, d_scratch, scratch_bytes, stream);
 }
 
 extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t L, uint64_t *d_rank,

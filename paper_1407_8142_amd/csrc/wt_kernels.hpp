@@ -379,6 +379,8 @@ struct LevelArgs {
     uint32_t k;              // bit examined at this level: L-1-l
     uint32_t level;          // l
     const uint32_t *fused_l0;  // levels >= *fused_l0 are done by the fused pass (NULL: none)
+    uint32_t qmask;          // node index = (symbol >> k) & qmask: ~0 for the tree (node and bit),
+                             // 1 for the wavelet matrix (one node per level, D = {0, zeros})
 };
 
 // Count-ahead: while level l scatters S_{l+1}, it also counts, for every tile
@@ -597,7 +599,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
         uint32_t sp = (uint32_t)(r * kBlock + tid);
         if (sp < len) {
             TOUT v = stage_out[sp];
-            uint64_t q = (uint64_t)((uint32_t)v >> k);
+            uint64_t q = (uint64_t)(((uint32_t)v >> k) & a.qmask);
             if (q < a.nD) {
                 uint64_t base = d_lds ? s.D[q] : a.D[q];
                 uint64_t dest = base + (sp < Zt ? Z0 + sp : O0 + (sp - Zt));
@@ -808,7 +810,7 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
         const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
         if (sl >= len) continue;
         const uint4 v = s_st128[j];
-        const uint32_t q0 = (v.x & 0xFFu) >> k, q15 = (v.w >> 24) >> k;
+        const uint32_t q0 = ((v.x & 0xFFu) >> k) & a.qmask, q15 = ((v.w >> 24) >> k) & a.qmask;
         if (sl + 15 < len && q0 == q15) {
             // One run: the bit is the low bit of q, so the region is uniform too.
             const uint32_t dest = s.D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
@@ -829,7 +831,7 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
             // Several runs meet here (or the tile ends): byte by byte.
             const uint32_t nc = clamp_count(len, sl, 16u);
             for (uint32_t c = 0; c < nc; ++c) {
-                const uint32_t bc = byte_of(v, (int)c), qc = bc >> k, sc = sl + c;
+                const uint32_t bc = byte_of(v, (int)c), qc = (bc >> k) & a.qmask, sc = sl + c;
                 const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
                 if (dest < a.n) {
                     out[dest] = (uint8_t)bc;

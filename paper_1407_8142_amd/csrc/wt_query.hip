@@ -1,4 +1,5 @@
-// Batched access / rank / select on a built levelwise wavelet tree
+// Batched access / rank / select on a built levelwise wavelet tree (and on
+// a wavelet matrix, further down)
 // (queries as defined in "Preliminaries"; tree walks without parent/child
 // pointers: node offsets come from C, in-node positions from rank/select on
 // the level bitmaps).  One thread per query; each query takes L dependent
@@ -174,6 +175,100 @@ __global__ void multi_kernel(const wt_view *views, uint32_t ntrees, const uint32
     }
 }
 
+// ---- wavelet matrix (TreeDev with C unused and zeros[l] per level) ----
+// Position p of level l continues on level l+1 at rank0(p), or at
+// zeros[l] + rank1(p) when its bit is 1.
+__device__ __forceinline__ uint64_t matrix_next(const TreeDev &t, const uint64_t *zeros, uint32_t l, uint64_t p,
+                                                uint32_t b) {
+    const uint64_t ones = rank1(t, l, p);
+    return b ? zeros[l] + ones : p - ones;
+}
+
+__device__ __forceinline__ uint32_t matrix_access_one(const TreeDev &t, const uint64_t *zeros, uint64_t j) {
+    uint32_t c = 0;
+    for (uint32_t l = 0; l < t.L; ++l) {
+        const uint32_t b = (uint32_t)((t.bits[(uint64_t)l * t.W + (j >> 6)] >> (j & 63)) & 1ull);
+        c = (c << 1) | b;
+        j = matrix_next(t, zeros, l, j, b);
+        if (j >= t.n && l + 1 < t.L) break;  // unreachable for a well-formed matrix
+    }
+    return c;
+}
+
+// [s, e): the run of level l holding the symbols whose top bits so far are
+// c's, from its start (s) to just past those that came from S[0, i) (e).
+__device__ __forceinline__ void matrix_descend(const TreeDev &t, const uint64_t *zeros, uint64_t c, uint64_t &s,
+                                               uint64_t &e) {
+    for (uint32_t l = 0; l < t.L; ++l) {
+        const uint32_t b = (uint32_t)((c >> (t.L - 1 - l)) & 1u);
+        s = matrix_next(t, zeros, l, s, b);
+        e = matrix_next(t, zeros, l, e, b);
+    }
+}
+
+__device__ __forceinline__ uint64_t matrix_rank_one(const TreeDev &t, const uint64_t *zeros, uint64_t c,
+                                                    uint64_t i) {
+    uint64_t s = 0, e = i;
+    matrix_descend(t, zeros, c, s, e);
+    return e - s;
+}
+
+__device__ __forceinline__ int64_t matrix_select_one(const TreeDev &t, const uint64_t *zeros, uint64_t c,
+                                                     uint64_t kk) {
+    if (c >= t.sigma || kk == 0) return -1;
+    uint64_t s = 0, e = t.n;
+    matrix_descend(t, zeros, c, s, e);
+    if (kk > e - s) return -1;
+    uint64_t p = s + kk - 1;
+    for (uint32_t l = t.L; l-- > 0;) {
+        const uint32_t b = (uint32_t)((c >> (t.L - 1 - l)) & 1u);
+        p = select_b(t, l, b, b ? p - zeros[l] : p);
+        if (p >= t.n) return -1;  // unreachable for a well-formed matrix
+    }
+    return (int64_t)p;
+}
+
+__global__ void matrix_access_kernel(TreeDev t, const uint64_t *zeros, const uint64_t *qi, uint64_t m,
+                                     uint32_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t j = qi[q];
+    out[q] = j >= t.n ? 0xFFFFFFFFu : matrix_access_one(t, zeros, j);
+}
+
+__global__ void matrix_rank_kernel(TreeDev t, const uint64_t *zeros, const uint32_t *qc, const uint64_t *qi,
+                                   uint64_t m, uint64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t c = qc[q], i = min(qi[q], t.n);
+    out[q] = c >= t.sigma ? 0 : matrix_rank_one(t, zeros, c, i);
+}
+
+__global__ void matrix_select_kernel(TreeDev t, const uint64_t *zeros, const uint32_t *qc, const uint64_t *qk,
+                                     uint64_t m, int64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    out[q] = matrix_select_one(t, zeros, qc[q], qk[q]);
+}
+
+static bool make_matrix(const wt_matrix_view *v, TreeDev &t) {
+    if (!v) return false;
+    if (v->L > 0 && (!v->zeros || (v->n > 0 && (!v->bits || !v->rank || !v->sel1 || !v->sel0)))) return false;
+    t.bits = v->bits;
+    t.C = nullptr;
+    t.rank = v->rank;
+    t.sel1 = v->sel1;
+    t.sel0 = v->sel0;
+    t.sel_counts = v->sel_counts;
+    t.n = v->n;
+    t.sigma = v->sigma;
+    t.L = v->L;
+    t.W = (v->n + 63) / 64;
+    t.rank_len = (v->n + WT_RANK_BLOCK_BITS - 1) / WT_RANK_BLOCK_BITS + 1;
+    t.cap = (v->n + WT_SELECT_SAMPLE - 1) / WT_SELECT_SAMPLE + 1;
+    return true;
+}
+
 static bool make_tree(const wt_view *v, TreeDev &t) {
     if (!v || !v->C) return false;
     if (v->L > 0 && v->n > 0 && (!v->bits || !v->rank || !v->sel1 || !v->sel0)) return false;
@@ -234,5 +329,38 @@ extern "C" int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uin
     if (!d_views || !d_tree || !d_kind || !d_a || !d_b || !d_out) return WT_ERR_ARG;
     multi_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
         d_views, ntrees, d_tree, d_kind, d_a, d_b, m, d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_matrix_access(const wt_matrix_view *v, const uint64_t *d_i, uint64_t m, uint32_t *d_sym,
+                                void *stream) {
+    TreeDev t;
+    if (!make_matrix(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_i || !d_sym) return WT_ERR_ARG;
+    matrix_access_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
+        t, v->zeros, d_i, m, d_sym);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_matrix_rank(const wt_matrix_view *v, const uint32_t *d_c, const uint64_t *d_i, uint64_t m,
+                              uint64_t *d_out, void *stream) {
+    TreeDev t;
+    if (!make_matrix(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_i || !d_out) return WT_ERR_ARG;
+    matrix_rank_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
+        t, v->zeros, d_c, d_i, m, d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_matrix_select(const wt_matrix_view *v, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
+                                int64_t *d_out, void *stream) {
+    TreeDev t;
+    if (!make_matrix(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
+    matrix_select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
+        t, v->zeros, d_c, d_k, m, d_out);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }

@@ -26,7 +26,8 @@ SELECT_SAMPLE = 4096
 EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratch_bytes", "wt_status_get",
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
            "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
-           "wt_set_sliced_histogram", "wt_set_level_pairs"]
+           "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
+           "wt_matrix_rank", "wt_matrix_select"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -51,6 +52,12 @@ class Outputs(ctypes.Structure):
 
 class View(ctypes.Structure):
     _fields_ = [("bits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32)]
+
+
+class MatrixView(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("zeros", ctypes.c_void_p), ("rank", ctypes.c_void_p),
                 ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32)]
 
@@ -106,10 +113,15 @@ def lib() -> ctypes.CDLL:
         L.wt_set_fused_levels.argtypes = [i32]
         L.wt_set_sliced_histogram.argtypes = [i32]
         L.wt_set_level_pairs.argtypes = [i32]
+        L.wt_build_matrix.argtypes = [vp, u64, u64, i32, ctypes.POINTER(Outputs), vp, vp, u64, vp]
+        L.wt_matrix_access.argtypes = [ctypes.POINTER(MatrixView), vp, u64, vp, vp]
+        L.wt_matrix_rank.argtypes = [ctypes.POINTER(MatrixView), vp, vp, u64, vp, vp]
+        L.wt_matrix_select.argtypes = [ctypes.POINTER(MatrixView), vp, vp, u64, vp, vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
                   "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
-                  "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs"):
+                  "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix",
+                  "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -236,6 +248,87 @@ class WaveletTree:
         u = lambda t: None if t is None else t.cpu().numpy().view(np.uint64)
         return {"L": self.L, "n": self.n, "sigma": self.sigma, "bits": u(self.bits), "C": u(self.C),
                 "rank": u(self.rank), "sel1": u(self.sel1), "sel0": u(self.sel0), "sel_counts": u(self.sel_counts)}
+
+
+@dataclass
+class WaveletMatrix:
+    """Device buffers of one built wavelet matrix: the tree's buffers plus the
+    per-level zero counts (C is produced too; the queries do not use it)."""
+    tree: WaveletTree
+    zeros: torch.Tensor
+
+    @staticmethod
+    def allocate(n: int, sigma: int, sym_bytes: int, directories: bool = True, device="cuda") -> "WaveletMatrix":
+        t = WaveletTree.allocate(n, sigma, sym_bytes, directories, device)
+        return WaveletMatrix(t, torch.empty(max(t.L, 1), dtype=torch.int64, device=device))
+
+    @property
+    def L(self) -> int:
+        return self.tree.L
+
+    @property
+    def n(self) -> int:
+        return self.tree.n
+
+    def build_from(self, seq: torch.Tensor, stream=None) -> "WaveletMatrix":
+        """Launch wt_build_matrix on ``seq`` into this matrix's buffers (asynchronous)."""
+        t = self.tree
+        if not seq.is_cuda or seq.element_size() != t.sym_bytes or seq.numel() != t.n or not seq.is_contiguous():
+            raise ValueError("seq does not match the allocated layout")
+        out = t.outputs()
+        rc = lib().wt_build_matrix(_ptr(seq), t.n, t.sigma, t.sym_bytes, ctypes.byref(out), _ptr(self.zeros),
+                                   _ptr(t.scratch), t.scratch.numel(), _stream(stream))
+        _check(rc, "wt_build_matrix")
+        return self
+
+    def status(self, stream=None) -> int:
+        return self.tree.status(stream)
+
+    def view(self) -> MatrixView:
+        t = self.tree
+        return MatrixView(_ptr(t.bits), _ptr(self.zeros), _ptr(t.rank), _ptr(t.sel1), _ptr(t.sel0),
+                          _ptr(t.sel_counts), t.n, t.sigma, t.L)
+
+    def access(self, i: torch.Tensor, stream=None) -> torch.Tensor:
+        self.tree._need_dirs()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int32, device=i.device)
+        v = self.view()
+        _check(lib().wt_matrix_access(ctypes.byref(v), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_matrix_access")
+        return out
+
+    def rank_query(self, c: torch.Tensor, i: torch.Tensor, stream=None) -> torch.Tensor:
+        self.tree._need_dirs()
+        c = c.to(torch.int32).contiguous()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int64, device=i.device)
+        v = self.view()
+        _check(lib().wt_matrix_rank(ctypes.byref(v), _ptr(c), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_matrix_rank")
+        return out
+
+    def select_query(self, c: torch.Tensor, k: torch.Tensor, stream=None) -> torch.Tensor:
+        self.tree._need_dirs()
+        c = c.to(torch.int32).contiguous()
+        k = k.to(torch.int64).contiguous()
+        out = torch.empty(k.numel(), dtype=torch.int64, device=k.device)
+        v = self.view()
+        _check(lib().wt_matrix_select(ctypes.byref(v), _ptr(c), _ptr(k), k.numel(), _ptr(out), _stream(stream)),
+               "wt_matrix_select")
+        return out
+
+    def to_numpy(self) -> dict:
+        import numpy as np
+        d = self.tree.to_numpy()
+        d["zeros"] = self.zeros.cpu().numpy().view(np.uint64)[: self.L]
+        return d
+
+
+def build_matrix(seq: torch.Tensor, sigma: int, directories: bool = True, stream=None) -> WaveletMatrix:
+    """Allocate buffers and build the wavelet matrix of ``seq``."""
+    m = WaveletMatrix.allocate(seq.numel(), sigma, seq.element_size(), directories, seq.device)
+    return m.build_from(seq, stream)
 
 
 def build(seq: torch.Tensor, sigma: int, directories: bool = True, stream=None) -> WaveletTree:

@@ -169,3 +169,31 @@ def test_batch_prepare_rejects_bad_arguments():
     assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(16), lay.scratch_bytes, None) == wt.WT_ERR_ARG
     assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(4096), lay.scratch_bytes - 1, None) == wt.WT_ERR_SCRATCH
     assert prep(arr, 1, ctypes.byref(lay), ctypes.c_void_p(4096), lay.scratch_bytes, None) == wt.WT_ERR_ARG
+
+
+def test_matrix_argument_errors_are_synchronous():
+    """wt_build_matrix and the matrix queries reject bad arguments before any
+    device work (no GPU needed)."""
+    lib = wt.lib()
+    out = wt.Outputs()
+    out.C = ctypes.c_void_p(4096)
+    out.bits = ctypes.c_void_p(8192)
+    # zero counts missing while there are levels
+    assert lib.wt_build_matrix(ctypes.c_void_p(16), 10, 4, 1, ctypes.byref(out), None, ctypes.c_void_p(256),
+                               1 << 20, None) == wt.WT_ERR_ARG
+    # the rest as for wt_build: misaligned input, small scratch
+    z = ctypes.c_void_p(12288)
+    assert lib.wt_build_matrix(ctypes.c_void_p(17), 10, 4, 1, ctypes.byref(out), z, ctypes.c_void_p(256),
+                               1 << 20, None) == wt.WT_ERR_ARG
+    assert lib.wt_build_matrix(ctypes.c_void_p(16), 1000, 256, 1, ctypes.byref(out), z, ctypes.c_void_p(256), 64,
+                               None) == wt.WT_ERR_SCRATCH
+    # queries: null view, missing zero counts, null buffers; empty batches are no-ops
+    assert lib.wt_matrix_access(None, None, 5, None, None) == wt.WT_ERR_ARG
+    v = wt.MatrixView()
+    v.n, v.sigma, v.L = 10, 4, 2
+    v.bits = v.rank = v.sel1 = v.sel0 = ctypes.c_void_p(4096)
+    assert lib.wt_matrix_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG
+    v.zeros = ctypes.c_void_p(4096)
+    assert lib.wt_matrix_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG
+    assert lib.wt_matrix_select(ctypes.byref(v), None, None, 0, None, None) == wt.WT_OK
+    assert lib.wt_matrix_access(ctypes.byref(v), None, 0, None, None) == wt.WT_OK
