@@ -68,7 +68,7 @@ def main():
     os.makedirs(args.out, exist_ok=True)
     probe_cmd = [PROBE, str(PROBE_MIB), "3"]
     bench_cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps", "2",
-                 "--warmup", "1", "--no-cpu-baseline", "--no-batch", "--no-serve"]
+                 "--warmup", "1", "--no-cpu-baseline", "--no-batch", "--no-serve", "--no-matrix"]
     known = PROBE_MIB * 1024.0  # KiB read and written by one copy launch
     cf = run_pass("FETCH_SIZE", probe_cmd, args.out, "copy_fetch")
     cw = run_pass("WRITE_SIZE", probe_cmd, args.out, "copy_write")
