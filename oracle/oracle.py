@@ -68,6 +68,21 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_select_matrix.restype = ctypes.c_int64
     lib.oracle_select_matrix.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_uint64]
+    lib.oracle_levels4.restype = ctypes.c_uint32
+    lib.oracle_levels4.argtypes = [ctypes.c_uint64]
+    lib.oracle_build_multiary.restype = ctypes.c_int
+    lib.oracle_build_multiary.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                          _u64p, _u64p]
+    lib.oracle_rank_select4.restype = ctypes.c_int
+    lib.oracle_rank_select4.argtypes = [_u64p, ctypes.c_uint64, ctypes.c_uint32, _u64p, _u64p, _u64p]
+    lib.oracle_access_multiary.restype = ctypes.c_uint64
+    lib.oracle_access_multiary.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.oracle_rank_multiary.restype = ctypes.c_uint64
+    lib.oracle_rank_multiary.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64]
+    lib.oracle_select_multiary.restype = ctypes.c_int64
+    lib.oracle_select_multiary.argtypes = [_u64p, _u64p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_uint64]
     return lib
 
 
@@ -227,3 +242,65 @@ def rank_matrix(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
 def select_matrix(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
     bits, zeros = _matrix_args(t)
     return int(load(lib_path).oracle_select_matrix(_ptr(bits), _ptr(zeros), t["n"], t["sigma"], c, k))
+
+
+# ---- multiary wavelet tree (d = 4) -----------------------------------------
+
+def build_multiary(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """4-ary tree: {'Lq', 'W4', 'n', 'sigma', 'digits' (Lq, W4) uint64, 'C'}."""
+    lib = load(lib_path)
+    S = np.ascontiguousarray(S)
+    n = int(S.shape[0])
+    Lq = int(lib.oracle_levels4(sigma))
+    W4 = (n + 31) // 32
+    digits = np.zeros(max(Lq * W4, 1), dtype=np.uint64)
+    C = np.zeros(sigma + 1, dtype=np.uint64)
+    rc = lib.oracle_build_multiary(S.ctypes.data_as(ctypes.c_void_p), n, sigma, sym_bytes_of(S), _ptr(digits),
+                                   _ptr(C))
+    if rc != 0:
+        raise OracleError(f"oracle_build_multiary returned {rc}")
+    return {"Lq": Lq, "W4": W4, "n": n, "sigma": sigma, "digits": digits[: Lq * W4].reshape(Lq, W4), "C": C}
+
+
+def rank_select4(digits: np.ndarray, n: int, Lq: int, lib_path: str = LIB) -> dict:
+    """Directories of 4-ary levels (see oracle_rank_select4 for the format)."""
+    lib = load(lib_path)
+    flat = np.ascontiguousarray(digits, dtype=np.uint64).reshape(-1)
+    if flat.size == 0:
+        flat = np.zeros(1, dtype=np.uint64)
+    R = (n + RANK_BLOCK_BITS - 1) // RANK_BLOCK_BITS + 1
+    cap = (n + SEL_SAMPLE - 1) // SEL_SAMPLE + 1
+    rank4 = np.zeros(max(Lq * R * 4, 1), dtype=np.uint64)
+    sel4 = np.zeros(max(Lq * 4 * cap, 1), dtype=np.uint64)
+    counts4 = np.zeros(max(Lq * 4, 1), dtype=np.uint64)
+    lib.oracle_rank_select4(_ptr(flat), n, Lq, _ptr(rank4), _ptr(sel4), _ptr(counts4))
+    return {"rank4": rank4[: Lq * R * 4].reshape(Lq, R, 4), "sel4": sel4[: Lq * 4 * cap].reshape(Lq, 4, cap),
+            "counts4": counts4[: Lq * 4].reshape(Lq, 4)}
+
+
+def build_multiary_all(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    t = build_multiary(S, sigma, lib_path)
+    t.update(rank_select4(t["digits"], t["n"], t["Lq"], lib_path))
+    return t
+
+
+def _multiary_args(t: dict):
+    d = np.ascontiguousarray(t["digits"], dtype=np.uint64).reshape(-1)
+    if d.size == 0:
+        d = np.zeros(1, dtype=np.uint64)
+    return d, np.ascontiguousarray(t["C"], dtype=np.uint64)
+
+
+def access_multiary(t: dict, i: int, lib_path: str = LIB) -> int:
+    d, C = _multiary_args(t)
+    return int(load(lib_path).oracle_access_multiary(_ptr(d), _ptr(C), t["n"], t["sigma"], i))
+
+
+def rank_multiary(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
+    d, C = _multiary_args(t)
+    return int(load(lib_path).oracle_rank_multiary(_ptr(d), _ptr(C), t["n"], t["sigma"], c, i))
+
+
+def select_multiary(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
+    d, C = _multiary_args(t)
+    return int(load(lib_path).oracle_select_multiary(_ptr(d), _ptr(C), t["n"], t["sigma"], c, k))

@@ -560,3 +560,200 @@ int64_t oracle_select_matrix(const uint64_t *bits, const uint64_t *zeros, uint64
     }
     return (int64_t)p;
 }
+
+/* ---- multiary wavelet tree, d = 4 (the paper's multiary variant) ----------
+ * Each node has up to 4 children and stores 2-bit entries.  With L binary
+ * levels the tree has Lq = ceil(L / 2) levels; codes are read as Lq base-4
+ * digits (a leading 0 bit when L is odd).  Level j lists S sorted stably by
+ * its top j digits, and its entry for a symbol is the symbol's digit j (from
+ * the top).  The construction keeps the sorted sequence from level to level:
+ * on level j the sequence is already sorted by the top j digits, so each
+ * run of equal top-j digits (a node, found by scanning for where that prefix
+ * changes) is sorted stably by digit j with a 4-bucket counting sort.
+ * Entry i of level j is bits 2(i mod 32) and 2(i mod 32)+1 of word i / 32 of
+ * digits[j * W4 + .], W4 = ceil(n / 32). */
+uint32_t oracle_levels4(uint64_t sigma)
+{
+    return (oracle_levels(sigma) + 1) / 2;
+}
+
+static uint32_t digit_at(uint64_t x, uint32_t Lq, uint32_t j)
+{
+    return (uint32_t)((x >> (2 * (Lq - 1 - j))) & 3);
+}
+
+int oracle_build_multiary(const void *S, uint64_t n, uint64_t sigma, int sym_bytes, uint64_t *digits,
+                          uint64_t *C)
+{
+    uint32_t Lq;
+    uint64_t W4 = (n + 31) / 32;
+    uint64_t *cur, *nxt;
+    if (sigma == 0 || (sym_bytes != 1 && sym_bytes != 2 && sym_bytes != 4))
+        return OR_ERR_ARG;
+    Lq = oracle_levels4(sigma);
+    cur = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    nxt = (uint64_t *)malloc((n ? n : 1) * sizeof(uint64_t));
+    if (!cur || !nxt) {
+        free(cur);
+        free(nxt);
+        return OR_ERR_NOMEM;
+    }
+    memset(C, 0, (size_t)(sigma + 1) * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; i++) {
+        cur[i] = sym_at(S, sym_bytes, i);
+        if (cur[i] >= sigma) {
+            free(cur);
+            free(nxt);
+            return OR_ERR_SYMBOL;
+        }
+        C[cur[i] + 1]++;
+    }
+    for (uint64_t c = 0; c < sigma; c++)
+        C[c + 1] += C[c];
+    if (Lq && W4)
+        memset(digits, 0, (size_t)(Lq * W4) * sizeof(uint64_t));
+    for (uint32_t j = 0; j < Lq; j++) {
+        uint64_t *Dg = digits + (uint64_t)j * W4;
+        uint32_t shift = 2 * (Lq - 1 - j) + 2; /* the top j digits are x >> shift */
+        for (uint64_t i = 0; i < n; i++)
+            Dg[i / 32] |= (uint64_t)digit_at(cur[i], Lq, j) << (2 * (i % 32));
+        if (j + 1 == Lq)
+            break;
+        /* nodes: maximal runs of equal top-j digits; a stable 4-bucket sort in each */
+        for (uint64_t a = 0; a < n;) {
+            uint64_t e = a + 1, cnt[4] = {0, 0, 0, 0}, off[4];
+            while (e < n && (cur[e] >> shift) == (cur[a] >> shift))
+                e++;
+            for (uint64_t i = a; i < e; i++)
+                cnt[digit_at(cur[i], Lq, j)]++;
+            off[0] = a;
+            for (int v = 1; v < 4; v++)
+                off[v] = off[v - 1] + cnt[v - 1];
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 8
+            /* planted mistake: buckets 1 and 2 swapped */
+            { uint64_t t = off[1]; off[1] = off[0] + cnt[0] + cnt[2]; off[2] = t; }
+#endif
+            for (uint64_t i = a; i < e; i++)
+                nxt[off[digit_at(cur[i], Lq, j)]++] = cur[i];
+            a = e;
+        }
+        { uint64_t *t = cur; cur = nxt; nxt = t; }
+    }
+    free(cur);
+    free(nxt);
+    return OR_OK;
+}
+
+static uint32_t digit_of(const uint64_t *Dg, uint64_t i)
+{
+    return (uint32_t)((Dg[i / 32] >> (2 * (i % 32))) & 3);
+}
+
+/* Directories of the 4-ary levels (the paper leaves the structure for larger
+ * alphabets to its generalized rank/select; this reading keeps one absolute
+ * count per digit value every 512 entries and one sample per 4096
+ * occurrences of each value):
+ *   rank4[(j * R + b) * 4 + v] = occurrences of v among entries [0, min(512 b, n)), b <= ceil(n/512);
+ *   sel4[(j * 4 + v) * cap + t] = position of the occurrence of v with 0-based ordinal 4096 t
+ *                                 (n past the last), cap = ceil(n/4096) + 1;
+ *   counts4[j * 4 + v] = ceil(occurrences of v / 4096). */
+int oracle_rank_select4(const uint64_t *digits, uint64_t n, uint32_t Lq, uint64_t *rank4, uint64_t *sel4,
+                        uint64_t *counts4)
+{
+    uint64_t W4 = (n + 31) / 32;
+    uint64_t R = (n + OR_RANK_BLOCK_BITS - 1) / OR_RANK_BLOCK_BITS + 1;
+    uint64_t cap = (n + OR_SEL_SAMPLE - 1) / OR_SEL_SAMPLE + 1;
+    for (uint32_t j = 0; j < Lq; j++) {
+        const uint64_t *Dg = digits + (uint64_t)j * W4;
+        uint64_t seen[4] = {0, 0, 0, 0};
+        for (uint64_t t = 0; t < 4 * cap; t++)
+            sel4[(uint64_t)j * 4 * cap + t] = n;
+        for (uint64_t i = 0; i <= n; i++) {
+            if (i % OR_RANK_BLOCK_BITS == 0)
+                for (int v = 0; v < 4; v++)
+                    rank4[((uint64_t)j * R + i / OR_RANK_BLOCK_BITS) * 4 + v] = seen[v];
+            if (i == n)
+                break;
+            uint32_t v = digit_of(Dg, i);
+            if (seen[v] % OR_SEL_SAMPLE == 0)
+                sel4[((uint64_t)j * 4 + v) * cap + seen[v] / OR_SEL_SAMPLE] = i;
+            seen[v]++;
+        }
+        if (n % OR_RANK_BLOCK_BITS != 0)
+            for (int v = 0; v < 4; v++)
+                rank4[((uint64_t)j * R + R - 1) * 4 + v] = seen[v];
+        for (int v = 0; v < 4; v++)
+            counts4[(uint64_t)j * 4 + v] = (seen[v] + OR_SEL_SAMPLE - 1) / OR_SEL_SAMPLE;
+    }
+    return OR_OK;
+}
+
+/* Tree-walking queries over the oracle's own digits and C, counting entries
+ * one at a time.  Node q of level j holds the symbols whose top j digits are
+ * q; it starts at C[q * 4^(Lq-j)] and its child v at C[(4q + v) * 4^(Lq-j-1)]. */
+static uint64_t count_digit(const uint64_t *Dg, uint64_t from, uint64_t to, uint32_t v)
+{
+    uint64_t r = 0;
+    for (uint64_t i = from; i < to; i++)
+        r += digit_of(Dg, i) == v;
+    return r;
+}
+
+static uint64_t start_of(const uint64_t *C, uint64_t sigma, uint64_t x)
+{
+    return C[x < sigma ? x : sigma];
+}
+
+uint64_t oracle_access_multiary(const uint64_t *digits, const uint64_t *C, uint64_t n, uint64_t sigma,
+                                uint64_t i)
+{
+    uint32_t Lq = oracle_levels4(sigma);
+    uint64_t W4 = (n + 31) / 32, q = 0, p = i;
+    for (uint32_t j = 0; j < Lq; j++) {
+        const uint64_t *Dg = digits + (uint64_t)j * W4;
+        uint32_t sh = 2 * (Lq - 1 - j);
+        uint32_t v = digit_of(Dg, p);
+        uint64_t a = start_of(C, sigma, q << (sh + 2));
+        uint64_t child = start_of(C, sigma, (4 * q + v) << sh);
+        p = child + count_digit(Dg, a, p, v);
+        q = 4 * q + v;
+    }
+    return q;
+}
+
+uint64_t oracle_rank_multiary(const uint64_t *digits, const uint64_t *C, uint64_t n, uint64_t sigma, uint64_t c,
+                              uint64_t i)
+{
+    uint32_t Lq = oracle_levels4(sigma);
+    uint64_t W4 = (n + 31) / 32, r;
+    if (c >= sigma)
+        return 0;
+    r = i > n ? n : i;
+    for (uint32_t j = 0; j < Lq; j++) {
+        const uint64_t *Dg = digits + (uint64_t)j * W4;
+        uint32_t sh = 2 * (Lq - 1 - j);
+        uint64_t a = start_of(C, sigma, (c >> (sh + 2)) << (sh + 2));
+        r = count_digit(Dg, a, a + r, digit_at(c, Lq, j));
+    }
+    return r;
+}
+
+int64_t oracle_select_multiary(const uint64_t *digits, const uint64_t *C, uint64_t n, uint64_t sigma, uint64_t c,
+                               uint64_t k)
+{
+    uint32_t Lq = oracle_levels4(sigma);
+    uint64_t W4 = (n + 31) / 32, r;
+    if (c >= sigma || k == 0 || k > C[c + 1] - C[c])
+        return -1;
+    r = k - 1;
+    for (uint32_t j = Lq; j-- > 0;) {
+        const uint64_t *Dg = digits + (uint64_t)j * W4;
+        uint32_t sh = 2 * (Lq - 1 - j), v = digit_at(c, Lq, j);
+        uint64_t a = start_of(C, sigma, (c >> (sh + 2)) << (sh + 2)), i = a;
+        for (uint64_t seen = 0; i < n; i++)
+            if (digit_of(Dg, i) == v && seen++ == r)
+                break;
+        r = i - a;
+    }
+    return (int64_t)r;
+}

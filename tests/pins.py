@@ -16,6 +16,9 @@ paper or the mathematics fixes.
                   bits, and its bitmap holds bit L-1-l of that order.
   matrix zeros    the zeros of matrix level l = number of symbols whose bit
                   L-1-l is 0.
+  4-ary levels    the multiary tree (d = 4) in the sortWT view: level j lists
+                  S stably sorted by its top j base-4 digits, and its entry
+                  is digit j; the digit counts of a level are those of S.
 """
 from __future__ import annotations
 
@@ -205,4 +208,84 @@ def check_matrix(t: dict, S: np.ndarray, sigma: int, expected_levels=None) -> li
             got = np.asarray(t[key], dtype=np.uint64).reshape(want[key].shape)
             if not np.array_equal(got, want[key]):
                 fails.append(f"matrix_dirs_{key}")
+    return fails
+
+
+def levels4(sigma: int) -> int:
+    return (levels(sigma) + 1) // 2
+
+
+def digit(s: int, j: int, Lq: int) -> int:
+    return (s >> (2 * (Lq - 1 - j))) & 3
+
+
+def multiary_levels_py(S, sigma: int):
+    """4-ary levels by pure-Python stable ``sorted`` (tiny inputs)."""
+    Lq = levels4(sigma)
+    out = []
+    for j in range(Lq):
+        T = sorted(S, key=lambda s: s >> (2 * (Lq - j)))
+        out.append([digit(s, j, Lq) for s in T])
+    return out
+
+
+def multiary_levels_np(S: np.ndarray, sigma: int) -> list[np.ndarray]:
+    Lq = levels4(sigma)
+    S64 = S.astype(np.uint64)
+    out = []
+    for j in range(Lq):
+        order = np.argsort(S64 >> np.uint64(2 * (Lq - j)), kind="stable")
+        out.append(((S64[order] >> np.uint64(2 * (Lq - 1 - j))) & np.uint64(3)).astype(np.uint8))
+    return out
+
+
+def pack4(entries, n: int) -> np.ndarray:
+    """2-bit entries, 32 per 64-bit word, LSB-first."""
+    W4 = (n + 31) // 32
+    e = np.zeros(W4 * 32, dtype=np.uint64)
+    e[:n] = np.asarray(entries, dtype=np.uint64)[:n]
+    if W4 == 0:
+        return np.zeros(0, dtype=np.uint64)
+    shifts = (np.arange(32, dtype=np.uint64) * np.uint64(2))
+    return np.bitwise_or.reduce(e.reshape(W4, 32) << shifts, axis=1)
+
+
+def naive_dirs4(rows: list, n: int) -> dict:
+    Lq = len(rows)
+    R = (n + RANK_BLOCK_BITS - 1) // RANK_BLOCK_BITS + 1
+    cap = (n + SEL_SAMPLE - 1) // SEL_SAMPLE + 1
+    rank4 = np.zeros((Lq, R, 4), dtype=np.uint64)
+    sel4 = np.full((Lq, 4, cap), n, dtype=np.uint64)
+    counts4 = np.zeros((Lq, 4), dtype=np.uint64)
+    pos = np.minimum(np.arange(R, dtype=np.int64) * RANK_BLOCK_BITS, n)
+    for j, row in enumerate(rows):
+        row = np.asarray(row, dtype=np.int64)
+        for v in range(4):
+            hit = (row == v).astype(np.int64)
+            cs = np.concatenate([[0], np.cumsum(hit)])
+            rank4[j, :, v] = cs[pos]
+            where = np.flatnonzero(hit)[::SEL_SAMPLE]
+            sel4[j, v, : where.size] = where
+            counts4[j, v] = where.size
+    return {"rank4": rank4, "sel4": sel4, "counts4": counts4}
+
+
+def check_multiary(t: dict, S: np.ndarray, sigma: int) -> list[str]:
+    """Names of the pins that the 4-ary tree ``t`` ({'digits','C',...}) fails."""
+    fails = []
+    n = S.shape[0]
+    Lq = levels4(sigma)
+    rows = multiary_levels_np(S, sigma) if n > 64 else multiary_levels_py(list(map(int, S)), sigma)
+    D = np.asarray(t["digits"], dtype=np.uint64).reshape(Lq, -1) if Lq else np.zeros((0, 0), dtype=np.uint64)
+    for j in range(Lq):
+        if not np.array_equal(D[j], pack4(rows[j], n)):
+            fails.append(f"multiary_level{j}")
+            break
+    if not np.array_equal(np.asarray(t["C"], dtype=np.uint64), expected_C(S, sigma)):
+        fails.append("multiary_C")
+    if "rank4" in t:
+        want = naive_dirs4(rows, n)
+        for key in ("rank4", "sel4", "counts4"):
+            if not np.array_equal(np.asarray(t[key], dtype=np.uint64).reshape(want[key].shape), want[key]):
+                fails.append(f"multiary_dirs_{key}")
     return fails

@@ -274,3 +274,79 @@ def test_matrix_pins_catch_planted_mutants(tmp_path):
         path = str(tmp_path / f"liboracle_m{m}.so")
         oracle.compile_oracle(path, mutant=m)
         assert _matrix_pin_failures(path), f"mutant {m} passed every matrix pin"
+
+
+# ---- multiary wavelet tree (d = 4) --------------------------------------------
+
+def multiary_query_failures(t, S, sigma, lib_path=oracle.LIB):
+    n = S.shape[0]
+    for i in range(n):
+        if oracle.access_multiary(t, i, lib_path) != int(S[i]):
+            return ["access_multiary"]
+    for c in range(sigma + 1):
+        for i in range(n + 1):
+            if oracle.rank_multiary(t, c, i, lib_path) != pins.naive_rank(S, c, i):
+                return ["rank_multiary"]
+        for k in range(n + 2):
+            want = pins.naive_select(S, c, k) if c < sigma else -1
+            if oracle.select_multiary(t, c, k, lib_path) != want:
+                return ["select_multiary"]
+    return []
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 3, 4, 5, 8])
+def test_multiary_exhaustive_tiny(sigma):
+    for n in range(0, 5 if sigma <= 5 else 4):
+        for seq in itertools.product(range(sigma), repeat=n):
+            S = np.asarray(seq, dtype=np.uint8)
+            t = oracle.build_multiary_all(S, sigma)
+            assert pins.check_multiary(t, S, sigma) == [], (seq, sigma)
+            assert multiary_query_failures(t, S, sigma) == [], (seq, sigma)
+
+
+@pytest.mark.parametrize("n,sigma,seed", [(1000, 256, 1), (70000, 256, 2), (33333, 5, 3), (20000, 1 << 16, 4),
+                                          (9000, (1 << 20) + 7, 5), (4097, 300, 6), (5000, 128, 7)])
+def test_multiary_random_medium(n, sigma, seed):
+    rng = np.random.default_rng(seed)
+    S = rng.integers(0, sigma, n).astype(_dtype(sigma))
+    t = oracle.build_multiary_all(S, sigma)
+    assert pins.check_multiary(t, S, sigma) == []
+    for _ in range(30):
+        i = int(rng.integers(0, n))
+        assert oracle.access_multiary(t, i) == int(S[i])
+        c = int(S[int(rng.integers(0, n))])
+        j = int(rng.integers(0, n + 1))
+        assert oracle.rank_multiary(t, c, j) == pins.naive_rank(S, c, j)
+        k = int(rng.integers(1, pins.naive_rank(S, c, n) + 2))
+        assert oracle.select_multiary(t, c, k) == pins.naive_select(S, c, k)
+
+
+def test_multiary_relates_to_binary_tree():
+    """With an even number of binary levels, the high bit of every entry of
+    4-ary level j is binary level 2j's bit at the same position (both levels
+    list S sorted by its top 2j bits); for sigma <= 4 the one level is S."""
+    rng = np.random.default_rng(31)
+    for sigma in (4, 16, 256, 1 << 12):
+        S = rng.integers(0, sigma, 3001).astype(_dtype(sigma))
+        m, tr = oracle.build_multiary(S, sigma), oracle.build(S, sigma)
+        for j in range(m["Lq"]):
+            row = pins.unpack(m["digits"][j].view(np.uint8).view(np.uint64), 2 * S.size)
+            hi = row[1::2]
+            assert np.array_equal(hi, pins.unpack(tr["bits"][2 * j], S.size)), (sigma, j)
+    S = rng.integers(0, 4, 777).astype(np.uint8)
+    assert np.array_equal(oracle.build_multiary(S, 4)["digits"][0], pins.pack4(S, S.size))
+
+
+def test_multiary_pins_catch_planted_mutant(tmp_path):
+    def failures(path):
+        f = set()
+        rng = np.random.default_rng(15)
+        for S, sigma in [(np.asarray([3, 1, 0, 2, 3, 0, 1, 2, 5, 7], np.uint8), 8),
+                         (rng.integers(0, 256, 4000).astype(np.uint8), 256)]:
+            t = oracle.build_multiary_all(S, sigma, path)
+            f.update(pins.check_multiary(t, S, sigma))
+        return f
+    assert failures(oracle.LIB) == set()
+    path = str(tmp_path / "liboracle_m8.so")
+    oracle.compile_oracle(path, mutant=8)
+    assert failures(path), "mutant 8 passed every multiary pin"
