@@ -177,6 +177,51 @@ int wt_matrix_select(const wt_matrix_view *m, const uint32_t *d_c, const uint64_
                      int64_t *d_out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Multiary wavelet tree with d = 4 (the paper's multiary variant), for byte
+ * symbols (sym_bytes = 1, n < 2^32; other inputs give WT_ERR_RANGE).  With
+ * L = ceil(log2 sigma) binary levels it has Lq = ceil(L/2) levels; codes are
+ * read as Lq base-4 digits (a leading 0 bit when L is odd).  Level j lists S
+ * sorted stably by its top j digits and stores the 2-bit digit j of each
+ * symbol: entry i is bits 2(i%32), 2(i%32)+1 of word i/32 of
+ * digits[j * ceil(n/32) + .] (levels contiguous, padding 0).
+ * Directories (the paper defers the structure for larger alphabets to its
+ * generalized rank/select; this library keeps, per level):
+ *   rank4[(j * R + b) * 4 + v] = occurrences of v among entries [0, min(512 b, n)),
+ *                                b = 0 .. R-1, R = ceil(n/512) + 1;
+ *   sel4[(j * 4 + v) * cap + t] = position of the occurrence of v with 0-based
+ *                                ordinal 4096 t, n past the last, cap = ceil(n/4096) + 1;
+ *   counts4[j * 4 + v] = ceil(occurrences of v / 4096).
+ * All outputs are caller-owned device buffers, all required (digits may be
+ * NULL when n = 0); C as for wt_build.  The scratch is wt_plan's for the same
+ * (n, sigma, 1).  Data errors as for wt_build (wt_status_get). */
+typedef struct {
+    uint64_t *digits;   /* [Lq][ceil(n/32)] */
+    uint64_t *C;        /* [sigma+1] */
+    uint64_t *rank4;    /* [Lq][R][4] */
+    uint64_t *sel4;     /* [Lq][4][cap] */
+    uint64_t *counts4;  /* [Lq][4] */
+} wt_multiary_outputs;
+
+int wt_build_multiary(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_multiary_outputs *out,
+                      void *d_scratch, uint64_t scratch_bytes, void *stream);
+
+typedef struct {
+    const uint64_t *digits, *C, *rank4, *sel4, *counts4;  /* device */
+    uint64_t n, sigma;
+    uint32_t Lq;
+} wt_multiary_view;
+
+/* Queries on a 4-ary tree; conventions as for wt_access / wt_rank /
+ * wt_select.  Node q of level j holds the symbols whose top j digits are q:
+ * it starts at C[q 4^(Lq-j)] and its child v at C[(4q+v) 4^(Lq-j-1)]. */
+int wt_multiary_access(const wt_multiary_view *t, const uint64_t *d_i, uint64_t count, uint32_t *d_sym,
+                       void *stream);
+int wt_multiary_rank(const wt_multiary_view *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t count,
+                     uint64_t *d_out, void *stream);
+int wt_multiary_select(const wt_multiary_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t count,
+                       int64_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched construction: many sequences of uneven length and alphabet, each
  * built exactly as wt_build builds it (levelWT, Fig. 1), by one kernel that
  * takes work items from a per-level queue: histogram tiles of every job,

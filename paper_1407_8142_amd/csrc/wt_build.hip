@@ -27,6 +27,7 @@
 #include "wt_device.hpp"
 #include "wt_kernels.hpp"
 #include "wt_pair.hpp"
+#include "wt_quad.hpp"
 
 namespace wt {
 
@@ -399,20 +400,54 @@ __global__ __launch_bounds__(kBlock) void pair_pass(PairArgs a) {
     pair_tile_u8<SCATTER, NEXT_PAIR, DIRS>(a, blockIdx.x, s);
 }
 
-// E_l[4p+d] = C[(4p+d) 2^(k-1)] - (symbols of digit d in the nodes before
-// p), for the pair that starts at level l = 2 * blockIdx.x (256 entries
-// each).
-__global__ __launch_bounds__(kBlock) void pair_tables(const uint64_t *C, uint64_t sigma, uint32_t L, uint32_t *E) {
-    const uint32_t l = 2u * blockIdx.x, k = L - 1u - l;
-    uint32_t *El = E + 256u * blockIdx.x;
+// E[4p+d] = C[(4p+d) << shift] - (symbols of digit d, bits [shift, shift+2),
+// in the nodes before p) for the digit level j = blockIdx.x, shift = shift0 -
+// 2j, 4^(j+1) entries at E + 256 j: the destinations of a split by two bits
+// (pairs of binary levels from level 2j, or the levels of the 4-ary tree).
+__global__ __launch_bounds__(kBlock) void digit_tables(const uint64_t *C, uint64_t sigma, uint32_t shift0,
+                                                       uint32_t *E) {
+    const uint32_t j = blockIdx.x, shift = shift0 - 2u * j;
+    uint32_t *Ej = E + 256u * j;
     auto Cc = [&](uint64_t x) { return C[x < sigma ? x : sigma]; };
-    for (uint32_t t = threadIdx.x; t < (4u << l); t += kBlock) {
+    for (uint32_t t = threadIdx.x; t < (4u << (2u * j)); t += kBlock) {
         const uint32_t p = t >> 2, d = t & 3u;
         uint64_t before = 0;
         for (uint32_t q = 0; q < p; ++q)
-            before += Cc((uint64_t)(4u * q + d + 1u) << (k - 1u)) - Cc((uint64_t)(4u * q + d) << (k - 1u));
-        El[t] = (uint32_t)(Cc((uint64_t)t << (k - 1u)) - before);
+            before += Cc((uint64_t)(4u * q + d + 1u) << shift) - Cc((uint64_t)(4u * q + d) << shift);
+        Ej[t] = (uint32_t)(Cc((uint64_t)t << shift) - before);
     }
+}
+
+// 4-ary tree: quad_pass runs quad_tile_u8 per block; quad_tails writes what
+// only the level's totals decide (the last rank entry, the sample counts and
+// the sample slots past them), the totals coming from C.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void quad_pass(QuadArgs a) {
+    __shared__ LdsQuad s;
+    quad_tile_u8<SCATTER>(a, blockIdx.x, s);
+}
+
+__global__ __launch_bounds__(kBlock) void quad_tails(const uint64_t *C, uint64_t sigma, uint32_t Lq, uint64_t n,
+                                                     uint64_t *rank4, uint64_t R, uint64_t *sel4, uint64_t cap,
+                                                     uint64_t *counts4) {
+    const uint32_t j = blockIdx.x, kq = 2u * (Lq - 1u - j);
+    __shared__ unsigned long long tot[4];
+    if (threadIdx.x < 4) tot[threadIdx.x] = 0;
+    __syncthreads();
+    auto Cc = [&](uint64_t x) { return C[x < sigma ? x : sigma]; };
+    for (uint64_t t = threadIdx.x; t < (4ull << (2u * j)); t += kBlock) {
+        const uint64_t c = Cc((t + 1) << kq) - Cc(t << kq);
+        if (c) atomicAdd(&tot[t & 3u], (unsigned long long)c);
+    }
+    __syncthreads();
+    constexpr uint64_t S = WT_SELECT_SAMPLE;
+    uint64_t *rk = rank4 + (uint64_t)j * R * 4, *sl = sel4 + (uint64_t)j * 4 * cap;
+    if (threadIdx.x < 4) {
+        rk[(R - 1) * 4 + threadIdx.x] = tot[threadIdx.x];
+        counts4[(uint64_t)j * 4 + threadIdx.x] = (tot[threadIdx.x] + S - 1) / S;
+    }
+    for (uint64_t i = threadIdx.x; i < 4 * cap; i += kBlock)
+        if (i % cap >= (tot[i / cap] + S - 1) / S) sl[i] = n;
 }
 
 // Exclusive prefixes (G_0, G_1, G_2) of per-tile packed digit counts (one
@@ -565,10 +600,14 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     p.off_status = o;
     o += 256;
     p.T = align_up(p.T, 64);  // per-level stride of the tile arrays (keeps vector loads aligned)
+    // Per-tile arrays for an even number of levels: passes over two levels
+    // (and the 4-ary tree) keep 64-bit counts and 16-byte prefixes per tile
+    // in the room of two levels.
+    const uint64_t Lt = p.L + (p.L & 1u);
     p.off_cnt = o;  // zeros per tile, per level (count-ahead), zeroed each build
-    o = align_up(o + 4ull * p.L * p.T, 256);
+    o = align_up(o + 4ull * Lt * p.T, 256);
     p.off_pre = o;  // exclusive zero prefix per tile, per level
-    o = align_up(o + 8ull * p.L * p.T, 256);
+    o = align_up(o + 8ull * Lt * p.T, 256);
     p.off_D = o;
     o = align_up(o + 8ull * D_len, 256);
     p.off_part = o;
@@ -722,11 +761,12 @@ static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, ui
     return true;
 }
 
-// `digits`: the per-tile output is the packed digit counts of the top two
-// bits (uint64 per tile) that a first pass over two levels reads.
+// `digits`: the per-tile output is the packed digit counts of bits
+// (dig_top, dig_top - 1), by default the top two (uint64 per tile), that a
+// first pass over two levels reads.
 template <typename T>
 static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
-                        void *rows, bool digits, hipStream_t s) {
+                        void *rows, bool digits, hipStream_t s, uint32_t dig_top = 0) {
     if (!digits && g_slices && launch_hist_slices<T>(seq, p, Cp1, status, cnt0, rows, s)) return;
     uint32_t reps = 0;  // LDS replicas (64 lanes share them), 0 = global atomics
     if (p.sigma <= 8192) reps = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, 8192 / (p.sigma + 1)));
@@ -736,8 +776,8 @@ static void launch_hist(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t 
     const size_t shm = reps ? (size_t)reps * (p.sigma + 1) * 4 : (size_t)HistHash<4096>::kWords * 4;
     if (digits)
         histogram<T, true><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma,
-                                                                 (unsigned long long *)Cp1, status, reps, p.L - 1,
-                                                                 cnt0, shift, ntiles);
+                                                                 (unsigned long long *)Cp1, status, reps,
+                                                                 dig_top ? dig_top : p.L - 1, cnt0, shift, ntiles);
     else
         histogram<T, false><<<(unsigned)blocks, kBlock, shm, s>>>((const T *)seq, p.n, p.sigma,
                                                                   (unsigned long long *)Cp1, status, reps,
@@ -799,7 +839,7 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
     uint64_t *pre = (uint64_t *)(sc + p.off_pre);
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint32_t *E = (uint32_t *)(sc + p.off_E);
-    pair_tables<<<p.L / 2, kBlock, 0, s>>>(out->C, p.sigma, p.L, E);
+    digit_tables<<<p.L / 2, kBlock, 0, s>>>(out->C, p.sigma, p.L - 2, E);
     const uint32_t shift = tile_shift_for(1);
     const uint64_t Tl = cdiv(n, 1ull << shift);
     const void *cur = d_seq;
@@ -1027,6 +1067,80 @@ extern "C" int wt_build_matrix(const void *d_seq, uint64_t n, uint64_t sigma, in
                                uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream) {
     if (!d_zeros && levels_of(sigma) > 0) return WT_ERR_ARG;
     return build_impl(d_seq, n, sigma, sym_bytes, out, true, d_zeros, d_scratch, scratch_bytes, stream);
+}
+
+extern "C" int wt_build_multiary(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes,
+                                 const wt_multiary_outputs *out, void *d_scratch, uint64_t scratch_bytes,
+                                 void *stream) {
+    Plan p;
+    int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    if (sym_bytes != 1 || n >= (1ull << 32)) return WT_ERR_RANGE;  // byte alphabets
+    const uint32_t Lq = (p.L + 1) / 2;
+    if (!out || !out->C || !d_scratch || (n > 0 && !d_seq)) return WT_ERR_ARG;
+    if (Lq > 0 && (!out->rank4 || !out->sel4 || !out->counts4 || (n > 0 && !out->digits))) return WT_ERR_ARG;
+    if (((uintptr_t)d_seq & 15u) || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    if (scratch_bytes < p.total) return WT_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    uint32_t *status = (uint32_t *)(sc + p.off_status);
+    uint32_t *cnt = (uint32_t *)(sc + p.off_cnt);
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
+    uint64_t *part = (uint64_t *)(sc + p.off_part);
+    uint32_t *E = (uint32_t *)(sc + p.off_E);
+    {
+        uint64_t na = p.off_pre / 8, nb = sigma + 1;
+        uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
+        zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
+    }
+    if (n > 0) {
+        // Digit counts of level 0 (bits 2Lq-1, 2Lq-2) per tile, and C.
+        launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, sc + p.off_S0, Lq > 0, s, 2 * Lq - 1);
+        CScanOp cop{out->C + 1};
+        const uint64_t chunks = cdiv(sigma, kScanChunk);
+        if (chunks > 1) {
+            scan_reduce<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+            scan_partials_seg<CScanOp><<<1, kBlock, 0, s>>>(cop, chunks, part);
+            scan_final<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+        } else {
+            scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
+        }
+    }
+    if (Lq == 0) return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+    const uint64_t W4 = cdiv(n, 32), R = cdiv(n, WT_RANK_BLOCK_BITS) + 1;
+    digit_tables<<<Lq, kBlock, 0, s>>>(out->C, sigma, 2 * Lq - 2, E);
+    quad_tails<<<Lq, kBlock, 0, s>>>(out->C, sigma, Lq, n, out->rank4, R, out->sel4, p.cap, out->counts4);
+    if (n == 0) return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+    const uint32_t shift = tile_shift_for(1);
+    const uint64_t Tl = cdiv(n, 1ull << shift);
+    const void *cur = d_seq;
+    for (uint32_t j = 0; j < Lq; ++j) {
+        const bool scatter = j + 1 < Lq;
+        void *dst = (j % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+        pair_prefix_scan<<<1, kScanThreads, 0, s>>>((const uint64_t *)(cnt + 2ull * j * p.T),
+                                                    (uint4 *)(pre + 2ull * j * p.T), Tl);
+        QuadArgs a;
+        a.in = (const uint8_t *)cur;
+        a.out = scatter ? (uint8_t *)dst : nullptr;
+        a.entries = (uint32_t *)(out->digits + (uint64_t)j * W4);
+        a.nwords32 = 2 * W4;
+        a.E = E + 256u * j;
+        a.nkeys = 4u << (2u * j);
+        a.pre = (const uint4 *)(pre + 2ull * j * p.T);
+        a.next_cnt = scatter ? (uint64_t *)(cnt + 2ull * (j + 1) * p.T) : nullptr;
+        a.next_shift = shift;
+        a.status = status;
+        a.rank4 = out->rank4 + (uint64_t)j * R * 4;
+        a.sel4 = out->sel4 + (uint64_t)j * 4 * p.cap;
+        a.cap = p.cap;
+        a.n = (uint32_t)n;
+        a.kq = 2 * (Lq - 1 - j);
+        if (scatter) quad_pass<true><<<(unsigned)Tl, kBlock, 0, s>>>(a);
+        else quad_pass<false><<<(unsigned)Tl, kBlock, 0, s>>>(a);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        cur = dst;
+    }
+    return WT_OK;
 }
 
 extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t L, uint64_t *d_rank,

@@ -1,5 +1,5 @@
 // Batched access / rank / select on a built levelwise wavelet tree (and on
-// a wavelet matrix, further down)
+// a wavelet matrix and a 4-ary tree, further down)
 // (queries as defined in "Preliminaries"; tree walks without parent/child
 // pointers: node offsets come from C, in-node positions from rank/select on
 // the level bitmaps).  One thread per query; each query takes L dependent
@@ -269,6 +269,132 @@ static bool make_matrix(const wt_matrix_view *v, TreeDev &t) {
     return true;
 }
 
+// ---- multiary tree, d = 4 ----
+struct QuadDev {
+    const uint64_t *digits, *C, *rank4, *sel4, *counts4;
+    uint64_t n, sigma, W4, R, cap;
+    uint32_t Lq;
+};
+
+// Entries equal to v among the 32 two-bit entries of x, as one bit per
+// entry (bit 2i set for entry i).
+__device__ __forceinline__ uint64_t match4(uint64_t x, uint32_t v) {
+    constexpr uint64_t M = 0x5555555555555555ull;
+    const uint64_t lo = x & M, hi = (x >> 1) & M;
+    return ((v & 1u) ? lo : (~lo & M)) & ((v & 2u) ? hi : (~hi & M));
+}
+
+// Entries equal to v among entries [0, p) of level j, p <= n.
+__device__ __forceinline__ uint64_t quad_rank(const QuadDev &t, uint32_t j, uint32_t v, uint64_t p) {
+    const uint64_t *Dg = t.digits + (uint64_t)j * t.W4;
+    const uint64_t blk = p >> 9;
+    uint64_t r = t.rank4[((uint64_t)j * t.R + blk) * 4 + v];
+    const uint64_t w_end = p >> 5;
+    for (uint64_t w = blk << 4; w < w_end; ++w) r += (uint64_t)__popcll(match4(Dg[w], v));
+    if (p & 31) r += (uint64_t)__popcll(match4(Dg[w_end], v) & ((1ull << (2 * (p & 31))) - 1ull));
+    return r;
+}
+
+// Position of the entry v of level j with 0-based ordinal o (o < its count).
+__device__ uint64_t quad_select(const QuadDev &t, uint32_t j, uint32_t v, uint64_t o) {
+    const uint64_t *samp = t.sel4 + ((uint64_t)j * 4 + v) * t.cap;
+    const uint64_t *R4 = t.rank4 + (uint64_t)j * t.R * 4;
+    const uint64_t *Dg = t.digits + (uint64_t)j * t.W4;
+    const uint64_t s = o / WT_SELECT_SAMPLE;
+    const uint64_t lo_pos = samp[s], hi_pos = samp[s + 1];
+    uint64_t lo = lo_pos >> 9, hi = (hi_pos >= t.n ? t.n - 1 : hi_pos) >> 9;
+    while (lo < hi) {  // last 512-entry block whose count of v is <= o
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if (R4[mid * 4 + v] <= o) lo = mid;
+        else hi = mid - 1;
+    }
+    uint64_t rem = o - R4[lo * 4 + v];
+    for (uint64_t w = lo << 4; w < t.W4; ++w) {
+        uint64_t x = match4(Dg[w], v);
+        if ((w << 5) + 32 > t.n) x &= (1ull << (2 * (t.n & 31))) - 1ull;
+        const uint64_t c = (uint64_t)__popcll(x);
+        if (rem < c) return (w << 5) + (select_in_word(x, (uint32_t)rem) >> 1);
+        rem -= c;
+    }
+    return t.n;  // unreachable for a well-formed tree
+}
+
+__device__ __forceinline__ uint64_t quad_start(const QuadDev &t, uint64_t x) { return t.C[x < t.sigma ? x : t.sigma]; }
+
+__device__ __forceinline__ uint32_t quad_access_one(const QuadDev &t, uint64_t p) {
+    uint64_t q = 0;
+    for (uint32_t j = 0; j < t.Lq; ++j) {
+        const uint32_t sh = 2 * (t.Lq - 1 - j);
+        const uint32_t v = (uint32_t)((t.digits[(uint64_t)j * t.W4 + (p >> 5)] >> (2 * (p & 31))) & 3u);
+        const uint64_t a = quad_start(t, q << (sh + 2));
+        p = quad_start(t, (4 * q + v) << sh) + quad_rank(t, j, v, p) - quad_rank(t, j, v, a);
+        q = 4 * q + v;
+        if (p >= t.n && j + 1 < t.Lq) break;  // unreachable for a well-formed tree
+    }
+    return (uint32_t)q;
+}
+
+__device__ __forceinline__ uint64_t quad_rank_one(const QuadDev &t, uint64_t c, uint64_t i) {
+    uint64_t r = i;
+    for (uint32_t j = 0; j < t.Lq && r; ++j) {
+        const uint32_t sh = 2 * (t.Lq - 1 - j), v = (uint32_t)((c >> sh) & 3u);
+        const uint64_t a = quad_start(t, (c >> (sh + 2)) << (sh + 2));
+        if (a + r > t.n) break;  // unreachable for a well-formed tree
+        r = quad_rank(t, j, v, a + r) - quad_rank(t, j, v, a);
+    }
+    return r;
+}
+
+__device__ __forceinline__ int64_t quad_select_one(const QuadDev &t, uint64_t c, uint64_t kk) {
+    if (c >= t.sigma || kk == 0 || kk > t.C[c + 1] - t.C[c]) return -1;
+    uint64_t r = kk - 1;
+    for (uint32_t j = t.Lq; j-- > 0;) {
+        const uint32_t sh = 2 * (t.Lq - 1 - j), v = (uint32_t)((c >> sh) & 3u);
+        const uint64_t a = quad_start(t, (c >> (sh + 2)) << (sh + 2));
+        const uint64_t p = quad_select(t, j, v, quad_rank(t, j, v, a) + r);
+        if (p >= t.n) return -1;  // unreachable for a well-formed tree
+        r = p - a;
+    }
+    return (int64_t)r;
+}
+
+__global__ void quad_access_kernel(QuadDev t, const uint64_t *qi, uint64_t m, uint32_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t j = qi[q];
+    out[q] = j >= t.n ? 0xFFFFFFFFu : quad_access_one(t, j);
+}
+
+__global__ void quad_rank_kernel(QuadDev t, const uint32_t *qc, const uint64_t *qi, uint64_t m, uint64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t c = qc[q], i = min(qi[q], t.n);
+    out[q] = c >= t.sigma ? 0 : quad_rank_one(t, c, i);
+}
+
+__global__ void quad_select_kernel(QuadDev t, const uint32_t *qc, const uint64_t *qk, uint64_t m, int64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    out[q] = quad_select_one(t, qc[q], qk[q]);
+}
+
+static bool make_quad(const wt_multiary_view *v, QuadDev &t) {
+    if (!v || !v->C) return false;
+    if (v->Lq > 0 && (!v->rank4 || !v->sel4 || (v->n > 0 && !v->digits))) return false;
+    t.digits = v->digits;
+    t.C = v->C;
+    t.rank4 = v->rank4;
+    t.sel4 = v->sel4;
+    t.counts4 = v->counts4;
+    t.n = v->n;
+    t.sigma = v->sigma;
+    t.Lq = v->Lq;
+    t.W4 = (v->n + 31) / 32;
+    t.R = (v->n + WT_RANK_BLOCK_BITS - 1) / WT_RANK_BLOCK_BITS + 1;
+    t.cap = (v->n + WT_SELECT_SAMPLE - 1) / WT_SELECT_SAMPLE + 1;
+    return true;
+}
+
 static bool make_tree(const wt_view *v, TreeDev &t) {
     if (!v || !v->C) return false;
     if (v->L > 0 && v->n > 0 && (!v->bits || !v->rank || !v->sel1 || !v->sel0)) return false;
@@ -362,5 +488,38 @@ extern "C" int wt_matrix_select(const wt_matrix_view *v, const uint32_t *d_c, co
     if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
     matrix_select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(
         t, v->zeros, d_c, d_k, m, d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_multiary_access(const wt_multiary_view *v, const uint64_t *d_i, uint64_t m, uint32_t *d_sym,
+                                  void *stream) {
+    QuadDev t;
+    if (!make_quad(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_i || !d_sym) return WT_ERR_ARG;
+    quad_access_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_i, m,
+                                                                                                     d_sym);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_multiary_rank(const wt_multiary_view *v, const uint32_t *d_c, const uint64_t *d_i, uint64_t m,
+                                uint64_t *d_out, void *stream) {
+    QuadDev t;
+    if (!make_quad(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_i || !d_out) return WT_ERR_ARG;
+    quad_rank_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_i, m,
+                                                                                                   d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_multiary_select(const wt_multiary_view *v, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
+                                  int64_t *d_out, void *stream) {
+    QuadDev t;
+    if (!make_quad(v, t)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
+    quad_select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_k,
+                                                                                                     m, d_out);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }

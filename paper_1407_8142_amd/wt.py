@@ -27,7 +27,8 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_access", "wt_rank", "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
            "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
-           "wt_matrix_rank", "wt_matrix_select"]
+           "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
+           "wt_multiary_select"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -60,6 +61,17 @@ class MatrixView(ctypes.Structure):
     _fields_ = [("bits", ctypes.c_void_p), ("zeros", ctypes.c_void_p), ("rank", ctypes.c_void_p),
                 ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
                 ("n", ctypes.c_uint64), ("sigma", ctypes.c_uint64), ("L", ctypes.c_uint32)]
+
+
+class MultiaryOutputs(ctypes.Structure):
+    _fields_ = [("digits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank4", ctypes.c_void_p),
+                ("sel4", ctypes.c_void_p), ("counts4", ctypes.c_void_p)]
+
+
+class MultiaryView(ctypes.Structure):
+    _fields_ = [("digits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank4", ctypes.c_void_p),
+                ("sel4", ctypes.c_void_p), ("counts4", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("sigma", ctypes.c_uint64), ("Lq", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
@@ -117,11 +129,16 @@ def lib() -> ctypes.CDLL:
         L.wt_matrix_access.argtypes = [ctypes.POINTER(MatrixView), vp, u64, vp, vp]
         L.wt_matrix_rank.argtypes = [ctypes.POINTER(MatrixView), vp, vp, u64, vp, vp]
         L.wt_matrix_select.argtypes = [ctypes.POINTER(MatrixView), vp, vp, u64, vp, vp]
+        L.wt_build_multiary.argtypes = [vp, u64, u64, i32, ctypes.POINTER(MultiaryOutputs), vp, u64, vp]
+        L.wt_multiary_access.argtypes = [ctypes.POINTER(MultiaryView), vp, u64, vp, vp]
+        L.wt_multiary_rank.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
+        L.wt_multiary_select.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
                   "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
                   "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix",
-                  "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select"):
+                  "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
+                  "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -329,6 +346,85 @@ def build_matrix(seq: torch.Tensor, sigma: int, directories: bool = True, stream
     """Allocate buffers and build the wavelet matrix of ``seq``."""
     m = WaveletMatrix.allocate(seq.numel(), sigma, seq.element_size(), directories, seq.device)
     return m.build_from(seq, stream)
+
+
+@dataclass
+class WaveletMultiary:
+    """Device buffers of one 4-ary wavelet tree (byte symbols): per level the
+    2-bit entries, C, and the digit directories (int64 tensors hold uint64)."""
+    n: int
+    sigma: int
+    Lq: int
+    digits: torch.Tensor
+    C: torch.Tensor
+    rank4: torch.Tensor
+    sel4: torch.Tensor
+    counts4: torch.Tensor
+    scratch: torch.Tensor
+
+    @staticmethod
+    def allocate(n: int, sigma: int, device="cuda") -> "WaveletMultiary":
+        lay = plan(n, sigma, 1)
+        Lq = (lay.L + 1) // 2
+        R = lay.rank_len
+        e = lambda *shape: torch.empty(*shape, dtype=torch.int64, device=device)
+        return WaveletMultiary(n=n, sigma=sigma, Lq=Lq, digits=e(Lq, (n + 31) // 32), C=e(sigma + 1),
+                               rank4=e(Lq, R, 4), sel4=e(Lq, 4, lay.sel_cap), counts4=e(Lq, 4),
+                               scratch=torch.empty(max(lay.scratch_bytes, 256), dtype=torch.uint8, device=device))
+
+    def build_from(self, seq: torch.Tensor, stream=None) -> "WaveletMultiary":
+        if not seq.is_cuda or seq.element_size() != 1 or seq.numel() != self.n or not seq.is_contiguous():
+            raise ValueError("seq must be a contiguous device tensor of n byte symbols")
+        out = MultiaryOutputs(_ptr(self.digits), _ptr(self.C), _ptr(self.rank4), _ptr(self.sel4),
+                              _ptr(self.counts4))
+        rc = lib().wt_build_multiary(_ptr(seq), self.n, self.sigma, 1, ctypes.byref(out), _ptr(self.scratch),
+                                     self.scratch.numel(), _stream(stream))
+        _check(rc, "wt_build_multiary")
+        return self
+
+    def status(self, stream=None) -> int:
+        return int(lib().wt_status_get(_ptr(self.scratch), _stream(stream)))
+
+    def view(self) -> MultiaryView:
+        return MultiaryView(_ptr(self.digits), _ptr(self.C), _ptr(self.rank4), _ptr(self.sel4), _ptr(self.counts4),
+                            self.n, self.sigma, self.Lq)
+
+    def access(self, i: torch.Tensor, stream=None) -> torch.Tensor:
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int32, device=i.device)
+        v = self.view()
+        _check(lib().wt_multiary_access(ctypes.byref(v), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_multiary_access")
+        return out
+
+    def rank_query(self, c: torch.Tensor, i: torch.Tensor, stream=None) -> torch.Tensor:
+        c = c.to(torch.int32).contiguous()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int64, device=i.device)
+        v = self.view()
+        _check(lib().wt_multiary_rank(ctypes.byref(v), _ptr(c), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_multiary_rank")
+        return out
+
+    def select_query(self, c: torch.Tensor, k: torch.Tensor, stream=None) -> torch.Tensor:
+        c = c.to(torch.int32).contiguous()
+        k = k.to(torch.int64).contiguous()
+        out = torch.empty(k.numel(), dtype=torch.int64, device=k.device)
+        v = self.view()
+        _check(lib().wt_multiary_select(ctypes.byref(v), _ptr(c), _ptr(k), k.numel(), _ptr(out), _stream(stream)),
+               "wt_multiary_select")
+        return out
+
+    def to_numpy(self) -> dict:
+        import numpy as np
+        u = lambda t: t.cpu().numpy().view(np.uint64)
+        return {"Lq": self.Lq, "n": self.n, "sigma": self.sigma, "digits": u(self.digits), "C": u(self.C),
+                "rank4": u(self.rank4), "sel4": u(self.sel4), "counts4": u(self.counts4)}
+
+
+def build_multiary(seq: torch.Tensor, sigma: int, stream=None) -> WaveletMultiary:
+    """Allocate buffers and build the 4-ary wavelet tree of ``seq`` (byte symbols)."""
+    return WaveletMultiary.allocate(seq.numel(), sigma, seq.device).build_from(seq, stream)
 
 
 def build(seq: torch.Tensor, sigma: int, directories: bool = True, stream=None) -> WaveletTree:

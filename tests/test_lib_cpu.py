@@ -197,3 +197,25 @@ def test_matrix_argument_errors_are_synchronous():
     assert lib.wt_matrix_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG
     assert lib.wt_matrix_select(ctypes.byref(v), None, None, 0, None, None) == wt.WT_OK
     assert lib.wt_matrix_access(ctypes.byref(v), None, 0, None, None) == wt.WT_OK
+
+
+def test_multiary_argument_errors_are_synchronous():
+    lib = wt.lib()
+    out = wt.MultiaryOutputs()
+    # wider symbols are out of range for the 4-ary build
+    assert lib.wt_build_multiary(ctypes.c_void_p(16), 10, 300, 2, ctypes.byref(out), ctypes.c_void_p(256),
+                                 1 << 20, None) == wt.WT_ERR_RANGE
+    # C missing, then directories missing
+    assert lib.wt_build_multiary(ctypes.c_void_p(16), 10, 200, 1, ctypes.byref(out), ctypes.c_void_p(256),
+                                 1 << 20, None) == wt.WT_ERR_ARG
+    out.C = ctypes.c_void_p(4096)
+    assert lib.wt_build_multiary(ctypes.c_void_p(16), 10, 200, 1, ctypes.byref(out), ctypes.c_void_p(256),
+                                 1 << 20, None) == wt.WT_ERR_ARG
+    out.digits = out.rank4 = out.sel4 = out.counts4 = ctypes.c_void_p(8192)
+    assert lib.wt_build_multiary(ctypes.c_void_p(16), 100000, 200, 1, ctypes.byref(out), ctypes.c_void_p(256), 64,
+                                 None) == wt.WT_ERR_SCRATCH
+    assert lib.wt_multiary_access(None, None, 5, None, None) == wt.WT_ERR_ARG
+    v = wt.MultiaryView()
+    v.C = ctypes.c_void_p(4096)
+    v.n, v.sigma, v.Lq = 10, 16, 2
+    assert lib.wt_multiary_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG
