@@ -122,30 +122,48 @@ def batch_model_bytes(jobs) -> float:
     return total
 
 
-def matrix_leg(d_seq, n: int, sigma: int, sym_bytes: int, L: int, steps: int, tree_ms: float):
-    """The same input built as a wavelet matrix (wt_build_matrix, with
-    directories), timed like the tree build."""
+def variant_leg(name: str, build_once, status, n: int, L: int, steps: int, tree_ms: float, launch: str):
+    """Times another construction of the same input (after two untimed runs)
+    with HIP events, as the tree build is timed; sym*lvl/s counts the binary
+    levels (the same information for every variant)."""
     import torch
 
     from paper_1407_8142_amd import wt
 
-    m = wt.WaveletMatrix.allocate(n, sigma, sym_bytes, True, d_seq.device)
     for _ in range(2):
-        m.build_from(d_seq)
+        build_once()
     torch.cuda.synchronize()
-    if m.status() != wt.WT_OK:
-        raise SystemExit("input rejected by wt_build_matrix")
+    if status() != wt.WT_OK:
+        raise SystemExit(f"input rejected by the {name} build")
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        m.build_from(d_seq)
+        build_once()
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    log(f"[matrix] {ms:.3f} ms/step, {n * L / (ms / 1e3):.3e} sym*lvl/s")
+    log(f"[{name}] {ms:.3f} ms/step, {n * L / (ms / 1e3):.3e} sym*lvl/s")
     return {"value": n * L / (ms / 1e3), "unit": "symbols*levels/s", "ms_per_step": ms, "steps": steps,
-            "tree_ms_per_step": tree_ms, "launch": "wt_build_matrix on the same input and buffers layout"}
+            "tree_ms_per_step": tree_ms, "launch": launch}
+
+
+def matrix_leg(d_seq, n: int, sigma: int, sym_bytes: int, L: int, steps: int, tree_ms: float):
+    """The same input built as a wavelet matrix (wt_build_matrix, with directories)."""
+    from paper_1407_8142_amd import wt
+
+    m = wt.WaveletMatrix.allocate(n, sigma, sym_bytes, True, d_seq.device)
+    return variant_leg("matrix", lambda: m.build_from(d_seq), m.status, n, L, steps, tree_ms,
+                       "wt_build_matrix on the same input")
+
+
+def multiary_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
+    """The same byte input built as a 4-ary wavelet tree (wt_build_multiary)."""
+    from paper_1407_8142_amd import wt
+
+    t = wt.WaveletMultiary.allocate(n, sigma, d_seq.device)
+    return variant_leg("multiary", lambda: t.build_from(d_seq), t.status, n, L, steps, tree_ms,
+                       "wt_build_multiary (d = 4, ceil(L/2) levels) on the same input")
 
 
 def batch_leg(count: int, steps: int):
@@ -286,7 +304,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the sequence length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27)
-    ap.add_argument("--no-matrix", action="store_true", help="skip the wavelet-matrix build of the same input")
+    ap.add_argument("--no-matrix", action="store_true",
+                    help="skip the wavelet-matrix and 4-ary builds of the same input")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -368,6 +387,8 @@ def main():
         cpu = cpu_baseline(S, sigma, L, sample)
 
     matrix = None if args.no_matrix else matrix_leg(d_seq, n, sigma, S.dtype.itemsize, L, args.steps, ms_per_step)
+    multiary = None if args.no_matrix or S.dtype.itemsize != 1 else multiary_leg(d_seq, n, sigma, L, args.steps,
+                                                                                ms_per_step)
     batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
     served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb)
 
@@ -381,6 +402,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "matrix": matrix,
+        "multiary": multiary,
         "batch": batch,
         "serve": served,
     }

@@ -422,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void digit_tables(const uint64_t *C, uint64
 // only the level's totals decide (the last rank entry, the sample counts and
 // the sample slots past them), the totals coming from C.
 template <bool SCATTER>
-__global__ __launch_bounds__(kBlock) void quad_pass(QuadArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void quad_pass(QuadArgs a) {
     __shared__ LdsQuad s;
     quad_tile_u8<SCATTER>(a, blockIdx.x, s);
 }

@@ -94,23 +94,26 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
     }
     if (*a.status) return;  // grid-uniform: the input was rejected (nothing written yet)
 
-    // Digit masks, counts and the interleaved entries of every chunk.
-    uint32_t g[4][kRows], w32[kRows];
+    // Digit bit masks, counts and the interleaved entries of every chunk
+    // (the mask of digit v is rebuilt from the two bit masks where needed).
+    uint32_t mh[kRows], ml[kRows], w32[kRows];
     uint32_t c0[kRows], c1[kRows], c2[kRows];
+    auto digit_mask = [&](int r, int v) -> uint32_t {
+        const uint32_t nv = clamp_count(len, (uint32_t)(r * kRowBytes + 16 * tid), 16u);
+        const uint32_t h = (v & 2) ? mh[r] : ~mh[r], l = (v & 1) ? ml[r] : ~ml[r];
+        return h & l & ((1u << nv) - 1u);
+    };
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
         const uint32_t nv = clamp_count(len, p, 16u);
         const uint32_t vm = (1u << nv) - 1u;
-        const uint32_t mh = mask16_bit(d[r], kq + 1u) & vm, ml = mask16_bit(d[r], kq) & vm;
-        g[0][r] = ~mh & ~ml & vm;
-        g[1][r] = ~mh & ml;
-        g[2][r] = mh & ~ml;
-        g[3][r] = mh & ml;
-        c0[r] = (uint32_t)__popc(g[0][r]);
-        c1[r] = (uint32_t)__popc(g[1][r]);
-        c2[r] = (uint32_t)__popc(g[2][r]);
-        w32[r] = spread16(ml) | (spread16(mh) << 1);
+        mh[r] = mask16_bit(d[r], kq + 1u) & vm;
+        ml[r] = mask16_bit(d[r], kq) & vm;
+        c0[r] = (uint32_t)__popc(~mh[r] & ~ml[r] & vm);
+        c1[r] = (uint32_t)__popc(~mh[r] & ml[r]);
+        c2[r] = (uint32_t)__popc(mh[r] & ~ml[r]);
+        w32[r] = spread16(ml[r]) | (spread16(mh[r]) << 1);
     }
     uint32_t l0[kRows], l1[kRows], l2[kRows];
     const uint32_t T0 = rows_scan(c0, l0, s.wz, lane, wave);
@@ -132,10 +135,11 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const uint32_t o0 = Gt[v] + lv[v], cnt = (uint32_t)__popc(g[v][r]);
+                const uint32_t gm = digit_mask(r, v);
+                const uint32_t o0 = Gt[v] + lv[v], cnt = (uint32_t)__popc(gm);
                 const uint64_t tt = ((uint64_t)o0 + S - 1) / S * S;
                 if (tt < (uint64_t)o0 + cnt && tt < a.n)  // an ordinal is below n
-                    a.sel4[(uint64_t)v * a.cap + tt / S] = pos + select_in_word(g[v][r], (uint32_t)(tt - o0));
+                    a.sel4[(uint64_t)v * a.cap + tt / S] = pos + select_in_word(gm, (uint32_t)(tt - o0));
             }
         }
     }
