@@ -51,6 +51,61 @@ __global__ void zero_fill(uint64_t *a, uint64_t na, uint64_t *b, uint64_t nb) {
 // With DIG, the per-tile output is the packed counts of the top two bits'
 // digit (the prefixes a first pass over two levels needs) instead of the
 // zeros of the top bit.
+// Byte symbols with LDS replicas (the common case): every byte is one LDS
+// add (its result unused) into its lane's replica, and the zeros of the top
+// bit (or the digit counts) are tallied by SWAR over the sixteen bytes of a
+// load, fewer instructions per byte than merging runs.  The four loads of a
+// thread's share of a whole tile are issued together; a ragged tile end is
+// counted byte by byte.
+// CHECK: sigma < 256, so a byte can be out of range (then it is counted in
+// the spare bin sigma and flagged).
+template <bool DIG, bool CHECK>
+__device__ __forceinline__ std::conditional_t<DIG, uint64_t, uint32_t> hist_count_u8(
+    const uint8_t *__restrict__ S, uint64_t base, uint32_t len, uint64_t sigma, uint32_t reps, uint32_t ktop,
+    uint32_t *tab, bool &bad) {
+    const int tid = threadIdx.x;
+    uint32_t *h = tab + (uint32_t)(lane_id() % reps) * (uint32_t)(sigma + 1);
+    const uint32_t smax = (uint32_t)sigma;
+    std::conditional_t<DIG, uint64_t, uint32_t> acc = 0;
+    auto one = [&](uint32_t x) {
+        if constexpr (CHECK) {
+            bad |= x >= smax;
+            x = min(x, smax);
+        }
+        atomicAdd(h + x, 1u);
+    };
+    auto count16 = [&](const uint4 &q) {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) one((w[i] >> (8 * b)) & 0xFFu);
+        if constexpr (DIG) acc += digit_inc16(q, ktop - 1u);
+        else acc += zeros16(q, ktop);
+    };
+    const uint4 *src = reinterpret_cast<const uint4 *>(S + base);
+    const uint32_t nvec = len / 16;
+    constexpr int kU = 4;
+    for (uint32_t v0 = tid; v0 < nvec; v0 += kBlock * kU) {
+        uint4 q[kU];
+        if (v0 + (uint32_t)((kU - 1) * kBlock) < nvec) {
+#pragma unroll
+            for (int k = 0; k < kU; ++k) q[k] = src[v0 + k * kBlock];
+#pragma unroll
+            for (int k = 0; k < kU; ++k) count16(q[k]);
+        } else {
+            for (uint32_t v = v0; v < nvec; v += kBlock) count16(src[v]);
+        }
+    }
+    for (uint32_t e = nvec * 16 + tid; e < len; e += kBlock) {
+        const uint32_t x = S[base + e];
+        one(x);
+        if constexpr (DIG) acc += digit_inc(x, ktop - 1u);
+        else acc += ((x >> ktop) & 1u) ^ 1u;
+    }
+    return acc;
+}
+
 template <typename T, bool DIG>
 __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
                                                     unsigned long long *Cp1, uint32_t *status, uint32_t reps,
@@ -65,8 +120,20 @@ __global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uin
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = tile << tile_shift;
         const uint32_t len = (uint32_t)min(1ull << tile_shift, n - base);
-        const auto zeros = hist_count<T, kH, unsigned long long, DIG>(S, base, len, sigma, reps, ktop, s_dyn,
-                                                                       &s_nused, Cp1, bad);
+        std::conditional_t<DIG, uint64_t, uint32_t> zeros;
+        if constexpr (sizeof(T) == 1) {
+            const uint8_t *S8 = reinterpret_cast<const uint8_t *>(S);
+            if (!reps)
+                zeros = hist_count<T, kH, unsigned long long, DIG>(S, base, len, sigma, reps, ktop, s_dyn, &s_nused,
+                                                                   Cp1, bad);
+            else if (sigma < 256)
+                zeros = hist_count_u8<DIG, true>(S8, base, len, sigma, reps, ktop, s_dyn, bad);
+            else
+                zeros = hist_count_u8<DIG, false>(S8, base, len, sigma, reps, ktop, s_dyn, bad);
+        } else {
+            zeros = hist_count<T, kH, unsigned long long, DIG>(S, base, len, sigma, reps, ktop, s_dyn, &s_nused, Cp1,
+                                                               bad);
+        }
         if (cnt0) {
             if constexpr (DIG) {
                 const uint64_t t = block_sum_u64(zeros, s_red);
