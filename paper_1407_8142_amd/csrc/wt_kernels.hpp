@@ -675,7 +675,8 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
 
     // Load: thread t, row r holds positions r*4096 + 16t .. +15.  A whole
     // tile's four loads are issued back to back (no branch between them),
-    // so their latencies overlap; the node table follows them.
+    // so their latencies overlap; the node table follows them.  Positions
+    // past the end of a short tile read as 0xFF (see the split).
     const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
     uint4 d[kRows];
     uint32_t m[kRows], z[kRows];
@@ -693,7 +694,7 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
                 uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
-                    if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+                    w[j >> 2] |= ((uint32_t)j < nv ? (uint32_t)in[p + j] : 0xFFu) << (8 * (j & 3));
                 d[r] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
@@ -764,32 +765,27 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     }
     if (!SCATTER) return;
 
-    // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).
-    if (len == (uint32_t)kTile) {
+    // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).  The
+    // zeros' and ones' cursors of a lane share one word (low and high 16
+    // bits); 16 times a byte's level bit selects the half, as the offset of
+    // the read and the shift of the increment, so a byte costs an extract
+    // and an add, with no branch.  The 0xFF bytes past the end of a short
+    // tile are ones after every zero of the tile, so position e >= len goes
+    // to slot Zt + (e - Zt) = e: slots [len, kTile), which nothing reads.
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
-            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
+        uint32_t A = zl[r] | ((Zt + e0 - zl[r]) << 16);
+        const uint32_t dw[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
 #pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const uint32_t bit = (m[r] >> b) & 1u;
-                s.stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
-                zc += bit ^ 1u;
-                oc += bit;
-            }
-        }
-    } else {
+        for (int j = 0; j < 4; ++j) {
+            // Bit 8i+4 of T is bit k of byte i (a rotation right by k-4 mod 32).
+            const uint32_t T = __builtin_amdgcn_alignbit(dw[j], dw[j], (k + 28u) & 31u) & 0x10101010u;
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t e0 = (uint32_t)(r * kRowBytes + 16 * tid);
-            const uint32_t nv = clamp_count(len, e0, 16u);
-            uint32_t zc = zl[r], oc = Zt + e0 - zl[r];
-#pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const uint32_t bit = (m[r] >> b) & 1u;
-                if ((uint32_t)b < nv) s.stage[bit ? oc : zc] = (uint8_t)byte_of(d[r], b);
-                zc += bit ^ 1u;
-                oc += bit;
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t sh = (T >> (8 * i)) & 31u;
+                s.stage[__builtin_amdgcn_ubfe(A, sh, 16u)] = (uint8_t)(dw[j] >> (8 * i));
+                A += 1u << sh;
             }
         }
     }
