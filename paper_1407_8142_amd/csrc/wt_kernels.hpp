@@ -427,6 +427,23 @@ __device__ __forceinline__ void count_flush(CountTable &t, uint32_t *next_cnt, i
     if (tid < kCountSlots && t.key[tid] != kNoTile && t.cnt[tid]) atomicAdd(next_cnt + t.key[tid], t.cnt[tid]);
 }
 
+// Hands every lane's (tile, c) with `want` set to the table with one update
+// per distinct tile of the wave: the lanes of a wave mostly fill the same
+// destination tile, and 64 lanes updating one LDS slot would serialize.
+// Called by all lanes of the wave.
+__device__ __forceinline__ void count_add_wave(CountTable &t, uint32_t *next_cnt, bool want, uint32_t tile,
+                                               uint32_t c, int lane) {
+    uint64_t pend = __ballot(want);
+    while (pend) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t kt = (uint32_t)__builtin_amdgcn_readlane((int)tile, leader);
+        const bool mine = want && tile == kt;
+        const uint32_t tot = wave_sum_u32(mine ? c : 0u);
+        if (lane == leader) count_add(t, next_cnt, kt, tot);
+        pend &= ~__ballot(mine);
+    }
+}
+
 // Per-lane running count for one destination tile.
 struct LaneCount {
     uint32_t tile = kNoTile, cnt = 0;
@@ -438,8 +455,24 @@ struct LaneCount {
         }
         cnt += c;
     }
+    // As add, but a finished tile's count is returned in (ftile, fcnt) for a
+    // wave-wide hand-over instead of going to the table.
+    __device__ __forceinline__ void step(uint32_t ntile, uint32_t c, uint32_t &ftile, uint32_t &fcnt) {
+        if (ntile != tile) {
+            ftile = tile;
+            fcnt = cnt;
+            tile = ntile;
+            cnt = 0;
+        }
+        cnt += c;
+    }
     __device__ __forceinline__ void flush(CountTable &t, uint32_t *next_cnt) {
         if (cnt) count_add(t, next_cnt, tile, cnt);
+        cnt = 0;
+    }
+    // flush by all lanes of the wave
+    __device__ __forceinline__ void flush_wave(CountTable &t, uint32_t *next_cnt, int lane) {
+        count_add_wave(t, next_cnt, cnt != 0, tile, cnt, lane);
         cnt = 0;
     }
 };
@@ -610,7 +643,7 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
             }
         }
     }
-    lc.flush(s.ct, a.next_cnt);
+    lc.flush_wave(s.ct, a.next_cnt, lane);
     __syncthreads();
     count_flush(s.ct, a.next_cnt, tid);
 }
@@ -799,44 +832,52 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     const uint32_t Mn = 0x01010101u << kn;
     const uint32_t n16 = a.n > 15 ? (uint32_t)(a.n - 15) : 0u;  // dest < n16 <=> dest + 15 < n
     uint8_t *out = reinterpret_cast<uint8_t *>(a.out);
+    // Wave w walks chunks [256w, 256w + 256) of the split tile, 64 at a time,
+    // so a lane's chunks mostly stay in one run and one destination tile:
+    // its running count changes tile rarely, and the counts of a wave reach
+    // the table together (count_add_wave).
     const uint4 *s_st128 = reinterpret_cast<const uint4 *>(s.stage);
+    constexpr int kChunksPerWave = kTile / 16 / kWaves;
     LaneCount lc;
 #pragma unroll
-    for (int i = 0; i < kTile / (16 * kBlock); ++i) {
-        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
-        if (sl >= len) continue;
-        const uint4 v = s_st128[j];
-        const uint32_t q0 = ((v.x & 0xFFu) >> k) & a.qmask, q15 = ((v.w >> 24) >> k) & a.qmask;
-        if (sl + 15 < len && q0 == q15) {
-            // One run: the bit is the low bit of q, so the region is uniform too.
-            const uint32_t dest = s.D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
-            if (dest < n16) {
-                *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
-                const uint32_t nt = dest >> a.next_shift;
-                if (((dest + 15) >> a.next_shift) == nt) {
-                    const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) + __popc(v.z & Mn) +
-                                                     __popc(v.w & Mn));
-                    lc.add(s.ct, a.next_cnt, nt, 16u - ones);
-                } else {
-                    for (uint32_t c = 0; c < 16; ++c)
-                        if (!((byte_of(v, (int)c) >> kn) & 1u))
-                            count_add(s.ct, a.next_cnt, (dest + c) >> a.next_shift, 1u);
+    for (int i = 0; i < kChunksPerWave / kWave; ++i) {
+        const uint32_t j = (uint32_t)(wave * kChunksPerWave + i * kWave + lane), sl = 16u * j;
+        uint32_t ftile = kNoTile, fcnt = 0;  // a tile this lane has finished counting
+        if (sl < len) {
+            const uint4 v = s_st128[j];
+            const uint32_t q0 = ((v.x & 0xFFu) >> k) & a.qmask, q15 = ((v.w >> 24) >> k) & a.qmask;
+            if (sl + 15 < len && q0 == q15) {
+                // One run: the bit is the low bit of q, so the region is uniform too.
+                const uint32_t dest = s.D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
+                if (dest < n16) {
+                    *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                    const uint32_t nt = dest >> a.next_shift;
+                    if (((dest + 15) >> a.next_shift) == nt) {
+                        const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) + __popc(v.z & Mn) +
+                                                         __popc(v.w & Mn));
+                        lc.step(nt, 16u - ones, ftile, fcnt);
+                    } else {
+                        for (uint32_t c = 0; c < 16; ++c)
+                            if (!((byte_of(v, (int)c) >> kn) & 1u))
+                                count_add(s.ct, a.next_cnt, (dest + c) >> a.next_shift, 1u);
+                    }
                 }
-            }
-        } else {
-            // Several runs meet here (or the tile ends): byte by byte.
-            const uint32_t nc = clamp_count(len, sl, 16u);
-            for (uint32_t c = 0; c < nc; ++c) {
-                const uint32_t bc = byte_of(v, (int)c), qc = (bc >> k) & a.qmask, sc = sl + c;
-                const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
-                if (dest < a.n) {
-                    out[dest] = (uint8_t)bc;
-                    if (!((bc >> kn) & 1u)) count_add(s.ct, a.next_cnt, dest >> a.next_shift, 1u);
+            } else {
+                // Several runs meet here (or the tile ends): byte by byte.
+                const uint32_t nc = clamp_count(len, sl, 16u);
+                for (uint32_t c = 0; c < nc; ++c) {
+                    const uint32_t bc = byte_of(v, (int)c), qc = (bc >> k) & a.qmask, sc = sl + c;
+                    const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
+                    if (dest < a.n) {
+                        out[dest] = (uint8_t)bc;
+                        if (!((bc >> kn) & 1u)) count_add(s.ct, a.next_cnt, dest >> a.next_shift, 1u);
+                    }
                 }
             }
         }
+        count_add_wave(s.ct, a.next_cnt, fcnt != 0, ftile, fcnt, lane);
     }
-    lc.flush(s.ct, a.next_cnt);
+    lc.flush_wave(s.ct, a.next_cnt, lane);
     __syncthreads();
     count_flush(s.ct, a.next_cnt, tid);
 }
