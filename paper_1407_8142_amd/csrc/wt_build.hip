@@ -711,7 +711,10 @@ static int timing_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
         ev = g_free.back();
         g_free.pop_back();
     } else {
-        if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) return WT_ERR_HIP;
+        // Timing only: no system-scope fence (a cache writeback) at each record.
+        if (hipEventCreateWithFlags(&ev.first, hipEventDisableSystemFence) != hipSuccess ||
+            hipEventCreateWithFlags(&ev.second, hipEventDisableSystemFence) != hipSuccess)
+            return WT_ERR_HIP;
     }
     return hipEventRecord(ev.first, s) == hipSuccess ? WT_OK : WT_ERR_HIP;
 }
