@@ -85,6 +85,33 @@ __device__ __forceinline__ void count_flush_t(CountTableT<CNT> &t, CNT *next_cnt
     if (tid < kCountSlots && t.key[tid] != kNoTile && t.cnt[tid]) global_add(next_cnt + t.key[tid], t.cnt[tid]);
 }
 
+// Sum over the 64 lanes of a wave of packed counts (all lanes active): the
+// 16-bit fields of one tile's counts never carry, so the halves of a 64-bit
+// word are summed as two 32-bit values.
+template <typename CNT>
+__device__ __forceinline__ CNT wave_sum_cnt(CNT v) {
+    if constexpr (sizeof(CNT) == 8)
+        return (uint64_t)wave_sum_u32((uint32_t)v) | ((uint64_t)wave_sum_u32((uint32_t)(v >> 32)) << 32);
+    else
+        return wave_sum_u32(v);
+}
+
+// count_add_wave for packed counts: one table update per distinct tile of
+// the wave.  Called by all lanes of the wave.
+template <typename CNT>
+__device__ __forceinline__ void count_add_wave_t(CountTableT<CNT> &t, CNT *next_cnt, bool want, uint32_t tile,
+                                                 CNT c, int lane) {
+    uint64_t pend = __ballot(want);
+    while (pend) {
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t kt = (uint32_t)__builtin_amdgcn_readlane((int)tile, leader);
+        const bool mine = want && tile == kt;
+        const CNT tot = wave_sum_cnt<CNT>(mine ? c : (CNT)0);
+        if (lane == leader) count_add_t(t, next_cnt, kt, tot);
+        pend &= ~__ballot(mine);
+    }
+}
+
 template <typename CNT>
 struct LaneCountT {
     uint32_t tile = kNoTile;
@@ -97,8 +124,22 @@ struct LaneCountT {
         }
         cnt += c;
     }
+    // As add, but a finished tile's count is returned for a wave-wide hand-over.
+    __device__ __forceinline__ void step(uint32_t ntile, CNT c, uint32_t &ftile, CNT &fcnt) {
+        if (ntile != tile) {
+            ftile = tile;
+            fcnt = cnt;
+            tile = ntile;
+            cnt = 0;
+        }
+        cnt += c;
+    }
     __device__ __forceinline__ void flush(CountTableT<CNT> &t, CNT *next_cnt) {
         if (cnt) count_add_t(t, next_cnt, tile, cnt);
+        cnt = 0;
+    }
+    __device__ __forceinline__ void flush_wave(CountTableT<CNT> &t, CNT *next_cnt, int lane) {
+        count_add_wave_t<CNT>(t, next_cnt, cnt != 0, tile, cnt, lane);
         cnt = 0;
     }
 };
@@ -425,41 +466,49 @@ __device__ __forceinline__ void pair_tile_u8(const PairArgs &a, uint32_t tile, L
     };
     const uint32_t n16 = a.n > 15u ? a.n - 15u : 0u;
     const uint4 *b128 = reinterpret_cast<const uint4 *>(s.buf);
+    // Wave w walks chunks [256w, 256w + 256) of the split tile, 64 at a time
+    // (a lane's chunks mostly share a destination tile; counts reach the
+    // table wave-wide, as in the one-level pass).
+    constexpr int kChunksPerWave = kTile / 16 / kWaves;
     LaneCountT<CNT> lc;
 #pragma unroll
-    for (int i = 0; i < kTile / (16 * kBlock); ++i) {
-        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
-        if (sl >= len) continue;
-        const uint4 v = b128[j];
-        const uint32_t q0 = (v.x & 0xFFu) >> kd, q15 = (v.w >> 24) >> kd;
-        if (sl + 15u < len && q0 == q15) {
-            const uint32_t dest = s.E[q0] + base4[q0 & 3u] + sl;
-            if (dest < n16) {
-                *reinterpret_cast<u128_unaligned *>(a.out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
-                const uint32_t nt = dest >> a.next_shift;
-                if (((dest + 15u) >> a.next_shift) == nt) {
-                    lc.add(ct, next, nt, tally16(v));
-                } else {
-                    for (uint32_t c = 0; c < 16; ++c) {
-                        const CNT t = tally1(byte_of(v, (int)c));
-                        if (t) count_add_t(ct, next, (dest + c) >> a.next_shift, t);
+    for (int i = 0; i < kChunksPerWave / kWave; ++i) {
+        const uint32_t j = (uint32_t)(wave * kChunksPerWave + i * kWave + lane), sl = 16u * j;
+        uint32_t ftile = kNoTile;
+        CNT fcnt = 0;
+        if (sl < len) {
+            const uint4 v = b128[j];
+            const uint32_t q0 = (v.x & 0xFFu) >> kd, q15 = (v.w >> 24) >> kd;
+            if (sl + 15u < len && q0 == q15) {
+                const uint32_t dest = s.E[q0] + base4[q0 & 3u] + sl;
+                if (dest < n16) {
+                    *reinterpret_cast<u128_unaligned *>(a.out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                    const uint32_t nt = dest >> a.next_shift;
+                    if (((dest + 15u) >> a.next_shift) == nt) {
+                        lc.step(nt, tally16(v), ftile, fcnt);
+                    } else {
+                        for (uint32_t c = 0; c < 16; ++c) {
+                            const CNT t = tally1(byte_of(v, (int)c));
+                            if (t) count_add_t(ct, next, (dest + c) >> a.next_shift, t);
+                        }
+                    }
+                }
+            } else {
+                const uint32_t nc = clamp_count(len, sl, 16u);
+                for (uint32_t c = 0; c < nc; ++c) {
+                    const uint32_t x = byte_of(v, (int)c), q = x >> kd;
+                    const uint32_t dest = s.E[q] + base4[q & 3u] + sl + c;
+                    if (dest < a.n) {
+                        a.out[dest] = (uint8_t)x;
+                        const CNT t = tally1(x);
+                        if (t) count_add_t(ct, next, dest >> a.next_shift, t);
                     }
                 }
             }
-        } else {
-            const uint32_t nc = clamp_count(len, sl, 16u);
-            for (uint32_t c = 0; c < nc; ++c) {
-                const uint32_t x = byte_of(v, (int)c), q = x >> kd;
-                const uint32_t dest = s.E[q] + base4[q & 3u] + sl + c;
-                if (dest < a.n) {
-                    a.out[dest] = (uint8_t)x;
-                    const CNT t = tally1(x);
-                    if (t) count_add_t(ct, next, dest >> a.next_shift, t);
-                }
-            }
         }
+        count_add_wave_t<CNT>(ct, next, fcnt != 0, ftile, fcnt, lane);
     }
-    lc.flush(ct, next);
+    lc.flush_wave(ct, next, lane);
     __syncthreads();
     count_flush_t(ct, next, tid);
 }

@@ -174,41 +174,48 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
     for (int v = 0; v < 4; ++v) base4[v] = Gt[v] - off[v];
     const uint32_t n16 = a.n > 15u ? a.n - 15u : 0u;
     const uint4 *b128 = reinterpret_cast<const uint4 *>(s.buf);
+    // Wave w walks chunks [256w, 256w + 256) of the split tile, 64 at a time
+    // (see the one-level pass: counts reach the table wave-wide).
+    constexpr int kChunksPerWave = kTile / 16 / kWaves;
     LaneCountT<uint64_t> lc;
 #pragma unroll
-    for (int i = 0; i < kTile / (16 * kBlock); ++i) {
-        const uint32_t j = (uint32_t)(tid + i * kBlock), sl = 16u * j;
-        if (sl >= len) continue;
-        const uint4 v = b128[j];
-        const uint32_t k0 = (v.x & 0xFFu) >> kq, k15 = (v.w >> 24) >> kq;
-        if (sl + 15u < len && k0 == k15) {
-            const uint32_t dest = s.E[k0] + base4[k0 & 3u] + sl;
-            if (dest < n16) {
-                *reinterpret_cast<u128_unaligned *>(a.out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
-                const uint32_t nt = dest >> a.next_shift;
-                if (((dest + 15u) >> a.next_shift) == nt) {
-                    lc.add(s.ct, a.next_cnt, nt, digit_inc16(v, kq - 2u));
-                } else {
-                    for (uint32_t c = 0; c < 16; ++c) {
-                        const uint64_t t = digit_inc(byte_of(v, (int)c), kq - 2u);
-                        if (t) count_add_t(s.ct, a.next_cnt, (dest + c) >> a.next_shift, t);
+    for (int i = 0; i < kChunksPerWave / kWave; ++i) {
+        const uint32_t j = (uint32_t)(wave * kChunksPerWave + i * kWave + lane), sl = 16u * j;
+        uint32_t ftile = kNoTile;
+        uint64_t fcnt = 0;
+        if (sl < len) {
+            const uint4 v = b128[j];
+            const uint32_t k0 = (v.x & 0xFFu) >> kq, k15 = (v.w >> 24) >> kq;
+            if (sl + 15u < len && k0 == k15) {
+                const uint32_t dest = s.E[k0] + base4[k0 & 3u] + sl;
+                if (dest < n16) {
+                    *reinterpret_cast<u128_unaligned *>(a.out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                    const uint32_t nt = dest >> a.next_shift;
+                    if (((dest + 15u) >> a.next_shift) == nt) {
+                        lc.step(nt, digit_inc16(v, kq - 2u), ftile, fcnt);
+                    } else {
+                        for (uint32_t c = 0; c < 16; ++c) {
+                            const uint64_t t = digit_inc(byte_of(v, (int)c), kq - 2u);
+                            if (t) count_add_t(s.ct, a.next_cnt, (dest + c) >> a.next_shift, t);
+                        }
+                    }
+                }
+            } else {
+                const uint32_t nc = clamp_count(len, sl, 16u);
+                for (uint32_t c = 0; c < nc; ++c) {
+                    const uint32_t x = byte_of(v, (int)c), key = x >> kq;
+                    const uint32_t dest = s.E[key] + base4[key & 3u] + sl + c;
+                    if (dest < a.n) {
+                        a.out[dest] = (uint8_t)x;
+                        const uint64_t t = digit_inc(x, kq - 2u);
+                        if (t) count_add_t(s.ct, a.next_cnt, dest >> a.next_shift, t);
                     }
                 }
             }
-        } else {
-            const uint32_t nc = clamp_count(len, sl, 16u);
-            for (uint32_t c = 0; c < nc; ++c) {
-                const uint32_t x = byte_of(v, (int)c), key = x >> kq;
-                const uint32_t dest = s.E[key] + base4[key & 3u] + sl + c;
-                if (dest < a.n) {
-                    a.out[dest] = (uint8_t)x;
-                    const uint64_t t = digit_inc(x, kq - 2u);
-                    if (t) count_add_t(s.ct, a.next_cnt, dest >> a.next_shift, t);
-                }
-            }
         }
+        count_add_wave_t<uint64_t>(s.ct, a.next_cnt, fcnt != 0, ftile, fcnt, lane);
     }
-    lc.flush(s.ct, a.next_cnt);
+    lc.flush_wave(s.ct, a.next_cnt, lane);
     __syncthreads();
     count_flush_t(s.ct, a.next_cnt, tid);
 }
