@@ -66,7 +66,8 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
     const uint4 P = a.pre[tile];
     const uint32_t Gt[4] = {P.x, P.y, P.z, t0 - P.x - P.y - P.z};
 
-    // Load (a whole tile's loads back to back), then the table.
+    // Load (a whole tile's loads back to back), then the table.  Positions
+    // past the end of a short tile read as 0xFF (see the split).
     const uint8_t *in = a.in + t0;
     uint4 d[kRows];
     if (len == (uint32_t)kTile) {
@@ -83,7 +84,7 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
                 uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
-                    if ((uint32_t)j < nv) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+                    w[j >> 2] |= ((uint32_t)j < nv ? (uint32_t)in[p + j] : 0xFFu) << (8 * (j & 3));
                 d[r] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
@@ -146,23 +147,28 @@ __device__ __forceinline__ void quad_tile_u8(const QuadArgs &a, uint32_t tile, L
     if (!SCATTER) return;
 
     // Split 4 ways: digit v's region starts at off[v]; inside it, the tile's
-    // order.
+    // order.  A lane's four cursors share one 64-bit word (16 bits each);
+    // 16 times a byte's digit is the shift that reads its cursor and the one
+    // that advances it.  The 0xFF bytes past the end of a short tile have
+    // digit 3 and follow every valid byte, so position e >= len goes to slot
+    // e: slots [len, kTile), which nothing reads.
     const uint32_t off[4] = {0u, T0, T0 + T1, T0 + T1 + T2};
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
-        const uint32_t nv = clamp_count(len, p, 16u);
-        uint32_t q0 = off[0] + l0[r], q1 = off[1] + l1[r], q2 = off[2] + l2[r],
-                 q3 = off[3] + (p - l0[r] - l1[r] - l2[r]);
+        uint64_t A = (uint64_t)(off[0] + l0[r]) | ((uint64_t)(off[1] + l1[r]) << 16) |
+                     ((uint64_t)(off[2] + l2[r]) << 32) | ((uint64_t)(off[3] + p - l0[r] - l1[r] - l2[r]) << 48);
+        const uint32_t dw[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            const uint32_t v = (w32[r] >> (2 * b)) & 3u;
-            const uint32_t slot = v == 0 ? q0 : (v == 1 ? q1 : (v == 2 ? q2 : q3));
-            if ((uint32_t)b < nv) s.buf[slot] = (uint8_t)byte_of(d[r], b);
-            q0 += v == 0;
-            q1 += v == 1;
-            q2 += v == 2;
-            q3 += v == 3;
+        for (int j = 0; j < 4; ++j) {
+            // Bits 8i+4, 8i+5 of T are the digit of byte i (a rotation right by kq-4 mod 32).
+            const uint32_t T = __builtin_amdgcn_alignbit(dw[j], dw[j], (kq + 28u) & 31u) & 0x30303030u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t sh = (T >> (8 * i)) & 0x30u;
+                s.buf[(uint32_t)(A >> sh) & 0xFFFFu] = (uint8_t)(dw[j] >> (8 * i));
+                A += 1ull << sh;
+            }
         }
     }
     __syncthreads();
