@@ -89,12 +89,25 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
 _LIBS: dict[str, ctypes.CDLL] = {}
 
 
+def _declare_huffman(lib: ctypes.CDLL) -> None:
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_huffman_lengths.restype = ctypes.c_uint32
+    lib.oracle_huffman_lengths.argtypes = [_u64p, ctypes.c_uint32, u32p]
+    lib.oracle_huffman_codes.restype = None
+    lib.oracle_huffman_codes.argtypes = [u32p, ctypes.c_uint32, _u64p]
+    lib.oracle_build_huffman.restype = ctypes.c_int
+    lib.oracle_build_huffman.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, u32p, _u64p,
+                                         ctypes.c_uint32, _u64p, _u64p]
+
+
 def load(path: str = LIB) -> ctypes.CDLL:
     """Load (compiling first if needed) the oracle shared object at ``path``."""
     if path not in _LIBS:
         if path == LIB and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             compile_oracle(LIB)
-        _LIBS[path] = _declare(ctypes.CDLL(path))
+        lib = _declare(ctypes.CDLL(path))
+        _declare_huffman(lib)
+        _LIBS[path] = lib
     return _LIBS[path]
 
 
@@ -304,3 +317,78 @@ def rank_multiary(t: dict, c: int, i: int, lib_path: str = LIB) -> int:
 def select_multiary(t: dict, c: int, k: int, lib_path: str = LIB) -> int:
     d, C = _multiary_args(t)
     return int(load(lib_path).oracle_select_multiary(_ptr(d), _ptr(C), t["n"], t["sigma"], c, k))
+
+
+# ---- Huffman-shaped tree (section "Extensions"; readings in wt_oracle.c) ---
+HUFF_MAX_SIGMA = 256
+
+
+def huffman_lengths(w: np.ndarray, lib_path: str = LIB) -> tuple[np.ndarray, int]:
+    """Code lengths (uint32 per symbol, 0 when absent) and the height."""
+    w = np.ascontiguousarray(w, dtype=np.uint64)
+    sigma = int(w.size)
+    if not 1 <= sigma <= HUFF_MAX_SIGMA:
+        raise OracleError("the Huffman-shaped tree takes 1 <= sigma <= 256")
+    lens = np.zeros(sigma, dtype=np.uint32)
+    h = load(lib_path).oracle_huffman_lengths(_ptr(w), sigma, lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    return lens, int(h)
+
+
+def huffman_codes(lens: np.ndarray, lib_path: str = LIB) -> np.ndarray:
+    """Canonical codes, left-aligned in 64 bits (uint64 per symbol, 0 when absent)."""
+    lens = np.ascontiguousarray(lens, dtype=np.uint32)
+    codes = np.zeros(lens.size, dtype=np.uint64)
+    load(lib_path).oracle_huffman_codes(lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), lens.size,
+                                        _ptr(codes))
+    return codes
+
+
+def build_huffman(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """Huffman-shaped tree of byte sequence S: {'lens', 'codes', 'h', 'W', 'n', 'nd' (h,), 'bits' (h, W)}."""
+    S = np.ascontiguousarray(S)
+    if S.dtype != np.uint8:
+        raise OracleError("the Huffman-shaped tree takes byte symbols")
+    n = int(S.size)
+    if n and int(S.max()) >= sigma:
+        raise OracleError("symbol out of range")
+    w = np.bincount(S, minlength=sigma).astype(np.uint64)[:sigma]
+    lens, h = huffman_lengths(w, lib_path)
+    codes = huffman_codes(lens, lib_path)
+    W = (n + 63) // 64
+    bits = np.zeros(max(h * W, 1), dtype=np.uint64)
+    nd = np.zeros(max(h, 1), dtype=np.uint64)
+    rc = load(lib_path).oracle_build_huffman(S.ctypes.data_as(ctypes.c_void_p), n, sigma,
+                                             lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), _ptr(codes),
+                                             h, _ptr(bits), _ptr(nd))
+    if rc != 0:
+        raise OracleError(f"oracle_build_huffman returned {rc}")
+    return {"sigma": sigma, "n": n, "W": W, "h": h, "lens": lens, "codes": codes, "weights": w,
+            "nd": nd[:h], "bits": bits[: h * W].reshape(h, W)}
+
+
+def build_huffman_all(S: np.ndarray, sigma: int, lib_path: str = LIB) -> dict:
+    """build_huffman plus directories over each level's nd[d] bits, at the
+    per-level strides of an n-symbol tree: rank rows of ceil(n/512)+1
+    entries (entries past the level's end repeat its total), select rows of
+    ceil(n/4096)+1 entries (unused ones hold nd[d]), sel_counts[d] for the
+    ones and sel_counts[h + d] for the zeros of level d."""
+    t = build_huffman(S, sigma, lib_path)
+    n, h = t["n"], t["h"]
+    rank_len = (n + RANK_BLOCK_BITS - 1) // RANK_BLOCK_BITS + 1
+    cap = (n + SEL_SAMPLE - 1) // SEL_SAMPLE + 1
+    rank = np.zeros((h, rank_len), dtype=np.uint64)
+    sel1 = np.zeros((h, cap), dtype=np.uint64)
+    sel0 = np.zeros((h, cap), dtype=np.uint64)
+    counts = np.zeros(2 * h, dtype=np.uint64)
+    for d in range(h):
+        m = int(t["nd"][d])
+        r = rank_select(t["bits"][d, : (m + 63) // 64], m, 1, lib_path)
+        rl = r["rank"].shape[1]
+        rank[d, :rl] = r["rank"][0]
+        rank[d, rl:] = r["rank"][0, -1]
+        cl = r["sel1"].shape[1]
+        sel1[d, :cl], sel1[d, cl:] = r["sel1"][0], m
+        sel0[d, :cl], sel0[d, cl:] = r["sel0"][0], m
+        counts[d], counts[h + d] = r["sel_counts"][0], r["sel_counts"][1]
+    t.update({"rank": rank, "sel1": sel1, "sel0": sel0, "sel_counts": counts})
+    return t

@@ -22,6 +22,11 @@
  *     reverse of its top l bits), per-level zero counts by numpy, equality
  *     with the tree for sigma <= 2, and matrix-walking queries against
  *     naive counting;
+ *   - Huffman-shaped tree: hand-derived code lengths on ties, optimality
+ *     by brute force over every Kraft-complete length vector, prefix-free
+ *     canonical codes, a decoder that walks the levels back to S, level
+ *     sizes from the weights, and equality with the binary tree for equal
+ *     weights over a power-of-two alphabet;
  *   - planted mutants of this file (ORACLE_MUTANT) must fail those pins.
  *
  * Readings where the paper is silent are listed next to the code below.
@@ -756,4 +761,131 @@ int64_t oracle_select_multiary(const uint64_t *digits, const uint64_t *C, uint64
         r = i - a;
     }
     return (int64_t)r;
+}
+
+/* ---- Huffman-shaped wavelet tree (section "Extensions") ---------------
+ * Readings (the paper gives the method, not these details):
+ *   - the leaves are the symbols that occur in S (weight = count > 0);
+ *   - merge order: repeatedly join the two smallest live nodes under the
+ *     total order (weight, leaves before internal nodes, then the symbol
+ *     of a leaf or the creation order of an internal node);
+ *   - the tree is the canonical tree of the resulting code lengths: codes
+ *     assigned in (length, symbol) order, bit 0 = left, so the in-order
+ *     leaf order is (length, symbol) and every internal node's left
+ *     subtree holds consecutive in-order ids below its right subtree's;
+ *   - level d holds, for every occurrence of a symbol whose code is longer
+ *     than d, that code's bit d, in the order of S stably sorted by the
+ *     code prefix of length d (the internal nodes of depth d, left to
+ *     right, each listing its symbols in the order of S);
+ *   - one distinct symbol, or n = 0, gives a tree of height 0.
+ * Codes are kept left-aligned in 64 bits (bit 63 is code bit 0). */
+#define OR_HUFF_MAX_SIGMA 256u
+
+/* The merge order: p before q. */
+#if defined(ORACLE_MUTANT) && ORACLE_MUTANT == 9
+/* planted mistake: internal nodes before leaves on equal weight */
+#define OR_KIND_FIRST(p, q) (kind[p] > kind[q])
+#else
+#define OR_KIND_FIRST(p, q) (kind[p] < kind[q])
+#endif
+#define OR_LESS(p, q) (wt[p] != wt[q] ? wt[p] < wt[q] : \
+                       kind[p] != kind[q] ? OR_KIND_FIRST(p, q) : id[p] < id[q])
+
+/* Code lengths: len[c] = depth of leaf c (0 for absent symbols, and for the
+ * only symbol of a one-leaf tree).  Returns the height. */
+uint32_t oracle_huffman_lengths(const uint64_t *w, uint32_t sigma, uint32_t *len)
+{
+    uint64_t wt[2 * OR_HUFF_MAX_SIGMA];
+    uint32_t kind[2 * OR_HUFF_MAX_SIGMA], id[2 * OR_HUFF_MAX_SIGMA], parent[2 * OR_HUFF_MAX_SIGMA];
+    int live[2 * OR_HUFF_MAX_SIGMA];
+    uint32_t leaf_of[OR_HUFF_MAX_SIGMA];
+    uint32_t nn = 0, m = 0;
+    for (uint32_t c = 0; c < sigma; c++) {
+        len[c] = 0;
+        if (w[c]) {
+            wt[nn] = w[c]; kind[nn] = 0; id[nn] = c; parent[nn] = UINT32_MAX; live[nn] = 1;
+            leaf_of[c] = nn++;
+            m++;
+        }
+    }
+    if (m <= 1) return 0;
+    for (uint32_t step = 0; step + 1 < m; step++) {
+        int32_t a = -1, b = -1;  /* smallest, second smallest */
+        for (uint32_t x = 0; x < nn; x++) {
+            if (!live[x]) continue;
+            if (a < 0 || OR_LESS(x, (uint32_t)a)) { b = a; a = (int32_t)x; }
+            else if (b < 0 || OR_LESS(x, (uint32_t)b)) b = (int32_t)x;
+        }
+        wt[nn] = wt[a] + wt[b]; kind[nn] = 1; id[nn] = step; parent[nn] = UINT32_MAX; live[nn] = 1;
+        parent[a] = nn; parent[b] = nn; live[a] = 0; live[b] = 0;
+        nn++;
+    }
+    uint32_t h = 0;
+    for (uint32_t c = 0; c < sigma; c++) {
+        if (!w[c]) continue;
+        uint32_t d = 0;
+        for (uint32_t x = leaf_of[c]; parent[x] != UINT32_MAX; x = parent[x]) d++;
+        len[c] = d;
+        if (d > h) h = d;
+    }
+    return h;
+}
+
+/* Canonical codes from the lengths, left-aligned (0 for absent symbols):
+ * in (length, symbol) order, the first code is all zeros and each next one
+ * is the previous plus one, shifted left by the growth in length. */
+void oracle_huffman_codes(const uint32_t *len, uint32_t sigma, uint64_t *code)
+{
+    uint64_t cur = 0;
+    uint32_t prev = 0;
+    int first = 1;
+    for (uint32_t c = 0; c < sigma; c++) code[c] = 0;
+    for (uint32_t l = 1; l < 64; l++) {
+        for (uint32_t c = 0; c < sigma; c++) {
+            if (len[c] != l) continue;
+            if (first) { cur = 0; first = 0; }
+            else cur = (cur + 1) << (l - prev);
+            prev = l;
+            code[c] = cur << (64 - l);
+        }
+    }
+}
+
+typedef struct { uint64_t key, pos; } or_keyed;
+static int or_keyed_cmp(const void *x, const void *y)
+{
+    const or_keyed *p = (const or_keyed *)x, *q = (const or_keyed *)y;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return p->pos < q->pos ? -1 : (p->pos > q->pos);
+}
+
+/* Level bitmaps (h levels of W = ceil(n/64) words, zero past nd[d]) and the
+ * level sizes nd[d], straight from the sort view above.  S is bytes. */
+int oracle_build_huffman(const uint8_t *S, uint64_t n, uint32_t sigma, const uint32_t *len,
+                         const uint64_t *code, uint32_t h, uint64_t *bits, uint64_t *nd)
+{
+    uint64_t W = (n + 63) / 64;
+    for (uint64_t i = 0; i < n; i++)
+        if (S[i] >= sigma) return OR_ERR_SYMBOL;
+    memset(bits, 0, (size_t)(h * W) * sizeof(uint64_t));
+    or_keyed *A = (or_keyed *)malloc((size_t)(n ? n : 1) * sizeof(or_keyed));
+    if (!A) return OR_ERR_NOMEM;
+    for (uint32_t d = 0; d < h; d++) {
+        uint64_t m = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            uint32_t c = S[i];
+            if (len[c] <= d) continue;
+            A[m].key = d ? code[c] >> (64 - d) : 0;
+            A[m].pos = i;
+            m++;
+        }
+        qsort(A, (size_t)m, sizeof(or_keyed), or_keyed_cmp);
+        for (uint64_t p = 0; p < m; p++) {
+            uint32_t c = S[A[p].pos];
+            if ((code[c] >> (63 - d)) & 1u) set_bit(bits + (uint64_t)d * W, p);
+        }
+        nd[d] = m;
+    }
+    free(A);
+    return OR_OK;
 }
