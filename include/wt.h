@@ -221,6 +221,59 @@ int wt_multiary_rank(const wt_multiary_view *t, const uint32_t *d_c, const uint6
 int wt_multiary_select(const wt_multiary_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t count,
                        int64_t *d_out, void *stream);
 
+/* ---- Huffman-shaped wavelet tree (section "Extensions") ----------------
+ * Byte symbols only (sym_bytes 1, sigma <= 256, n < 2^32).  The shape is the
+ * canonical tree of the Huffman code lengths of the symbols that occur:
+ * the two smallest live nodes are joined first, in the order (weight,
+ * leaves before internal nodes, symbol for a leaf / creation order for an
+ * internal node); codes are assigned in (length, symbol) order with 0 =
+ * left, so the in-order leaf order is (length, symbol).  Level d holds the
+ * code bit d of every symbol whose code is longer than d, in the order of S
+ * stably sorted by the code prefix of length d; its length is nd[d].  One
+ * distinct symbol, or n = 0, gives height 0 (no levels).
+ *
+ * wt_huffman_plan: the largest height an input of (n, sigma) can have
+ * (a leaf at depth d needs at least F(d+2) symbols, F the Fibonacci
+ * numbers) and the scratch the build needs for a tree of up to h_cap levels
+ * (256-byte aligned, reused across builds, the status word first as for
+ * wt_build).
+ *
+ * wt_build_huffman: asynchronous up to the code construction, then it
+ * waits once on `stream` for the height and the level sizes (they size the
+ * level passes) and enqueues the rest.  Outputs, caller-owned device
+ * buffers with the per-level strides of an n-symbol binary tree
+ * (W = ceil(n/64), rank_len and sel_cap as from wt_plan(n, sigma, 1)):
+ *   bits[d * W + w]             level d's words, zero past nd[d];
+ *   rank/sel1/sel0              as for wt_build_rank_select over level d's
+ *                               nd[d] bits (rank entries at or past the
+ *                               level's end hold its ones, unused samples
+ *                               hold nd[d]);
+ *   sel_counts[d], [h + d]      ceil(ones / 4096), ceil(zeros / 4096);
+ *   C[sigma + 1]                as for wt_build;
+ *   lens[256] (u32), codes[256] code length and left-aligned canonical code
+ *                               (bit 63 = code bit 0) per symbol, 0 if absent;
+ *   nd[h_cap]                   level sizes.
+ * *h_out (host) receives the height.  Returns WT_ERR_RANGE when the height
+ * exceeds h_cap (nothing past the code construction is then enqueued),
+ * WT_ERR_RANGE for sym_bytes != 1, sigma > 256 or n >= 2^32, WT_ERR_ARG for
+ * missing outputs or misaligned pointers, WT_ERR_SCRATCH for a short
+ * scratch.  A symbol >= sigma is reported by wt_status_get; the level passes
+ * are then skipped and the outputs are unspecified. */
+typedef struct {
+    uint64_t *bits;        /* [h_cap][W] */
+    uint64_t *C;           /* [sigma+1] */
+    uint64_t *rank;        /* [h_cap][rank_len] */
+    uint64_t *sel1, *sel0; /* [h_cap][sel_cap] */
+    uint64_t *sel_counts;  /* [2 h_cap] */
+    uint32_t *lens;        /* [256] */
+    uint64_t *codes;       /* [256] */
+    uint64_t *nd;          /* [h_cap] */
+} wt_huffman_outputs;
+
+int wt_huffman_plan(uint64_t n, uint64_t sigma, uint32_t h_cap, uint32_t *h_bound, uint64_t *scratch_bytes);
+int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, const wt_huffman_outputs *out, uint32_t h_cap,
+                     uint32_t *h_out, void *d_scratch, uint64_t scratch_bytes, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched construction: many sequences of uneven length and alphabet, each
  * built exactly as wt_build builds it (levelWT, Fig. 1), by one kernel that

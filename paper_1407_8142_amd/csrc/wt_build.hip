@@ -28,6 +28,7 @@
 #include "wt_kernels.hpp"
 #include "wt_pair.hpp"
 #include "wt_quad.hpp"
+#include "wt_huff.hpp"
 
 namespace wt {
 
@@ -1237,6 +1238,148 @@ extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t
     }
     dim3 g2((unsigned)cdiv(cap, kBlock), L);
     dir_finish<<<g2, kBlock, 0, s>>>(nullptr, zeros_tot, n, L, d_rank, rank_len, d_sel1, d_sel0, cap, d_sel_counts);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Huffman-shaped tree (byte alphabets): scratch = status block, HuffTab,
+// per-tile zero counts and their prefixes for h_cap levels, two sequence
+// buffers.
+struct HuffPlan {
+    uint64_t T, off_tab, off_cnt, off_pre, off_S0, off_S1, total;
+};
+
+static uint32_t huff_height_bound(uint64_t n, uint64_t sigma) {
+    if (n < 2 || sigma < 2) return 0;
+    // a leaf at depth d needs F(d+2) symbols at least
+    uint64_t f1 = 1, f2 = 1;  // F(d+1), F(d+2) for d = 0
+    uint32_t d = 0;
+    while (true) {
+        const uint64_t f3 = f1 + f2;  // F(d+3)
+        if (f3 > n) break;
+        f1 = f2;
+        f2 = f3;
+        ++d;
+    }
+    return (uint32_t)std::min<uint64_t>(d, sigma - 1);
+}
+
+static HuffPlan huff_plan(uint64_t n, uint32_t h_cap) {
+    HuffPlan p;
+    p.T = align_up(std::max<uint64_t>(cdiv(n, 16384), 1), 64);
+    uint64_t o = 256;
+    p.off_tab = o;
+    o = align_up(o + sizeof(HuffTab), 256);
+    p.off_cnt = o;
+    o = align_up(o + 4ull * (h_cap + 1) * p.T, 256);
+    p.off_pre = o;
+    o = align_up(o + 8ull * (h_cap + 1) * p.T, 256);
+    p.off_S0 = o;
+    o = align_up(o + n, 256);
+    p.off_S1 = o;
+    o = align_up(o + n, 256);
+    p.total = o;
+    return p;
+}
+
+extern "C" int wt_huffman_plan(uint64_t n, uint64_t sigma, uint32_t h_cap, uint32_t *h_bound,
+                               uint64_t *scratch_bytes) {
+    if (sigma == 0 || sigma > kHuffSyms || n >= (1ull << 32) || h_cap > (uint32_t)kHuffMaxLevels)
+        return WT_ERR_RANGE;
+    if (h_bound) *h_bound = huff_height_bound(n, sigma);
+    if (scratch_bytes) *scratch_bytes = huff_plan(n, h_cap).total;
+    return WT_OK;
+}
+
+extern "C" int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, const wt_huffman_outputs *out,
+                                uint32_t h_cap, uint32_t *h_out, void *d_scratch, uint64_t scratch_bytes,
+                                void *stream) {
+    if (sigma == 0 || sigma > kHuffSyms || n >= (1ull << 32) || h_cap > (uint32_t)kHuffMaxLevels)
+        return WT_ERR_RANGE;
+    if (!out || !out->C || !out->lens || !out->codes || !d_scratch || (n > 0 && !d_seq)) return WT_ERR_ARG;
+    if (h_cap > 0 && (!out->bits || !out->rank || !out->sel1 || !out->sel0 || !out->sel_counts || !out->nd))
+        return WT_ERR_ARG;
+    if (((uintptr_t)d_seq & 15u) || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    Plan p;
+    int rc = make_plan(n, sigma, 1, p);
+    if (rc) return rc;
+    const HuffPlan hp = huff_plan(n, h_cap);
+    if (scratch_bytes < hp.total) return WT_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    uint32_t *status = (uint32_t *)sc;
+    HuffTab *tab = (HuffTab *)(sc + hp.off_tab);
+    uint32_t *cnt = (uint32_t *)(sc + hp.off_cnt);
+    uint64_t *pre = (uint64_t *)(sc + hp.off_pre);
+    // Zero: status and the per-tile counts; C.
+    {
+        const uint64_t na = hp.off_pre / 8, nb = sigma + 1;
+        const uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
+        zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
+    }
+    if (n > 0) {
+        launch_hist<uint8_t>(d_seq, p, out->C + 1, status, nullptr, sc + hp.off_S0, false, s);
+        CScanOp cop{out->C + 1};  // sigma <= 256: one chunk
+        scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
+    }
+    huff_codes<<<1, kHuffSyms, 0, s>>>(out->C, (uint32_t)sigma, tab);
+    huff_levels<<<kHuffMaxLevels, kHuffSyms, 0, s>>>(tab);
+    if (hipMemcpyAsync(out->lens, tab->lens, sizeof(tab->lens), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(out->codes, tab->codes, sizeof(tab->codes), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return WT_ERR_HIP;
+    // The height and level sizes size the level passes: one wait.
+    struct {
+        uint32_t h, status;
+        uint64_t nd[kHuffMaxLevels];
+    } host{};
+    if (hipMemcpyAsync(&host.h, &tab->h, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&host.status, status, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(host.nd, tab->nd, sizeof(host.nd), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return WT_ERR_HIP;
+    const uint32_t h = host.h;
+    if (h_out) *h_out = h;
+    if (h > h_cap) return WT_ERR_RANGE;
+    if (host.status || h == 0 || n == 0) return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+    if (hipMemcpyAsync(out->nd, tab->nd, sizeof(uint64_t) * h, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return WT_ERR_HIP;
+    const uint64_t W = p.W;
+    huff_count0<<<(unsigned)cdiv(n, 16384), kBlock, 0, s>>>((const uint8_t *)d_seq, n, tab, cnt);
+    const uint8_t *cur = (const uint8_t *)d_seq;
+    for (uint32_t d = 0; d < h; ++d) {
+        const bool scatter = d + 1 < h;
+        const uint64_t nd = host.nd[d];
+        const uint64_t Tl = cdiv(nd, 16384);
+        uint8_t *dst = (d % 2 == 0) ? sc + hp.off_S0 : sc + hp.off_S1;
+        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)d * hp.T, pre + (uint64_t)d * hp.T, Tl);
+        HuffArgs a;
+        a.in = cur;
+        a.out = scatter ? dst : nullptr;
+        a.bits = out->bits + (uint64_t)d * W;
+        a.lut = tab->lut[d];
+        a.Dh = tab->Dh[d];
+        a.tile_prefix = pre + (uint64_t)d * hp.T;
+        a.next_cnt = scatter ? cnt + (uint64_t)(d + 1) * hp.T : nullptr;
+        a.next_shift = 14;
+        a.status = status;
+        a.rank = out->rank + (uint64_t)d * p.rank_len;
+        a.sel1 = out->sel1 + (uint64_t)d * p.cap;
+        a.sel0 = out->sel0 + (uint64_t)d * p.cap;
+        a.n = (uint32_t)nd;
+        a.out_n = scatter ? (uint32_t)host.nd[d + 1] : 0u;
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (g_timing && (rc = timing_begin(s, ev))) return rc;
+        if (scatter) huff_level_pass<true, true><<<(unsigned)Tl, kBlock, 0, s>>>(a);
+        else huff_level_pass<false, true><<<(unsigned)Tl, kBlock, 0, s>>>(a);
+        if (g_timing && (rc = timing_end(s, ev))) return rc;
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        cur = dst;
+    }
+    {
+        dim3 g((unsigned)std::max<uint64_t>(1, std::min<uint64_t>(cdiv(std::max(p.cap, W), kBlock), 1024)), h);
+        huff_dir_finish<<<g, kBlock, 0, s>>>(tab, W, out->bits, out->rank, p.rank_len, out->sel1, out->sel0, p.cap,
+                                             out->sel_counts);
+    }
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }
 

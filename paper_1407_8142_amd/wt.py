@@ -28,7 +28,7 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
            "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
-           "wt_multiary_select"]
+           "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -72,6 +72,12 @@ class MultiaryView(ctypes.Structure):
     _fields_ = [("digits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank4", ctypes.c_void_p),
                 ("sel4", ctypes.c_void_p), ("counts4", ctypes.c_void_p), ("n", ctypes.c_uint64),
                 ("sigma", ctypes.c_uint64), ("Lq", ctypes.c_uint32)]
+
+
+class HuffmanOutputs(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank", ctypes.c_void_p),
+                ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
+                ("lens", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("nd", ctypes.c_void_p)]
 
 
 class Job(ctypes.Structure):
@@ -133,12 +139,16 @@ def lib() -> ctypes.CDLL:
         L.wt_multiary_access.argtypes = [ctypes.POINTER(MultiaryView), vp, u64, vp, vp]
         L.wt_multiary_rank.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
         L.wt_multiary_select.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
+        L.wt_huffman_plan.argtypes = [u64, u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u64)]
+        L.wt_build_huffman.argtypes = [vp, u64, u64, ctypes.POINTER(HuffmanOutputs), u32, ctypes.POINTER(u32), vp,
+                                       u64, vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
                   "wt_select", "wt_set_lookback_spin_limit", "wt_timing_enable", "wt_timing_collect",
                   "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi",
                   "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix",
                   "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
-                  "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select"):
+                  "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select", "wt_huffman_plan",
+                  "wt_build_huffman"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -568,3 +578,70 @@ def to_device(S, device="cuda") -> torch.Tensor:
     import numpy as np
     raw = {1: np.int8, 2: np.int16, 4: np.int32}[S.dtype.itemsize]
     return torch.from_numpy(np.ascontiguousarray(S).view(raw)).to(device)
+
+
+@dataclass
+class WaveletHuffman:
+    """Device buffers of one Huffman-shaped wavelet tree (byte symbols),
+    sized for the largest height the input length allows (int64 tensors hold
+    uint64; lens is int32)."""
+    n: int
+    sigma: int
+    h_cap: int
+    bits: torch.Tensor
+    C: torch.Tensor
+    rank: torch.Tensor
+    sel1: torch.Tensor
+    sel0: torch.Tensor
+    sel_counts: torch.Tensor
+    lens: torch.Tensor
+    codes: torch.Tensor
+    nd: torch.Tensor
+    scratch: torch.Tensor
+    h: int = 0
+
+    @staticmethod
+    def allocate(n: int, sigma: int, device="cuda", h_cap: int | None = None) -> "WaveletHuffman":
+        L = lib()
+        hb, sb = ctypes.c_uint32(0), ctypes.c_uint64(0)
+        _check(L.wt_huffman_plan(n, sigma, 0, ctypes.byref(hb), None), "wt_huffman_plan")
+        cap = hb.value if h_cap is None else h_cap
+        _check(L.wt_huffman_plan(n, sigma, cap, None, ctypes.byref(sb)), "wt_huffman_plan")
+        lay = plan(n, sigma, 1)
+        e = lambda *shape: torch.empty(*shape, dtype=torch.int64, device=device)
+        k = max(cap, 1)
+        return WaveletHuffman(n=n, sigma=sigma, h_cap=cap, bits=e(k, lay.words_per_level), C=e(sigma + 1),
+                              rank=e(k, lay.rank_len), sel1=e(k, lay.sel_cap), sel0=e(k, lay.sel_cap),
+                              sel_counts=e(2 * k), lens=torch.empty(256, dtype=torch.int32, device=device),
+                              codes=e(256), nd=e(k),
+                              scratch=torch.empty(max(sb.value, 256), dtype=torch.uint8, device=device))
+
+    def build_from(self, seq: torch.Tensor, stream=None) -> "WaveletHuffman":
+        if not seq.is_cuda or seq.element_size() != 1 or seq.numel() != self.n or not seq.is_contiguous():
+            raise ValueError("seq must be a contiguous device tensor of n byte symbols")
+        out = HuffmanOutputs(_ptr(self.bits), _ptr(self.C), _ptr(self.rank), _ptr(self.sel1), _ptr(self.sel0),
+                             _ptr(self.sel_counts), _ptr(self.lens), _ptr(self.codes), _ptr(self.nd))
+        h = ctypes.c_uint32(0)
+        rc = lib().wt_build_huffman(_ptr(seq), self.n, self.sigma, ctypes.byref(out), self.h_cap, ctypes.byref(h),
+                                    _ptr(self.scratch), self.scratch.numel(), _stream(stream))
+        _check(rc, "wt_build_huffman")
+        self.h = int(h.value)
+        return self
+
+    def status(self, stream=None) -> int:
+        return int(lib().wt_status_get(_ptr(self.scratch), _stream(stream)))
+
+    def to_numpy(self) -> dict:
+        import numpy as np
+        u = lambda t: t.cpu().numpy().view(np.uint64)
+        h = self.h
+        counts = u(self.sel_counts)
+        return {"h": h, "n": self.n, "sigma": self.sigma, "bits": u(self.bits)[:h], "C": u(self.C),
+                "rank": u(self.rank)[:h], "sel1": u(self.sel1)[:h], "sel0": u(self.sel0)[:h],
+                "sel_counts": counts[: 2 * h], "lens": self.lens.cpu().numpy().view(np.uint32),
+                "codes": u(self.codes), "nd": u(self.nd)[:h]}
+
+
+def build_huffman(seq: torch.Tensor, sigma: int, stream=None) -> WaveletHuffman:
+    """Allocate buffers and build the Huffman-shaped wavelet tree of ``seq`` (byte symbols)."""
+    return WaveletHuffman.allocate(seq.numel(), sigma, seq.device).build_from(seq, stream)
