@@ -166,6 +166,23 @@ def multiary_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
                        "wt_build_multiary (d = 4, ceil(L/2) levels) on the same input")
 
 
+def huffman_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
+    """The same byte input built as a Huffman-shaped wavelet tree
+    (wt_build_huffman): the step time, the height, the code bits it stores
+    (the sum of its level lengths) and their rate beside sym*lvl/s."""
+    from paper_1407_8142_amd import wt
+
+    t = wt.WaveletHuffman.allocate(n, sigma, d_seq.device)
+    leg = variant_leg("huffman", lambda: t.build_from(d_seq), t.status, n, L, steps, tree_ms,
+                      "wt_build_huffman (one wait for the height, then a level pass per level) on the same input")
+    bits = int(t.nd[: t.h].sum().item())
+    leg.update({"height": t.h, "code_bits": bits, "code_bits_per_symbol": round(bits / max(n, 1), 4),
+                "code_bits_per_s": bits / (leg["ms_per_step"] / 1e3)})
+    log(f"[huffman] height {t.h}, {bits / max(n, 1):.3f} code bits per symbol, "
+        f"{leg['code_bits_per_s']:.3e} code bits/s")
+    return leg
+
+
 def batch_leg(count: int, steps: int):
     """Batched build vs one wt_build per sequence, same outputs, same GPU."""
     import ctypes
@@ -305,7 +322,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27)
     ap.add_argument("--no-matrix", action="store_true",
-                    help="skip the wavelet-matrix and 4-ary builds of the same input")
+                    help="skip the wavelet-matrix, 4-ary and Huffman-shaped builds of the same input")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -407,6 +424,8 @@ def main():
     matrix = None if args.no_matrix else matrix_leg(d_seq, n, sigma, S.dtype.itemsize, L, args.steps, ms_per_step)
     multiary = None if args.no_matrix or S.dtype.itemsize != 1 else multiary_leg(d_seq, n, sigma, L, args.steps,
                                                                                 ms_per_step)
+    huffman = None if args.no_matrix or S.dtype.itemsize != 1 or sigma > 256 else huffman_leg(
+        d_seq, n, sigma, L, args.steps, ms_per_step)
     batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
     served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb)
 
@@ -421,6 +440,7 @@ def main():
         "cpu_baseline": cpu,
         "matrix": matrix,
         "multiary": multiary,
+        "huffman": huffman,
         "batch": batch,
         "serve": served,
     }
