@@ -234,9 +234,10 @@ int wt_multiary_select(const wt_multiary_view *t, const uint32_t *d_c, const uin
  *
  * wt_huffman_plan: the largest height an input of (n, sigma) can have
  * (a leaf at depth d needs at least F(d+2) symbols, F the Fibonacci
- * numbers) and the scratch the build needs for a tree of up to h_cap levels
+ * numbers), the scratch the build needs for a tree of up to h_cap levels
  * (256-byte aligned, reused across builds, the status word first as for
- * wt_build).
+ * wt_build) and the size of the tree's tables (an opaque output the
+ * queries read: code, level tables, node starts, child links).
  *
  * wt_build_huffman: asynchronous up to the code construction, then it
  * waits once on `stream` for the height and the level sizes (they size the
@@ -252,7 +253,8 @@ int wt_multiary_select(const wt_multiary_view *t, const uint32_t *d_c, const uin
  *   C[sigma + 1]                as for wt_build;
  *   lens[256] (u32), codes[256] code length and left-aligned canonical code
  *                               (bit 63 = code bit 0) per symbol, 0 if absent;
- *   nd[h_cap]                   level sizes.
+ *   nd[h_cap]                   level sizes;
+ *   tables                      tables_bytes, 16-byte aligned, opaque.
  * *h_out (host) receives the height.  Returns WT_ERR_RANGE when the height
  * exceeds h_cap (nothing past the code construction is then enqueued),
  * WT_ERR_RANGE for sym_bytes != 1, sigma > 256 or n >= 2^32, WT_ERR_ARG for
@@ -268,11 +270,33 @@ typedef struct {
     uint32_t *lens;        /* [256] */
     uint64_t *codes;       /* [256] */
     uint64_t *nd;          /* [h_cap] */
+    void *tables;          /* tables_bytes */
 } wt_huffman_outputs;
 
-int wt_huffman_plan(uint64_t n, uint64_t sigma, uint32_t h_cap, uint32_t *h_bound, uint64_t *scratch_bytes);
+int wt_huffman_plan(uint64_t n, uint64_t sigma, uint32_t h_cap, uint32_t *h_bound, uint64_t *scratch_bytes,
+                    uint64_t *tables_bytes);
 int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, const wt_huffman_outputs *out, uint32_t h_cap,
                      uint32_t *h_out, void *d_scratch, uint64_t scratch_bytes, void *stream);
+
+/* Queries on a Huffman-shaped tree; conventions as for wt_access / wt_rank
+ * / wt_select (a symbol that does not occur has rank 0 and select -1).  A
+ * query walks the code of its symbol (access: the bits it reads) from the
+ * root: at depth d, node q starts at the node start the tables hold, the
+ * position inside it comes from rank on level d's nd[d] bits, and the child
+ * link gives the next node or the leaf.  The view holds the build's
+ * device outputs and h (0 for a tree of one symbol or none). */
+typedef struct {
+    const uint64_t *bits, *rank, *sel1, *sel0;  /* device, strides as in wt_huffman_outputs */
+    const void *tables;                          /* device */
+    uint64_t n, sigma;
+    uint32_t h;
+} wt_huffman_view;
+
+int wt_huffman_access(const wt_huffman_view *t, const uint64_t *d_i, uint64_t count, uint32_t *d_sym, void *stream);
+int wt_huffman_rank(const wt_huffman_view *t, const uint32_t *d_c, const uint64_t *d_i, uint64_t count,
+                    uint64_t *d_out, void *stream);
+int wt_huffman_select(const wt_huffman_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t count,
+                      int64_t *d_out, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched construction: many sequences of uneven length and alphabet, each

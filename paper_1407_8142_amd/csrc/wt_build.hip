@@ -1242,11 +1242,11 @@ extern "C" int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t
 }
 
 // ---------------------------------------------------------------------------
-// Huffman-shaped tree (byte alphabets): scratch = status block, HuffTab,
-// per-tile zero counts and their prefixes for h_cap levels, two sequence
-// buffers.
+// Huffman-shaped tree (byte alphabets): scratch = status block, per-tile
+// zero counts and their prefixes for h_cap levels, two sequence buffers.
+// The tables (HuffTab) are an output: the queries read them.
 struct HuffPlan {
-    uint64_t T, off_tab, off_cnt, off_pre, off_S0, off_S1, total;
+    uint64_t T, off_cnt, off_pre, off_S0, off_S1, total;
 };
 
 static uint32_t huff_height_bound(uint64_t n, uint64_t sigma) {
@@ -1268,8 +1268,6 @@ static HuffPlan huff_plan(uint64_t n, uint32_t h_cap) {
     HuffPlan p;
     p.T = align_up(std::max<uint64_t>(cdiv(n, 16384), 1), 64);
     uint64_t o = 256;
-    p.off_tab = o;
-    o = align_up(o + sizeof(HuffTab), 256);
     p.off_cnt = o;
     o = align_up(o + 4ull * (h_cap + 1) * p.T, 256);
     p.off_pre = o;
@@ -1283,11 +1281,12 @@ static HuffPlan huff_plan(uint64_t n, uint32_t h_cap) {
 }
 
 extern "C" int wt_huffman_plan(uint64_t n, uint64_t sigma, uint32_t h_cap, uint32_t *h_bound,
-                               uint64_t *scratch_bytes) {
+                               uint64_t *scratch_bytes, uint64_t *tables_bytes) {
     if (sigma == 0 || sigma > kHuffSyms || n >= (1ull << 32) || h_cap > (uint32_t)kHuffMaxLevels)
         return WT_ERR_RANGE;
     if (h_bound) *h_bound = huff_height_bound(n, sigma);
     if (scratch_bytes) *scratch_bytes = huff_plan(n, h_cap).total;
+    if (tables_bytes) *tables_bytes = sizeof(HuffTab);
     return WT_OK;
 }
 
@@ -1296,7 +1295,9 @@ extern "C" int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, c
                                 void *stream) {
     if (sigma == 0 || sigma > kHuffSyms || n >= (1ull << 32) || h_cap > (uint32_t)kHuffMaxLevels)
         return WT_ERR_RANGE;
-    if (!out || !out->C || !out->lens || !out->codes || !d_scratch || (n > 0 && !d_seq)) return WT_ERR_ARG;
+    if (!out || !out->C || !out->lens || !out->codes || !out->tables || !d_scratch || (n > 0 && !d_seq))
+        return WT_ERR_ARG;
+    if ((uintptr_t)out->tables & 15u) return WT_ERR_ARG;
     if (h_cap > 0 && (!out->bits || !out->rank || !out->sel1 || !out->sel0 || !out->sel_counts || !out->nd))
         return WT_ERR_ARG;
     if (((uintptr_t)d_seq & 15u) || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
@@ -1308,12 +1309,12 @@ extern "C" int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, c
     hipStream_t s = (hipStream_t)stream;
     unsigned char *sc = (unsigned char *)d_scratch;
     uint32_t *status = (uint32_t *)sc;
-    HuffTab *tab = (HuffTab *)(sc + hp.off_tab);
+    HuffTab *tab = (HuffTab *)out->tables;
     uint32_t *cnt = (uint32_t *)(sc + hp.off_cnt);
     uint64_t *pre = (uint64_t *)(sc + hp.off_pre);
     // Zero: status and the per-tile counts; C.
     {
-        const uint64_t na = hp.off_pre / 8, nb = sigma + 1;
+        const uint64_t na = hp.off_pre / 8, nb = sigma + 1;  // status and counts
         const uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
         zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
     }

@@ -21,26 +21,10 @@
 // the child's start in level d+1 minus the node's zeros (ones) before it.
 #pragma once
 
+#include "wt_huff_tab.hpp"
 #include "wt_kernels.hpp"
 
 namespace wt {
-
-constexpr int kHuffSyms = 256;
-constexpr int kHuffMaxLevels = 48;  // n < 2^32 bounds the height by 46 (a depth-d leaf needs F(d+2) symbols)
-
-struct HuffTab {
-    uint32_t h, m, pad[2];            // height, symbols present
-    uint64_t weight[kHuffSyms];       // occurrences per symbol
-    uint32_t lens[kHuffSyms];         // code length per symbol (0: absent, or the only symbol)
-    uint64_t codes[kHuffSyms];        // canonical code, left-aligned (bit 63 = code bit 0)
-    uint32_t order[kHuffSyms];        // present symbols in (length, symbol) order
-    uint64_t nd[kHuffMaxLevels];      // level sizes
-    uint64_t ones[kHuffMaxLevels];    // ones per level
-    uint32_t lut[kHuffMaxLevels][kHuffSyms];
-    uint32_t Dh[kHuffMaxLevels][2 * kHuffSyms];
-};
-
-constexpr uint32_t kHuffBit = 1u, kHuffNext = 2u, kHuffCont = 4u;
 
 // Code lengths and canonical codes, one block of 256 threads (thread c is
 // symbol c).  Weights come from C.  The two-queue merge is sequential (at
@@ -167,6 +151,11 @@ __global__ __launch_bounds__(kHuffSyms) void huff_levels(HuffTab *t) {
     const uint32_t b_p = deep_p ? (uint32_t)(code_p >> (63 - d)) & 1u : 0u;
     const bool first_g = deep && (!deep_p || pref_p != pref);
     const bool first_s = deep && (first_g || b_p != b);
+    // The same for depth d+1 among the leaves deeper than d+1 (the internal
+    // nodes of level d+1, for the child links).
+    const bool deep1 = deep && L > d + 1, deep1_p = deep_p && t->lens[cp] > d + 1;
+    const uint64_t pref1 = deep1 ? code >> (63 - d) : 0ull, pref1_p = deep1_p ? code_p >> (63 - d) : 0ull;
+    const bool first_g1 = deep1 && (!deep1_p || pref1_p != pref1);
     auto add = [](uint64_t x, uint64_t y) { return x + y; };
     auto add32 = [](uint32_t x, uint32_t y) { return x + y; };
     auto mx = [](uint32_t x, uint32_t y) { return x > y ? x : y; };
@@ -180,6 +169,7 @@ __global__ __launch_bounds__(kHuffSyms) void huff_levels(HuffTab *t) {
     const uint32_t q = huff_block_scan<uint32_t>(first_g ? 1u : 0u, tmp32, add32) - 1u;
     const uint32_t fg = huff_block_scan<uint32_t>(first_g ? r : 0u, tmp32, mx);
     const uint32_t fs = huff_block_scan<uint32_t>(first_s ? r : 0u, tmp32, mx);
+    const uint32_t q1 = huff_block_scan<uint32_t>(first_g1 ? 1u : 0u, tmp32, add32) - 1u;
     if (deep) {
         const bool cont = L > d + 1;
         const uint32_t key = 2u * q + b;
@@ -189,6 +179,8 @@ __global__ __launch_bounds__(kHuffSyms) void huff_levels(HuffTab *t) {
             const uint64_t before = b ? Ew[fg] - Ew0[fg] : Ew0[fg];
             t->Dh[d][key] = (uint32_t)(Ewd[fs] - before);
         }
+        if (r == fg) t->nstart[d][q] = Ew[fg];
+        t->child[d][key] = cont ? q1 : (kHuffLeaf | c);
     }
     if (r == kHuffSyms - 1) {
         t->nd[d] = iw;

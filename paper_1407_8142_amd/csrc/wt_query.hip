@@ -8,6 +8,7 @@
 
 #include "../../include/wt.h"
 #include "wt_device.hpp"
+#include "wt_huff_tab.hpp"
 
 namespace wt {
 
@@ -415,6 +416,116 @@ static bool make_tree(const wt_view *v, TreeDev &t) {
 
 constexpr int kQBlock = 256;
 
+// ---------------------------------------------------------------------------
+// Huffman-shaped tree (byte alphabets).  Level d has nd[d] bits: rank and
+// select run on a copy of the view with n = nd[d] (the strides stay those of
+// an n-symbol tree).  A walk follows the node starts and child links of the
+// build's tables; node indices are below 256 and are masked so that even a
+// malformed table cannot index past them.
+struct HuffDev {
+    TreeDev t;  // t.L = height
+    const HuffTab *tab;
+};
+
+__device__ __forceinline__ TreeDev huff_level(const HuffDev &H, uint32_t d) {
+    TreeDev x = H.t;
+    x.n = H.tab->nd[d];
+    return x;
+}
+
+__device__ __forceinline__ uint32_t huff_access_one(const HuffDev &H, uint64_t j) {
+    const HuffTab *tb = H.tab;
+    if (H.t.L == 0) return tb->order[0];  // the only symbol
+    uint32_t q = 0;
+    for (uint32_t d = 0; d < H.t.L; ++d) {
+        const TreeDev tl = huff_level(H, d);
+        if (j >= tl.n) break;  // unreachable for a well-formed tree
+        const uint64_t s = tb->nstart[d][q];
+        const uint32_t b = (uint32_t)((tl.bits[(uint64_t)d * tl.W + (j >> 6)] >> (j & 63)) & 1ull);
+        const uint64_t ones = rank1(tl, d, j) - rank1(tl, d, s);
+        const uint64_t r = b ? ones : (j - s) - ones;
+        const uint32_t ch = tb->child[d][2 * q + b];
+        if (ch & kHuffLeaf) return ch & 0xFFu;
+        if (d + 1 >= H.t.L) break;  // unreachable for a well-formed tree
+        q = ch & 0xFFu;
+        j = tb->nstart[d + 1][q] + r;
+    }
+    return 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint64_t huff_rank_one(const HuffDev &H, uint64_t c, uint64_t i) {
+    const HuffTab *tb = H.tab;
+    if (c >= H.t.sigma || tb->weight[c] == 0) return 0;
+    if (H.t.L == 0) return i;  // c is the only symbol
+    const uint32_t L = min(tb->lens[c], H.t.L);
+    uint64_t r = i;  // elements of the current node before the query position
+    for (uint32_t d = 0; d < L && r; ++d) {
+        const uint32_t key = tb->lut[d][c] >> 8, q = (key >> 1) & 0xFFu, b = key & 1u;
+        const TreeDev tl = huff_level(H, d);
+        const uint64_t s = tb->nstart[d][q];
+        if (s + r > tl.n) return 0;  // unreachable for a well-formed tree
+        const uint64_t ones = rank1(tl, d, s + r) - rank1(tl, d, s);
+        r = b ? ones : r - ones;
+    }
+    return r;
+}
+
+__device__ __forceinline__ int64_t huff_select_one(const HuffDev &H, uint64_t c, uint64_t kk) {
+    const HuffTab *tb = H.tab;
+    if (c >= H.t.sigma || kk == 0 || kk > tb->weight[c]) return -1;
+    if (H.t.L == 0) return (int64_t)(kk - 1);
+    uint64_t r = kk - 1;  // 0-based index inside the current child
+    for (uint32_t d = min(tb->lens[c], H.t.L); d-- > 0;) {
+        const uint32_t key = tb->lut[d][c] >> 8, q = (key >> 1) & 0xFFu, b = key & 1u;
+        const TreeDev tl = huff_level(H, d);
+        const uint64_t s = tb->nstart[d][q];
+        const uint64_t j = select_b(tl, d, b, rank_b(tl, d, s, b) + r);
+        if (j >= tl.n) return -1;  // unreachable for a well-formed tree
+        r = j - s;
+    }
+    return (int64_t)r;
+}
+
+__global__ void huff_access_kernel(HuffDev H, const uint64_t *qi, uint64_t m, uint32_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const uint64_t j = qi[q];
+    out[q] = j >= H.t.n ? 0xFFFFFFFFu : huff_access_one(H, j);
+}
+
+__global__ void huff_rank_kernel(HuffDev H, const uint32_t *qc, const uint64_t *qi, uint64_t m, uint64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    out[q] = huff_rank_one(H, qc[q], min(qi[q], H.t.n));
+}
+
+__global__ void huff_select_kernel(HuffDev H, const uint32_t *qc, const uint64_t *qk, uint64_t m, int64_t *out) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    out[q] = huff_select_one(H, qc[q], qk[q]);
+}
+
+static bool make_huff(const wt_huffman_view *v, HuffDev &H) {
+    if (!v || !v->tables || v->sigma == 0 || v->sigma > (uint64_t)kHuffSyms || v->h > (uint32_t)kHuffMaxLevels)
+        return false;
+    if (v->h > 0 && v->n > 0 && (!v->bits || !v->rank || !v->sel1 || !v->sel0)) return false;
+    TreeDev &t = H.t;
+    t.bits = v->bits;
+    t.C = nullptr;
+    t.rank = v->rank;
+    t.sel1 = v->sel1;
+    t.sel0 = v->sel0;
+    t.sel_counts = nullptr;
+    t.n = v->n;
+    t.sigma = v->sigma;
+    t.L = v->h;
+    t.W = (v->n + 63) / 64;
+    t.rank_len = (v->n + WT_RANK_BLOCK_BITS - 1) / WT_RANK_BLOCK_BITS + 1;
+    t.cap = (v->n + WT_SELECT_SAMPLE - 1) / WT_SELECT_SAMPLE + 1;
+    H.tab = (const HuffTab *)v->tables;
+    return true;
+}
+
 }  // namespace wt
 
 using namespace wt;
@@ -521,5 +632,38 @@ extern "C" int wt_multiary_select(const wt_multiary_view *v, const uint32_t *d_c
     if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
     quad_select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(t, d_c, d_k,
                                                                                                      m, d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_huffman_access(const wt_huffman_view *v, const uint64_t *d_i, uint64_t m, uint32_t *d_sym,
+                                 void *stream) {
+    HuffDev H;
+    if (!make_huff(v, H)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_i || !d_sym) return WT_ERR_ARG;
+    huff_access_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(H, d_i, m,
+                                                                                                     d_sym);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_huffman_rank(const wt_huffman_view *v, const uint32_t *d_c, const uint64_t *d_i, uint64_t m,
+                               uint64_t *d_out, void *stream) {
+    HuffDev H;
+    if (!make_huff(v, H)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_i || !d_out) return WT_ERR_ARG;
+    huff_rank_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(H, d_c, d_i, m,
+                                                                                                   d_out);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+extern "C" int wt_huffman_select(const wt_huffman_view *v, const uint32_t *d_c, const uint64_t *d_k, uint64_t m,
+                                 int64_t *d_out, void *stream) {
+    HuffDev H;
+    if (!make_huff(v, H)) return WT_ERR_ARG;
+    if (m == 0) return WT_OK;
+    if (!d_c || !d_k || !d_out) return WT_ERR_ARG;
+    huff_select_kernel<<<(unsigned)((m + kQBlock - 1) / kQBlock), kQBlock, 0, (hipStream_t)stream>>>(H, d_c, d_k, m,
+                                                                                                     d_out);
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }

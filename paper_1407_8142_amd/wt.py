@@ -28,7 +28,8 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_batch_plan", "wt_batch_prepare", "wt_batch_run", "wt_batch_status", "wt_query_multi", "wt_set_fused_levels",
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
            "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
-           "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman"]
+           "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank",
+           "wt_huffman_select"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -77,7 +78,14 @@ class MultiaryView(ctypes.Structure):
 class HuffmanOutputs(ctypes.Structure):
     _fields_ = [("bits", ctypes.c_void_p), ("C", ctypes.c_void_p), ("rank", ctypes.c_void_p),
                 ("sel1", ctypes.c_void_p), ("sel0", ctypes.c_void_p), ("sel_counts", ctypes.c_void_p),
-                ("lens", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("nd", ctypes.c_void_p)]
+                ("lens", ctypes.c_void_p), ("codes", ctypes.c_void_p), ("nd", ctypes.c_void_p),
+                ("tables", ctypes.c_void_p)]
+
+
+class HuffmanView(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("sel1", ctypes.c_void_p),
+                ("sel0", ctypes.c_void_p), ("tables", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("sigma", ctypes.c_uint64), ("h", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
@@ -139,7 +147,10 @@ def lib() -> ctypes.CDLL:
         L.wt_multiary_access.argtypes = [ctypes.POINTER(MultiaryView), vp, u64, vp, vp]
         L.wt_multiary_rank.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
         L.wt_multiary_select.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
-        L.wt_huffman_plan.argtypes = [u64, u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u64)]
+        L.wt_huffman_plan.argtypes = [u64, u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.wt_huffman_access.argtypes = [ctypes.POINTER(HuffmanView), vp, u64, vp, vp]
+        L.wt_huffman_rank.argtypes = [ctypes.POINTER(HuffmanView), vp, vp, u64, vp, vp]
+        L.wt_huffman_select.argtypes = [ctypes.POINTER(HuffmanView), vp, vp, u64, vp, vp]
         L.wt_build_huffman.argtypes = [vp, u64, u64, ctypes.POINTER(HuffmanOutputs), u32, ctypes.POINTER(u32), vp,
                                        u64, vp]
         for f in ("wt_plan", "wt_build", "wt_build_rank_select", "wt_status_get", "wt_access", "wt_rank",
@@ -148,7 +159,7 @@ def lib() -> ctypes.CDLL:
                   "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix",
                   "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
                   "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select", "wt_huffman_plan",
-                  "wt_build_huffman"):
+                  "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank", "wt_huffman_select"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -597,30 +608,32 @@ class WaveletHuffman:
     lens: torch.Tensor
     codes: torch.Tensor
     nd: torch.Tensor
+    tables: torch.Tensor
     scratch: torch.Tensor
     h: int = 0
 
     @staticmethod
     def allocate(n: int, sigma: int, device="cuda", h_cap: int | None = None) -> "WaveletHuffman":
         L = lib()
-        hb, sb = ctypes.c_uint32(0), ctypes.c_uint64(0)
-        _check(L.wt_huffman_plan(n, sigma, 0, ctypes.byref(hb), None), "wt_huffman_plan")
+        hb, sb, tb = ctypes.c_uint32(0), ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(L.wt_huffman_plan(n, sigma, 0, ctypes.byref(hb), None, None), "wt_huffman_plan")
         cap = hb.value if h_cap is None else h_cap
-        _check(L.wt_huffman_plan(n, sigma, cap, None, ctypes.byref(sb)), "wt_huffman_plan")
+        _check(L.wt_huffman_plan(n, sigma, cap, None, ctypes.byref(sb), ctypes.byref(tb)), "wt_huffman_plan")
         lay = plan(n, sigma, 1)
         e = lambda *shape: torch.empty(*shape, dtype=torch.int64, device=device)
         k = max(cap, 1)
         return WaveletHuffman(n=n, sigma=sigma, h_cap=cap, bits=e(k, lay.words_per_level), C=e(sigma + 1),
                               rank=e(k, lay.rank_len), sel1=e(k, lay.sel_cap), sel0=e(k, lay.sel_cap),
                               sel_counts=e(2 * k), lens=torch.empty(256, dtype=torch.int32, device=device),
-                              codes=e(256), nd=e(k),
+                              codes=e(256), nd=e(k), tables=torch.empty(tb.value, dtype=torch.uint8, device=device),
                               scratch=torch.empty(max(sb.value, 256), dtype=torch.uint8, device=device))
 
     def build_from(self, seq: torch.Tensor, stream=None) -> "WaveletHuffman":
         if not seq.is_cuda or seq.element_size() != 1 or seq.numel() != self.n or not seq.is_contiguous():
             raise ValueError("seq must be a contiguous device tensor of n byte symbols")
         out = HuffmanOutputs(_ptr(self.bits), _ptr(self.C), _ptr(self.rank), _ptr(self.sel1), _ptr(self.sel0),
-                             _ptr(self.sel_counts), _ptr(self.lens), _ptr(self.codes), _ptr(self.nd))
+                             _ptr(self.sel_counts), _ptr(self.lens), _ptr(self.codes), _ptr(self.nd),
+                             _ptr(self.tables))
         h = ctypes.c_uint32(0)
         rc = lib().wt_build_huffman(_ptr(seq), self.n, self.sigma, ctypes.byref(out), self.h_cap, ctypes.byref(h),
                                     _ptr(self.scratch), self.scratch.numel(), _stream(stream))
@@ -630,6 +643,36 @@ class WaveletHuffman:
 
     def status(self, stream=None) -> int:
         return int(lib().wt_status_get(_ptr(self.scratch), _stream(stream)))
+
+    def view(self) -> HuffmanView:
+        return HuffmanView(_ptr(self.bits), _ptr(self.rank), _ptr(self.sel1), _ptr(self.sel0), _ptr(self.tables),
+                           self.n, self.sigma, self.h)
+
+    def access(self, i: torch.Tensor, stream=None) -> torch.Tensor:
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int32, device=i.device)
+        v = self.view()
+        _check(lib().wt_huffman_access(ctypes.byref(v), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_huffman_access")
+        return out
+
+    def rank_query(self, c: torch.Tensor, i: torch.Tensor, stream=None) -> torch.Tensor:
+        c = c.to(torch.int32).contiguous()
+        i = i.to(torch.int64).contiguous()
+        out = torch.empty(i.numel(), dtype=torch.int64, device=i.device)
+        v = self.view()
+        _check(lib().wt_huffman_rank(ctypes.byref(v), _ptr(c), _ptr(i), i.numel(), _ptr(out), _stream(stream)),
+               "wt_huffman_rank")
+        return out
+
+    def select_query(self, c: torch.Tensor, k: torch.Tensor, stream=None) -> torch.Tensor:
+        c = c.to(torch.int32).contiguous()
+        k = k.to(torch.int64).contiguous()
+        out = torch.empty(k.numel(), dtype=torch.int64, device=k.device)
+        v = self.view()
+        _check(lib().wt_huffman_select(ctypes.byref(v), _ptr(c), _ptr(k), k.numel(), _ptr(out), _stream(stream)),
+               "wt_huffman_select")
+        return out
 
     def to_numpy(self) -> dict:
         import numpy as np

@@ -144,5 +144,6 @@ def test_fullsize_huffman(wtmod, oracle_mod, text):
         assert int(got["nd"][dd]) == int(sum(hist[c] for c in deeper)), dd
         ones = int(sum(hist[c] for c in deeper if (int(codes[c]) >> (63 - dd)) & 1))
         assert int(pc[dd]) == ones and int(got["rank"][dd, -1]) == ones, dd
+    sampled_queries(S, t.access, t.rank_query, t.select_query, 4)
     del t
     torch.cuda.empty_cache()

@@ -123,3 +123,60 @@ def test_huffman_rebuild_same_buffers(wtmod, oracle_mod):
         got = t.to_numpy()
         assert got["h"] == want["h"]
         assert np.array_equal(got["bits"], want["bits"]) and np.array_equal(got["rank"], want["rank"])
+
+
+def _naive_rank(S, c, i):
+    return int(np.count_nonzero(S[: min(i, S.size)] == c))
+
+
+def _naive_select(S, c, k):
+    if k <= 0:
+        return -1
+    pos = np.flatnonzero(S == c)
+    return int(pos[k - 1]) if k <= pos.size else -1
+
+
+@pytest.mark.parametrize("case", ["tiny", "zipf", "uniform", "fibonacci", "constant", "one", "sparse", "text"])
+def test_huffman_queries(wtmod, oracle_mod, case):
+    rng = np.random.default_rng(hash(case) % 977)
+    if case == "tiny":
+        S, sigma = np.array([0, 3, 1, 0, 2, 0, 0, 3, 0], np.uint8), 5
+    elif case == "zipf":
+        S, sigma = (np.minimum(rng.zipf(1.2, 70001), 256) - 1).astype(np.uint8), 256
+    elif case == "uniform":
+        S, sigma = rng.integers(0, 146, 50000).astype(np.uint8), 146
+    elif case == "fibonacci":
+        fib = [1, 1]
+        while len(fib) < 22:
+            fib.append(fib[-1] + fib[-2])
+        S, sigma = rng.permutation(np.repeat(np.arange(22), fib)).astype(np.uint8), 22
+    elif case == "constant":
+        S, sigma = np.full(3000, 4, np.uint8), 9
+    elif case == "one":
+        S, sigma = np.array([7], np.uint8), 8
+    elif case == "sparse":
+        S, sigma = (rng.integers(0, 6, 40000) * 41).astype(np.uint8), 250
+    else:
+        S, sigma = inputs.text_like(1 << 20), 256
+    say(f"[huffman queries] {case}: n={S.size} sigma={sigma}")
+    t = check(wtmod, oracle_mod, S, sigma, f"queries {case}")
+    n = S.size
+    dev = torch.device("cuda")
+    if n <= 16:
+        qi = np.arange(n + 2)
+        cs = np.repeat(np.arange(sigma + 2), n + 2)
+        js = np.tile(np.arange(n + 2), sigma + 2)
+    else:
+        qi = rng.integers(0, n + 3, 3000)
+        cs = np.where(rng.random(3000) < 0.85, S[rng.integers(0, n, 3000)], rng.integers(0, sigma + 2, 3000))
+        js = rng.integers(0, n + 3, 3000)
+    acc = t.access(torch.from_numpy(qi).to(dev)).cpu().numpy().view(np.uint32)
+    want = np.where(qi < n, S.astype(np.int64)[np.minimum(qi, n - 1)], 0xFFFFFFFF).astype(np.uint32)
+    assert np.array_equal(acc, want)
+    rk = t.rank_query(torch.from_numpy(cs.astype(np.int32)).to(dev), torch.from_numpy(js).to(dev)).cpu().numpy()
+    assert all(int(rk[q]) == (_naive_rank(S, int(cs[q]), int(js[q])) if cs[q] < sigma else 0) for q in range(cs.size))
+    counts = np.bincount(S, minlength=256)
+    ks = js if n <= 16 else np.minimum(js, counts[np.minimum(cs, 255)] + 2)
+    sl = t.select_query(torch.from_numpy(cs.astype(np.int32)).to(dev), torch.from_numpy(ks).to(dev)).cpu().numpy()
+    assert all(int(sl[q]) == (_naive_select(S, int(cs[q]), int(ks[q])) if cs[q] < sigma else -1)
+               for q in range(cs.size))

@@ -227,19 +227,21 @@ def test_huffman_plan_and_argument_errors_are_synchronous():
     # height bound: the largest d with F(d+2) <= n, at most sigma - 1
     for n, sigma, want in [(0, 256, 0), (1, 256, 0), (2, 256, 1), (3, 256, 2), (4, 256, 2), (5, 256, 3),
                            (1 << 28, 256, 40), (1 << 28, 5, 4), (1000, 1, 0)]:
-        assert lib.wt_huffman_plan(n, sigma, 0, ctypes.byref(hb), None) == wt.WT_OK
+        assert lib.wt_huffman_plan(n, sigma, 0, ctypes.byref(hb), None, None) == wt.WT_OK
         assert hb.value == want, (n, sigma, hb.value)
-    assert lib.wt_huffman_plan(1 << 20, 256, 10, None, ctypes.byref(sb)) == wt.WT_OK and sb.value > 2 << 20
-    assert lib.wt_huffman_plan(1 << 20, 257, 10, None, None) == wt.WT_ERR_RANGE
-    assert lib.wt_huffman_plan(1 << 32, 256, 10, None, None) == wt.WT_ERR_RANGE
-    assert lib.wt_huffman_plan(100, 256, 49, None, None) == wt.WT_ERR_RANGE
+    tb = ctypes.c_uint64(0)
+    assert lib.wt_huffman_plan(1 << 20, 256, 10, None, ctypes.byref(sb), ctypes.byref(tb)) == wt.WT_OK
+    assert sb.value > 2 << 20 and tb.value > 0
+    assert lib.wt_huffman_plan(1 << 20, 257, 10, None, None, None) == wt.WT_ERR_RANGE
+    assert lib.wt_huffman_plan(1 << 32, 256, 10, None, None, None) == wt.WT_ERR_RANGE
+    assert lib.wt_huffman_plan(100, 256, 49, None, None, None) == wt.WT_ERR_RANGE
     out = wt.HuffmanOutputs()
     h = ctypes.c_uint32(0)
     assert lib.wt_build_huffman(ctypes.c_void_p(16), 10, 300, ctypes.byref(out), 4, ctypes.byref(h),
                                 ctypes.c_void_p(256), 1 << 20, None) == wt.WT_ERR_RANGE
     assert lib.wt_build_huffman(ctypes.c_void_p(16), 10, 200, ctypes.byref(out), 4, ctypes.byref(h),
                                 ctypes.c_void_p(256), 1 << 20, None) == wt.WT_ERR_ARG
-    out.C = out.lens = out.codes = ctypes.c_void_p(4096)
+    out.C = out.lens = out.codes = out.tables = ctypes.c_void_p(4096)
     assert lib.wt_build_huffman(ctypes.c_void_p(16), 10, 200, ctypes.byref(out), 4, ctypes.byref(h),
                                 ctypes.c_void_p(256), 1 << 20, None) == wt.WT_ERR_ARG
     out.bits = out.rank = out.sel1 = out.sel0 = out.sel_counts = out.nd = ctypes.c_void_p(8192)
@@ -247,3 +249,10 @@ def test_huffman_plan_and_argument_errors_are_synchronous():
                                 ctypes.c_void_p(256), 1 << 20, None) == wt.WT_ERR_ARG
     assert lib.wt_build_huffman(ctypes.c_void_p(16), 100000, 200, ctypes.byref(out), 4, ctypes.byref(h),
                                 ctypes.c_void_p(256), 64, None) == wt.WT_ERR_SCRATCH
+    assert lib.wt_huffman_access(None, None, 5, None, None) == wt.WT_ERR_ARG
+    v = wt.HuffmanView()
+    v.n, v.sigma, v.h = 10, 300, 2
+    v.tables = ctypes.c_void_p(4096)
+    assert lib.wt_huffman_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG  # sigma > 256
+    v.sigma = 200
+    assert lib.wt_huffman_select(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG  # no bits
