@@ -221,6 +221,20 @@ int wt_multiary_rank(const wt_multiary_view *t, const uint32_t *d_c, const uint6
 int wt_multiary_select(const wt_multiary_view *t, const uint32_t *d_c, const uint64_t *d_k, uint64_t count,
                        int64_t *d_out, void *stream);
 
+/* ---- sortWT (section "sortWT") ------------------------------------------
+ * A second construction of the same tree (the same outputs as wt_build with
+ * directories, bit for bit), independent of the level passes: level l is
+ * bit L-1-l of S stably sorted by its top l bits, so the levels are built
+ * side by side: per level a count of each key per tile, a scan of those
+ * counts per key, a stable scatter into a sorted copy of S, and the bits of
+ * that copy; then the directories by the standalone builder.  Byte symbols
+ * only (sym_bytes 1, n < 2^32, else WT_ERR_RANGE).  The scratch
+ * (wt_sort_scratch_bytes; 0 when out of range) holds every sorted copy, L n
+ * bytes.  Outputs, errors and wt_status_get as for wt_build. */
+uint64_t wt_sort_scratch_bytes(uint64_t n, uint64_t sigma);
+int wt_build_sort(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                  void *d_scratch, uint64_t scratch_bytes, void *stream);
+
 /* ---- Huffman-shaped wavelet tree (section "Extensions") ----------------
  * Byte symbols only (sym_bytes 1, sigma <= 256, n < 2^32).  The shape is the
  * canonical tree of the Huffman code lengths of the symbols that occur:

@@ -29,6 +29,7 @@
 #include "wt_pair.hpp"
 #include "wt_quad.hpp"
 #include "wt_huff.hpp"
+#include "wt_sort.hpp"
 
 namespace wt {
 
@@ -1382,6 +1383,76 @@ extern "C" int wt_build_huffman(const void *d_seq, uint64_t n, uint64_t sigma, c
                                              out->sel_counts);
     }
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// sortWT (byte alphabets): scratch = status block, tile counts and starts per
+// (level, key, tile), the L sorted copies of S, the directory builder's.
+struct SortPlan {
+    uint64_t T, off_cnt, off_base, off_S, off_rs, total;
+};
+
+static SortPlan sort_plan(uint64_t n, uint32_t L) {
+    SortPlan p;
+    p.T = std::max<uint64_t>(cdiv(n, kSortTile), 1);
+    uint64_t o = 256;
+    p.off_cnt = o;
+    o = align_up(o + 4ull * L * kSortKeys * p.T, 256);
+    p.off_base = o;
+    o = align_up(o + 8ull * L * kSortKeys * p.T, 256);
+    p.off_S = o;
+    o = align_up(o + (uint64_t)L * align_up(n, 256), 256);
+    p.off_rs = o;
+    o = align_up(o + wt_rank_select_scratch_bytes(n, L), 256);
+    p.total = o;
+    return p;
+}
+
+extern "C" uint64_t wt_sort_scratch_bytes(uint64_t n, uint64_t sigma) {
+    if (sigma == 0 || sigma > 256 || n >= (1ull << 32)) return 0;
+    return sort_plan(n, levels_of(sigma)).total;
+}
+
+extern "C" int wt_build_sort(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                             void *d_scratch, uint64_t scratch_bytes, void *stream) {
+    Plan p;
+    int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    if (sym_bytes != 1 || n >= (1ull << 32)) return WT_ERR_RANGE;  // byte alphabets
+    if (!out || !out->C || !d_scratch || (n > 0 && !d_seq)) return WT_ERR_ARG;
+    if (p.L > 0 && (!out->rank || !out->sel1 || !out->sel0 || !out->sel_counts || (n > 0 && !out->bits)))
+        return WT_ERR_ARG;
+    if (((uintptr_t)d_seq & 15u) || ((uintptr_t)d_scratch & 255u)) return WT_ERR_ARG;
+    const SortPlan sp = sort_plan(n, p.L);
+    if (scratch_bytes < sp.total) return WT_ERR_SCRATCH;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *sc = (unsigned char *)d_scratch;
+    uint32_t *status = (uint32_t *)sc;
+    {
+        const uint64_t blocks = std::min<uint64_t>(cdiv(32 + sigma + 1, kBlock), 4096);
+        zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, 32, out->C, sigma + 1);
+    }
+    if (n > 0) {
+        launch_hist<uint8_t>(d_seq, p, out->C + 1, status, nullptr, sc + sp.off_S, false, s);
+        CScanOp cop{out->C + 1};  // sigma <= 256: one chunk
+        scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
+    }
+    if (p.L == 0) return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+    const uint64_t stride = align_up(n, 256);
+    uint32_t *cnt = (uint32_t *)(sc + sp.off_cnt);
+    uint64_t *base = (uint64_t *)(sc + sp.off_base);
+    uint8_t *sorted = sc + sp.off_S;
+    if (n > 0) {
+        const dim3 gt((unsigned)sp.T, p.L), gk(kSortKeys, p.L);
+        sort_count<<<gt, kBlock, 0, s>>>((const uint8_t *)d_seq, n, p.L, sp.T, cnt);
+        sort_scan<<<gk, kBlock, 0, s>>>(cnt, out->C, sigma, p.L, sp.T, base);
+        sort_scatter<<<gt, kBlock, 0, s>>>((const uint8_t *)d_seq, n, p.L, sp.T, base, sorted, stride);
+        const dim3 gb((unsigned)cdiv(p.W, kWaves), p.L);
+        sort_bits<<<gb, kBlock, 0, s>>>(sorted, n, p.L, stride, out->bits, p.W);
+    }
+    if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+    return wt_build_rank_select(out->bits, n, p.L, out->rank, out->sel1, out->sel0, out->sel_counts,
+                                sc + sp.off_rs, sp.total - sp.off_rs, stream);
 }
 
 extern "C" int wt_status_get(const void *d_scratch, void *stream) {

@@ -29,7 +29,7 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
            "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
            "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank",
-           "wt_huffman_select"]
+           "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 
 
@@ -149,6 +149,9 @@ def lib() -> ctypes.CDLL:
         L.wt_multiary_select.argtypes = [ctypes.POINTER(MultiaryView), vp, vp, u64, vp, vp]
         L.wt_huffman_plan.argtypes = [u64, u64, u32, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.wt_huffman_access.argtypes = [ctypes.POINTER(HuffmanView), vp, u64, vp, vp]
+        L.wt_sort_scratch_bytes.argtypes = [u64, u64]
+        L.wt_sort_scratch_bytes.restype = u64
+        L.wt_build_sort.argtypes = [vp, u64, u64, i32, ctypes.POINTER(Outputs), vp, u64, vp]
         L.wt_huffman_rank.argtypes = [ctypes.POINTER(HuffmanView), vp, vp, u64, vp, vp]
         L.wt_huffman_select.argtypes = [ctypes.POINTER(HuffmanView), vp, vp, u64, vp, vp]
         L.wt_build_huffman.argtypes = [vp, u64, u64, ctypes.POINTER(HuffmanOutputs), u32, ctypes.POINTER(u32), vp,
@@ -159,7 +162,8 @@ def lib() -> ctypes.CDLL:
                   "wt_set_fused_levels", "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix",
                   "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
                   "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select", "wt_huffman_plan",
-                  "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank", "wt_huffman_select"):
+                  "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank", "wt_huffman_select",
+                  "wt_build_sort"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -688,3 +692,23 @@ class WaveletHuffman:
 def build_huffman(seq: torch.Tensor, sigma: int, stream=None) -> WaveletHuffman:
     """Allocate buffers and build the Huffman-shaped wavelet tree of ``seq`` (byte symbols)."""
     return WaveletHuffman.allocate(seq.numel(), sigma, seq.device).build_from(seq, stream)
+
+
+def build_sort(seq: torch.Tensor, sigma: int, stream=None, tree: WaveletTree | None = None) -> WaveletTree:
+    """Build the tree of ``seq`` (byte symbols) by sortWT (wt_build_sort): the
+    same outputs as ``build`` with directories, from the sorted copies of S
+    instead of the level passes.  ``tree``, when given, is reused (its
+    scratch grown to the sortWT size)."""
+    n = seq.numel()
+    if not seq.is_cuda or seq.element_size() != 1 or not seq.is_contiguous():
+        raise ValueError("seq must be a contiguous device tensor of byte symbols")
+    nbytes = int(lib().wt_sort_scratch_bytes(n, sigma))
+    if nbytes == 0:
+        raise WTError(WT_ERR_RANGE, "wt_sort_scratch_bytes")
+    t = tree if tree is not None else WaveletTree.allocate(n, sigma, 1, True, seq.device)
+    if t.scratch.numel() < nbytes:
+        t.scratch = torch.empty(nbytes, dtype=torch.uint8, device=seq.device)
+    out = Outputs(_ptr(t.bits), _ptr(t.C), _ptr(t.rank), _ptr(t.sel1), _ptr(t.sel0), _ptr(t.sel_counts))
+    _check(lib().wt_build_sort(_ptr(seq), n, sigma, 1, ctypes.byref(out), _ptr(t.scratch), t.scratch.numel(),
+                               _stream(stream)), "wt_build_sort")
+    return t

@@ -8,7 +8,9 @@ against what holds at any size and against answers computed one by one:
   bit, resp. code bit, is set at that level), and the last rank entry;
 - the Huffman code lengths and codes against the oracle's code
   construction on the same counts, and its level sizes against the weights;
-- sampled access, rank and select answers against S itself.
+- sampled access, rank and select answers against S itself;
+- the sortWT construction (sorted copies of S, no level passes) against the
+  level-pass build, every output buffer bit for bit.
 Integer work: tolerance zero."""
 import sys
 
@@ -146,4 +148,17 @@ def test_fullsize_huffman(wtmod, oracle_mod, text):
         assert int(pc[dd]) == ones and int(got["rank"][dd, -1]) == ones, dd
     sampled_queries(S, t.access, t.rank_query, t.select_query, 4)
     del t
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_sort_equals_level_passes(wtmod, text):
+    S, sigma, hist, d = text
+    say("[fullsize] sortWT against the level passes")
+    a = wtmod.build(d, sigma)
+    b = wtmod.build_sort(d, sigma)
+    torch.cuda.synchronize()
+    assert a.status() == wtmod.WT_OK and b.status() == wtmod.WT_OK
+    for k in ("bits", "C", "rank", "sel1", "sel0", "sel_counts"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    del a, b
     torch.cuda.empty_cache()

@@ -256,3 +256,20 @@ def test_huffman_plan_and_argument_errors_are_synchronous():
     assert lib.wt_huffman_rank(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG  # sigma > 256
     v.sigma = 200
     assert lib.wt_huffman_select(ctypes.byref(v), None, None, 5, None, None) == wt.WT_ERR_ARG  # no bits
+
+
+def test_sort_scratch_and_argument_errors_are_synchronous():
+    lib = wt.lib()
+    assert lib.wt_sort_scratch_bytes(1000, 300) == 0
+    assert lib.wt_sort_scratch_bytes(1 << 32, 256) == 0
+    # the scratch holds L sorted copies of S
+    assert lib.wt_sort_scratch_bytes(1 << 20, 256) >= 8 << 20
+    out = wt.Outputs()
+    assert lib.wt_build_sort(ctypes.c_void_p(16), 10, 300, 2, ctypes.byref(out), ctypes.c_void_p(256), 1 << 20,
+                             None) == wt.WT_ERR_RANGE
+    assert lib.wt_build_sort(ctypes.c_void_p(16), 10, 200, 1, ctypes.byref(out), ctypes.c_void_p(256), 1 << 20,
+                             None) == wt.WT_ERR_ARG
+    out.C = ctypes.c_void_p(4096)
+    out.bits = out.rank = out.sel1 = out.sel0 = out.sel_counts = ctypes.c_void_p(8192)
+    assert lib.wt_build_sort(ctypes.c_void_p(16), 100000, 200, 1, ctypes.byref(out), ctypes.c_void_p(256), 64,
+                             None) == wt.WT_ERR_SCRATCH
