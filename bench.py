@@ -183,6 +183,17 @@ def huffman_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
     return leg
 
 
+def sort_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
+    """The same byte input built by sortWT (wt_build_sort): a sorted copy of S
+    per level instead of the level passes, the same outputs."""
+    from paper_1407_8142_amd import wt
+
+    t = wt.WaveletTree.allocate(n, sigma, 1, True, d_seq.device)
+    wt.build_sort(d_seq, sigma, tree=t)  # grows the scratch once
+    return variant_leg("sort", lambda: wt.build_sort(d_seq, sigma, tree=t), t.status, n, L, steps, tree_ms,
+                       "wt_build_sort (every level from S stably sorted by its top l bits) on the same input")
+
+
 def batch_leg(count: int, steps: int):
     """Batched build vs one wt_build per sequence, same outputs, same GPU."""
     import ctypes
@@ -322,7 +333,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 27)
     ap.add_argument("--no-matrix", action="store_true",
-                    help="skip the wavelet-matrix, 4-ary and Huffman-shaped builds of the same input")
+                    help="skip the wavelet-matrix, 4-ary, Huffman-shaped and sortWT builds of the same input")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -426,6 +437,8 @@ def main():
                                                                                 ms_per_step)
     huffman = None if args.no_matrix or S.dtype.itemsize != 1 or sigma > 256 else huffman_leg(
         d_seq, n, sigma, L, args.steps, ms_per_step)
+    sortwt = None if args.no_matrix or S.dtype.itemsize != 1 or sigma > 256 else sort_leg(
+        d_seq, n, sigma, L, args.steps, ms_per_step)
     batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
     served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb)
 
@@ -441,6 +454,7 @@ def main():
         "matrix": matrix,
         "multiary": multiary,
         "huffman": huffman,
+        "sort": sortwt,
         "batch": batch,
         "serve": served,
     }

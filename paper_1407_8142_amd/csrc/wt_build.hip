@@ -1447,7 +1447,7 @@ extern "C" int wt_build_sort(const void *d_seq, uint64_t n, uint64_t sigma, int 
         sort_count<<<gt, kBlock, 0, s>>>((const uint8_t *)d_seq, n, p.L, sp.T, cnt);
         sort_scan<<<gk, kBlock, 0, s>>>(cnt, out->C, sigma, p.L, sp.T, base);
         sort_scatter<<<gt, kBlock, 0, s>>>((const uint8_t *)d_seq, n, p.L, sp.T, base, sorted, stride);
-        const dim3 gb((unsigned)cdiv(p.W, kWaves), p.L);
+        const dim3 gb((unsigned)cdiv(p.W, kBlock), p.L);
         sort_bits<<<gb, kBlock, 0, s>>>(sorted, n, p.L, stride, out->bits, p.W);
     }
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;

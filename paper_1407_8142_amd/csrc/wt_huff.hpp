@@ -30,8 +30,8 @@ namespace wt {
 // symbol c).  Weights come from C.  The two-queue merge is sequential (at
 // most 255 joins); everything else is a count over the other symbols.
 __global__ __launch_bounds__(kHuffSyms) void huff_codes(const uint64_t *C, uint32_t sigma, HuffTab *t) {
-    __shared__ uint64_t w[kHuffSyms], iw[kHuffSyms];
-    __shared__ uint32_t leafq[kHuffSyms], lparent[kHuffSyms], len[kHuffSyms];
+    __shared__ uint64_t w[kHuffSyms], iw[kHuffSyms], wq[kHuffSyms];
+    __shared__ uint32_t lparent[kHuffSyms], len[kHuffSyms];
     __shared__ uint32_t iparent[kHuffSyms], idepth[kHuffSyms];
     __shared__ uint32_t s_m, s_h;
     const uint32_t c = threadIdx.x;
@@ -43,10 +43,10 @@ __global__ __launch_bounds__(kHuffSyms) void huff_codes(const uint64_t *C, uint3
     }
     __syncthreads();
     const bool here = w[c] != 0;
+    uint32_t rq = 0;  // rank in (weight, symbol) order: the leaf queue
     if (here) {
-        uint32_t r = 0;  // rank in (weight, symbol) order
-        for (uint32_t x = 0; x < kHuffSyms; ++x) r += w[x] != 0 && (w[x] < w[c] || (w[x] == w[c] && x < c));
-        leafq[r] = c;
+        for (uint32_t x = 0; x < kHuffSyms; ++x) rq += w[x] != 0 && (w[x] < w[c] || (w[x] == w[c] && x < c));
+        wq[rq] = w[c];
         atomicAdd(&s_m, 1u);
     }
     __syncthreads();
@@ -55,22 +55,26 @@ __global__ __launch_bounds__(kHuffSyms) void huff_codes(const uint64_t *C, uint3
         // Join the two smallest of (leaf queue head, internal queue head):
         // a leaf comes first on equal weight; internal nodes appear in
         // non-decreasing weight, so their queue is their creation order.
+        // The two heads stay in registers (one LDS read per join step).
+        constexpr uint64_t kNone = ~0ull;
         uint32_t lh = 0, ih = 0, ni = 0;
+        uint64_t lw = wq[0], hw = kNone;
         for (uint32_t s = 0; s + 1 < m; ++s) {
             uint64_t sum = 0;
-#pragma unroll 1
+#pragma unroll
             for (int k = 0; k < 2; ++k) {
-                if (lh < m && (ih >= ni || w[leafq[lh]] <= iw[ih])) {
-                    const uint32_t x = leafq[lh++];
-                    sum += w[x];
-                    lparent[x] = s;
+                if (lh < m && (ih >= ni || lw <= hw)) {
+                    sum += lw;
+                    lparent[lh++] = s;  // by queue rank
+                    lw = lh < m ? wq[lh] : kNone;
                 } else {
-                    const uint32_t x = ih++;
-                    sum += iw[x];
-                    iparent[x] = s;
+                    sum += hw;
+                    iparent[ih++] = s;
+                    hw = ih < ni ? iw[ih] : kNone;
                 }
             }
             iw[s] = sum;
+            if (ih == s) hw = sum;  // the new node heads an empty queue
             ni = s + 1;
         }
         idepth[m - 2] = 0;
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(kHuffSyms) void huff_codes(const uint64_t *C, uint3
     }
     __syncthreads();
     if (m >= 2 && here) {
-        len[c] = idepth[lparent[c]] + 1;
+        len[c] = idepth[lparent[rq]] + 1;
         atomicMax(&s_h, len[c]);
     }
     __syncthreads();

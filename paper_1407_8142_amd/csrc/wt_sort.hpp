@@ -11,7 +11,7 @@
 //                 order: lanes holding the same key are found by a ballot
 //                 per key bit, and a per-wave running count per key lives
 //                 in LDS), then S_l[start + rank] = x;
-//   sort_bits:    B_l from S_l, one ballot per word.
+//   sort_bits:    B_l from S_l, a bit word per thread from four 16-byte loads.
 // The directories come from the standalone builder.  The paper finds sortWT
 // slower than levelWT (it writes every level's sorted copy); here it serves
 // as a cross-check of the level passes at any size.
@@ -119,16 +119,31 @@ __global__ __launch_bounds__(kBlock) void sort_scatter(const uint8_t *S, uint64_
     }
 }
 
+// Thread t of the grid makes bit word t of level l from 64 sorted symbols:
+// four 16-byte loads, the bit of four bytes at a time gathered by shifts and
+// ORs.  The copy is padded to 256 bytes; bits past n are masked off.
 __global__ __launch_bounds__(kBlock) void sort_bits(const uint8_t *Sl, uint64_t n, uint32_t L, uint64_t stride,
                                                     uint64_t *bits, uint64_t W) {
-    const uint32_t l = blockIdx.y;
-    const int lane = lane_id();
-    const uint64_t w = (uint64_t)blockIdx.x * kWaves + threadIdx.x / kWave;
-    if (w >= W) return;  // whole waves
-    const uint64_t p = (w << 6) + (uint64_t)lane;
-    const bool v = p < n && ((Sl[(uint64_t)l * stride + p] >> (L - 1 - l)) & 1u);
-    const uint64_t word = __ballot(v);
-    if (lane == 0) bits[(uint64_t)l * W + w] = word;
+    const uint32_t l = blockIdx.y, k = L - 1 - l;
+    const uint64_t w = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (w >= W) return;
+    const uint4 *src = reinterpret_cast<const uint4 *>(Sl + (uint64_t)l * stride + (w << 6));
+    uint64_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 v = src[q];
+        const uint32_t dw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // bit k of byte i of dw[j] -> bit 4j + i of the 16-bit group
+            uint32_t x = (dw[j] >> k) & 0x01010101u;
+            x = (x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xFu;
+            word |= (uint64_t)x << (16 * q + 4 * j);
+        }
+    }
+    const uint64_t rem = n - (w << 6);
+    if (rem < 64) word &= (1ull << rem) - 1ull;
+    bits[(uint64_t)l * W + w] = word;
 }
 
 }  // namespace wt
