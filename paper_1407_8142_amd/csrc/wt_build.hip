@@ -30,6 +30,7 @@
 #include "wt_quad.hpp"
 #include "wt_huff.hpp"
 #include "wt_sort.hpp"
+#include "wt_u16.hpp"
 
 namespace wt {
 
@@ -430,6 +431,12 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     level_tile_u8<SCATTER, DIRS>(a, blockIdx.x, s);
 }
 
+template <bool SCATTER, bool DIRS>
+__global__ __launch_bounds__(kBlock) void level_pass_u16(LevelArgs a) {
+    __shared__ LdsLevelU16 s;
+    level_tile_u16<SCATTER, DIRS>(a, blockIdx.x, s);
+}
+
 
 // ---------------------------------------------------------------------------
 // Fused tail levels (see fused_segment): the largest node of every level,
@@ -749,6 +756,17 @@ static void launch_level(bool scatter, bool dirs, hipStream_t s, const LevelArgs
         } else {
             if (dirs) level_pass_u8<false, true><<<g8, b8, 0, s>>>(a);
             else level_pass_u8<false, false><<<g8, b8, 0, s>>>(a);
+        }
+        return;
+    }
+    if (sizeof(TIN) == 2 && sizeof(TOUT) == 2 && a.n < (1ull << 32)) {
+        dim3 g16((unsigned)cdiv(a.n, LdsLevelU16::kTile)), b16(kBlock);
+        if (scatter) {
+            if (dirs) level_pass_u16<true, true><<<g16, b16, 0, s>>>(a);
+            else level_pass_u16<true, false><<<g16, b16, 0, s>>>(a);
+        } else {
+            if (dirs) level_pass_u16<false, true><<<g16, b16, 0, s>>>(a);
+            else level_pass_u16<false, false><<<g16, b16, 0, s>>>(a);
         }
         return;
     }
