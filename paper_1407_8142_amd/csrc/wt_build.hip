@@ -31,6 +31,7 @@
 #include "wt_huff.hpp"
 #include "wt_sort.hpp"
 #include "wt_u16.hpp"
+#include "wt_u32.hpp"
 
 namespace wt {
 
@@ -437,6 +438,12 @@ __global__ __launch_bounds__(kBlock) void level_pass_u16(LevelArgs a) {
     level_tile_u16<SCATTER, DIRS>(a, blockIdx.x, s);
 }
 
+template <bool SCATTER, bool DIRS>
+__global__ __launch_bounds__(kBlock) void level_pass_u32(LevelArgs a) {
+    __shared__ LdsLevelU32 s;
+    level_tile_u32<SCATTER, DIRS>(a, blockIdx.x, s);
+}
+
 
 // ---------------------------------------------------------------------------
 // Fused tail levels (see fused_segment): the largest node of every level,
@@ -767,6 +774,17 @@ static void launch_level(bool scatter, bool dirs, hipStream_t s, const LevelArgs
         } else {
             if (dirs) level_pass_u16<false, true><<<g16, b16, 0, s>>>(a);
             else level_pass_u16<false, false><<<g16, b16, 0, s>>>(a);
+        }
+        return;
+    }
+    if (sizeof(TIN) == 4 && sizeof(TOUT) == 4 && a.n < (1ull << 32)) {
+        dim3 g32((unsigned)cdiv(a.n, LdsLevelU32::kTile)), b32(kBlock);
+        if (scatter) {
+            if (dirs) level_pass_u32<true, true><<<g32, b32, 0, s>>>(a);
+            else level_pass_u32<true, false><<<g32, b32, 0, s>>>(a);
+        } else {
+            if (dirs) level_pass_u32<false, true><<<g32, b32, 0, s>>>(a);
+            else level_pass_u32<false, false><<<g32, b32, 0, s>>>(a);
         }
         return;
     }
