@@ -438,10 +438,10 @@ __global__ __launch_bounds__(kBlock) void level_pass_u16(LevelArgs a) {
     level_tile_u16<SCATTER, DIRS>(a, blockIdx.x, s);
 }
 
-template <bool SCATTER, bool DIRS>
+template <typename TOUT, bool SCATTER, bool DIRS>
 __global__ __launch_bounds__(kBlock) void level_pass_u32(LevelArgs a) {
     __shared__ LdsLevelU32 s;
-    level_tile_u32<SCATTER, DIRS>(a, blockIdx.x, s);
+    level_tile_u32<TOUT, SCATTER, DIRS>(a, blockIdx.x, s);
 }
 
 
@@ -777,14 +777,14 @@ static void launch_level(bool scatter, bool dirs, hipStream_t s, const LevelArgs
         }
         return;
     }
-    if (sizeof(TIN) == 4 && sizeof(TOUT) == 4 && a.n < (1ull << 32)) {
+    if (sizeof(TIN) == 4 && a.n < (1ull << 32)) {
         dim3 g32((unsigned)cdiv(a.n, LdsLevelU32::kTile)), b32(kBlock);
         if (scatter) {
-            if (dirs) level_pass_u32<true, true><<<g32, b32, 0, s>>>(a);
-            else level_pass_u32<true, false><<<g32, b32, 0, s>>>(a);
+            if (dirs) level_pass_u32<TOUT, true, true><<<g32, b32, 0, s>>>(a);
+            else level_pass_u32<TOUT, true, false><<<g32, b32, 0, s>>>(a);
         } else {
-            if (dirs) level_pass_u32<false, true><<<g32, b32, 0, s>>>(a);
-            else level_pass_u32<false, false><<<g32, b32, 0, s>>>(a);
+            if (dirs) level_pass_u32<TOUT, false, true><<<g32, b32, 0, s>>>(a);
+            else level_pass_u32<TOUT, false, false><<<g32, b32, 0, s>>>(a);
         }
         return;
     }

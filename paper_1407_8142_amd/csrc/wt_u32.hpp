@@ -10,8 +10,10 @@
 //            past a short tile read as 0xFFFFFFFF, ones that land on unread
 //            slots;
 //   scatter: four slots per lane; a run (same node, same bit) leaves as one
-//            16-byte store.  Node tables of up to kD32 entries are kept in
-//            LDS, larger ones read from global memory per chunk.
+//            store (16 bytes, or 8 / 4 when the next level is 16 / 8 bits
+//            wide: a 32-bit input whose alphabet fits fewer bits).  Node
+//            tables of up to kD32 entries are kept in LDS, larger ones read
+//            from global memory per chunk.
 #pragma once
 
 #include "wt_kernels.hpp"
@@ -30,7 +32,7 @@ struct LdsLevelU32 {
     CountTable ct;
 };
 
-template <bool SCATTER, bool DIRS>
+template <typename TOUT, bool SCATTER, bool DIRS>
 __device__ __forceinline__ void level_tile_u32(const LevelArgs &a, uint32_t tile, LdsLevelU32 &s) {
     constexpr int kTile = LdsLevelU32::kTile, kRows = LdsLevelU32::kRows, kRowSyms = LdsLevelU32::kRowSyms;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
@@ -141,7 +143,7 @@ __device__ __forceinline__ void level_tile_u32(const LevelArgs &a, uint32_t tile
     const uint32_t kn = k - 1;
     const uint32_t n4 = a.n > 3 ? (uint32_t)(a.n - 3) : 0u;  // dest < n4 <=> dest + 3 < n
     const uint32_t qmax = (uint32_t)a.nD - 1u;
-    uint32_t *out = reinterpret_cast<uint32_t *>(a.out);
+    TOUT *out = reinterpret_cast<TOUT *>(a.out);
     auto dbase = [&](uint32_t q) -> uint32_t { return d_lds ? s.D[q] : (uint32_t)a.D[q]; };
     const uint4 *s_st128 = reinterpret_cast<const uint4 *>(s.stage);
     constexpr int kChunksPerWave = kTile / 4 / kWaves;
@@ -157,7 +159,17 @@ __device__ __forceinline__ void level_tile_u32(const LevelArgs &a, uint32_t tile
             if (sl + 3 < len && q0 == q3) {
                 const uint32_t dest = dbase(q0) + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
                 if (dest < n4) {
-                    *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                    if constexpr (sizeof(TOUT) == 4) {
+                        *reinterpret_cast<u128_unaligned *>(out + dest) = u128_unaligned{v.x, v.y, v.z, v.w};
+                    } else if constexpr (sizeof(TOUT) == 2) {
+                        typedef uint32_t u64_unaligned __attribute__((ext_vector_type(2), aligned(2)));
+                        *reinterpret_cast<u64_unaligned *>(out + dest) =
+                            u64_unaligned{(v.x & 0xFFFFu) | (v.y << 16), (v.z & 0xFFFFu) | (v.w << 16)};
+                    } else {
+                        typedef uint32_t u32_unaligned __attribute__((aligned(1)));
+                        *reinterpret_cast<u32_unaligned *>(out + dest) =
+                            (v.x & 0xFFu) | ((v.y & 0xFFu) << 8) | ((v.z & 0xFFu) << 16) | (v.w << 24);
+                    }
                     const uint32_t nt = dest >> a.next_shift;
                     const uint32_t ones = ((v.x >> kn) & 1u) + ((v.y >> kn) & 1u) + ((v.z >> kn) & 1u) +
                                           ((v.w >> kn) & 1u);
@@ -177,7 +189,7 @@ __device__ __forceinline__ void level_tile_u32(const LevelArgs &a, uint32_t tile
                     const uint32_t qc = min((x >> k) & a.qmask, qmax), sc = sl + c;
                     const uint32_t dest = dbase(qc) + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
                     if (dest < a.n) {
-                        out[dest] = x;
+                        out[dest] = (TOUT)x;
                         if (!((x >> kn) & 1u)) count_add(s.ct, a.next_cnt, dest >> a.next_shift, 1u);
                     }
                 }
