@@ -433,8 +433,10 @@ int wt_set_level_pairs(int enable);
  * predecessor found unpublished.  Default 8.  Applies to later launches. */
 int wt_set_lookback_spin_limit(int polls);
 
-/* Kernel timing for measurement tools.  While enabled, wt_build brackets
- * every level-pass launch with a pair of HIP events on its stream.
+/* Kernel timing for measurement tools.  While enabled, every level-pass
+ * launch of wt_build (and of the matrix and Huffman builds) carries a start
+ * and a stop HIP event in its own dispatch on its stream (hipExtLaunchKernel),
+ * so each pair times that kernel.
  * wt_timing_collect waits for the recorded events, writes up to `cap`
  * durations in milliseconds (launch order) and returns how many launches
  * were recorded since the previous collect (or a negative wt_status). */
