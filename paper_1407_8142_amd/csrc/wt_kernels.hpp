@@ -664,6 +664,23 @@ __device__ __forceinline__ void level_tile(const LevelArgs &a, uint64_t tile, Ld
 //          unaligned) 16-byte store.
 typedef uint32_t u128_unaligned __attribute__((ext_vector_type(4), aligned(1)));
 
+// A + 2^(s mod 32): v_lshl_add_u32 reads its shift amount mod 32, so a split
+// cursor can advance by an unmasked selector (no AND per byte).
+__device__ __forceinline__ uint32_t add_pow2_mod32(uint32_t A, uint32_t s) {
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, 1, %1, %2" : "=v"(r) : "v"(s), "v"(A));
+    return r;
+}
+
+// x >> 8 that the compiler cannot fold into later shifts: bytes 1 and 3 of
+// x then leave from its low byte and from bits 16..23 (a d16_hi LDS write),
+// with one shift for both.
+__device__ __forceinline__ uint32_t shr8_opaque(uint32_t x) {
+    uint32_t r;
+    asm("v_lshrrev_b32 %0, 8, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t mask16_bit(uint4 d, uint32_t k) {
     // Transpose so that byte B of t_i is byte 4B+i of the chunk ...
     const uint32_t a0 = __builtin_amdgcn_perm(d.y, d.x, 0x05010400u);
@@ -813,12 +830,17 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             // Bit 8i+4 of T is bit k of byte i (a rotation right by k-4 mod 32).
+            // The field offset of v_bfe_u32 and the amount of a shift are the
+            // low five bits of their operands, so T >> 8i serves unmasked:
+            // its bits 0..4 are 16 times bit k of byte i.
             const uint32_t T = __builtin_amdgcn_alignbit(dw[j], dw[j], (k + 28u) & 31u) & 0x10101010u;
+            const uint32_t h = shr8_opaque(dw[j]);  // bytes 1 and 3 in the low bytes of its halves
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t sh = (T >> (8 * i)) & 31u;
-                s.stage[__builtin_amdgcn_ubfe(A, sh, 16u)] = (uint8_t)(dw[j] >> (8 * i));
-                A += 1u << sh;
+                const uint32_t sh = T >> (8 * i);
+                const uint32_t src = (i & 1) ? h : dw[j];
+                s.stage[__builtin_amdgcn_ubfe(A, sh, 16u)] = (uint8_t)(src >> (16 * (i >> 1)));
+                A = add_pow2_mod32(A, sh);
             }
         }
     }
