@@ -394,23 +394,31 @@ struct LevelArgs {
 // is full falls back to a direct atomic.
 constexpr int kCountSlots = 64;
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
-struct CountTable {
-    uint32_t key[kCountSlots];
-    uint32_t cnt[kCountSlots];
+// LOG2: log2 of the slot count (the byte pass, whose blocks touch only a
+// few destination tiles, takes 32 slots to fit one more block per CU).
+template <int LOG2>
+struct CountTableN {
+    static constexpr int kSlots = 1 << LOG2;
+    uint32_t key[kSlots];
+    uint32_t cnt[kSlots];
 };
+using CountTable = CountTableN<6>;
+static_assert(CountTable::kSlots == kCountSlots, "pair tables share the slot count");
 
-__device__ __forceinline__ void count_init(CountTable &t, int tid) {
-    if (tid < kCountSlots) {
+template <int LOG2>
+__device__ __forceinline__ void count_init(CountTableN<LOG2> &t, int tid) {
+    if (tid < CountTableN<LOG2>::kSlots) {
         t.key[tid] = kNoTile;
         t.cnt[tid] = 0;
     }
 }
 
-__device__ __forceinline__ void count_add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+template <int LOG2>
+__device__ __forceinline__ void count_add(CountTableN<LOG2> &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
     // Hashed slot with a short linear probe: the tiles one block touches are
     // few but can be far apart by large powers of two (a run of zeros and a
     // run of ones half a level apart), so the low bits alone would collide.
-    uint32_t slot = (ntile * 0x9E3779B9u) >> 26;
+    uint32_t slot = (ntile * 0x9E3779B9u) >> (32 - LOG2);
 #pragma unroll 1
     for (int probe = 0; probe < 8; ++probe) {
         const uint32_t old = atomicCAS(&t.key[slot], kNoTile, ntile);
@@ -418,20 +426,23 @@ __device__ __forceinline__ void count_add(CountTable &t, uint32_t *next_cnt, uin
             atomicAdd(&t.cnt[slot], c);
             return;
         }
-        slot = (slot + 1) & (kCountSlots - 1);
+        slot = (slot + 1) & (CountTableN<LOG2>::kSlots - 1);
     }
     atomicAdd(next_cnt + ntile, c);
 }
 
-__device__ __forceinline__ void count_flush(CountTable &t, uint32_t *next_cnt, int tid) {
-    if (tid < kCountSlots && t.key[tid] != kNoTile && t.cnt[tid]) atomicAdd(next_cnt + t.key[tid], t.cnt[tid]);
+template <int LOG2>
+__device__ __forceinline__ void count_flush(CountTableN<LOG2> &t, uint32_t *next_cnt, int tid) {
+    if (tid < CountTableN<LOG2>::kSlots && t.key[tid] != kNoTile && t.cnt[tid])
+        atomicAdd(next_cnt + t.key[tid], t.cnt[tid]);
 }
 
 // Hands every lane's (tile, c) with `want` set to the table with one update
 // per distinct tile of the wave: the lanes of a wave mostly fill the same
 // destination tile, and 64 lanes updating one LDS slot would serialize.
 // Called by all lanes of the wave.
-__device__ __forceinline__ void count_add_wave(CountTable &t, uint32_t *next_cnt, bool want, uint32_t tile,
+template <int LOG2>
+__device__ __forceinline__ void count_add_wave(CountTableN<LOG2> &t, uint32_t *next_cnt, bool want, uint32_t tile,
                                                uint32_t c, int lane) {
     uint64_t pend = __ballot(want);
     while (pend) {
@@ -447,7 +458,8 @@ __device__ __forceinline__ void count_add_wave(CountTable &t, uint32_t *next_cnt
 // Per-lane running count for one destination tile.
 struct LaneCount {
     uint32_t tile = kNoTile, cnt = 0;
-    __device__ __forceinline__ void add(CountTable &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
+    template <int LOG2>
+    __device__ __forceinline__ void add(CountTableN<LOG2> &t, uint32_t *next_cnt, uint32_t ntile, uint32_t c) {
         if (ntile != tile) {
             if (cnt) count_add(t, next_cnt, tile, cnt);
             tile = ntile;
@@ -466,12 +478,14 @@ struct LaneCount {
         }
         cnt += c;
     }
-    __device__ __forceinline__ void flush(CountTable &t, uint32_t *next_cnt) {
+    template <int LOG2>
+    __device__ __forceinline__ void flush(CountTableN<LOG2> &t, uint32_t *next_cnt) {
         if (cnt) count_add(t, next_cnt, tile, cnt);
         cnt = 0;
     }
     // flush by all lanes of the wave
-    __device__ __forceinline__ void flush_wave(CountTable &t, uint32_t *next_cnt, int lane) {
+    template <int LOG2>
+    __device__ __forceinline__ void flush_wave(CountTableN<LOG2> &t, uint32_t *next_cnt, int lane) {
         count_add_wave(t, next_cnt, cnt != 0, tile, cnt, lane);
         cnt = 0;
     }
@@ -691,11 +705,17 @@ __device__ __forceinline__ uint32_t mask16_bit(uint4 d, uint32_t k) {
     const uint32_t t1 = __builtin_amdgcn_perm(a2, a0, 0x07060302u);
     const uint32_t t2 = __builtin_amdgcn_perm(a3, a1, 0x05040100u);
     const uint32_t t3 = __builtin_amdgcn_perm(a3, a1, 0x07060302u);
-    // ... then byte B of u holds bit k of chunk bytes 4B..4B+3 at bits 0..3.
+    // ... then byte B of u holds bit k of chunk bytes 4B..4B+3 at bits 0..3:
+    // a rotation right by k - i (mod 32) takes bit k of every byte of t_i to
+    // bit i of that byte (k < 8, so no bit crosses into the wrong byte).
     const uint32_t M = 0x01010101u;
-    uint32_t u = ((t0 >> k) & M) | (((t1 >> k) & M) << 1) | (((t2 >> k) & M) << 2) | (((t3 >> k) & M) << 3);
+    uint32_t u = __builtin_amdgcn_alignbit(t0, t0, k & 31u) & M;
+    u |= __builtin_amdgcn_alignbit(t1, t1, (k - 1u) & 31u) & (M << 1);
+    u |= __builtin_amdgcn_alignbit(t2, t2, (k - 2u) & 31u) & (M << 2);
+    u |= __builtin_amdgcn_alignbit(t3, t3, (k - 3u) & 31u) & (M << 3);
+    // Bytes 0 and 2 of u | u >> 4 hold positions 0..7 and 8..15.
     u |= u >> 4;
-    return (u & 0xFFu) | ((u >> 8) & 0xFF00u);
+    return __builtin_amdgcn_perm(u, u, 0x0C0C0200u);
 }
 
 __device__ __forceinline__ uint32_t byte_of(const uint4 &d, int b) {
@@ -708,9 +728,9 @@ struct LdsLevelU8 {
     __align__(16) uint8_t stage[kTile];
     __align__(16) uint16_t m16[kTile / 16];  // 256 words of B_l
     uint32_t wz[kRows][kWaves];
-    uint32_t zpre[kTile / 64];
+    uint16_t zpre[kTile / 64];  // at most kTile
     uint32_t D[256];
-    CountTable ct;
+    CountTableN<5> ct;  // with the 16-bit zpre: 8 blocks per CU fit in LDS
 };
 
 template <bool SCATTER, bool DIRS>
