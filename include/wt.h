@@ -408,10 +408,14 @@ int wt_set_fused_levels(int enable);
 /* Wide-alphabet histogram (on by default).  For sigma > 8192, wt_build counts
  * symbols in 2^16-symbol slices of packed 16-bit LDS counters, one row of
  * counts per input chunk, summed by a second kernel (the rows use the
- * sequence ping-pong of the scratch, idle at that point); inputs too short
- * for that use per-block LDS hashing with global atomics.  C is the same
- * either way.  0 selects the hashing path for later launches (for
- * comparisons). */
+ * sequence ping-pong of the scratch, idle at that point).  Trees of more
+ * than 16 levels over 32-bit symbols (2^20 <= n < 2^32) count in two
+ * phases instead: the groups of the top L-16 bits before level 0 (all that
+ * the levels above L-16 need), then, once S_{L-16} holds each group as a
+ * contiguous segment, the low 16 bits segment by segment.  Inputs too short
+ * for either use per-block LDS hashing with global atomics.  C and every
+ * output are the same on all paths.  0 selects the hashing path for later
+ * launches (for comparisons). */
 int wt_set_sliced_histogram(int enable);
 
 /* Two levels per pass (off by default).  When on, for byte symbols

@@ -29,6 +29,7 @@
 #include "wt_kernels.hpp"
 #include "wt_pair.hpp"
 #include "wt_quad.hpp"
+#include "wt_hist2.hpp"
 #include "wt_huff.hpp"
 #include "wt_sort.hpp"
 #include "wt_u16.hpp"
@@ -1075,6 +1076,16 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
     // (inputs too small for that are the fused pass's), 32-bit positions.
     const bool pairs = g_pairs && !matrix && !fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
                        n < (1ull << 32);
+    // Wide alphabets (more than 16 levels): the two-phase histogram (see
+    // hist_coarse / hist_fine) when its rows, overflow counts and tags fit
+    // the idle ping-pong buffer at level c and no level before c can fuse.
+    const uint32_t cbits = p.L > kFineBits ? p.L - kFineBits : 0u;
+    const uint32_t fine_blocks = (uint32_t)std::min(num_cus(), 1024);
+    const uint64_t fine_rows = (uint64_t)fine_blocks << kFineBits;  // u32 counts
+    const uint64_t fine_bytes = 4 * fine_rows + 8 * align_up(sigma, 32) + 4 * 1024;
+    const bool two_phase = g_slices && !matrix && !pairs && cbits >= 1 && cbits <= kCoarseMaxBits &&
+                           sym_bytes == 4 && p.mid_bytes == 4 && n >= (1ull << 20) && n < (1ull << 32) &&
+                           fine_bytes <= align_up(n * p.mid_bytes, 256) && (!fuse || lmin >= cbits);
 
     // Zero: status + per-tile zero counts (one contiguous range), and C.
     {
@@ -1082,7 +1093,19 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
         uint64_t blocks = std::min<uint64_t>(cdiv(na + nb, kBlock), 4096);
         zero_fill<<<(unsigned)blocks, kBlock, 0, s>>>((uint64_t *)sc, na, out->C, nb);
     }
-    if (n > 0) {
+    if (n > 0 && two_phase) {
+        // Coarse phase: group counts into the idle S1 (level 0 writes S0),
+        // level-0 tile zeros, the symbol check; then C at the group starts.
+        unsigned long long *cc = (unsigned long long *)(sc + p.off_S1);
+        zero_fill<<<1, kBlock, 0, s>>>((uint64_t *)cc, 1ull << cbits, nullptr, 0);
+        const uint32_t shift = tile_shift_for(4);
+        const uint64_t ntiles = cdiv(n, 1ull << shift);
+        const uint32_t reps = std::min<uint32_t>(16u, kCoarseTab / ((1u << cbits) + 1u));
+        const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)num_cus() * 8));
+        hist_coarse<uint32_t><<<(unsigned)blocks, kBlock, 0, s>>>((const uint32_t *)d_seq, n, sigma, p.L, cbits, reps,
+                                                                   shift, ntiles, cnt, cc, status);
+        coarse_to_C<<<1, 1024, 0, s>>>(cc, cbits, p.L, sigma, out->C);
+    } else if (n > 0) {
         void *rows = sc + p.off_S0;
         if (sym_bytes == 1) launch_hist<uint8_t>(d_seq, p, out->C + 1, status, cnt, rows, pairs, s);
         else if (sym_bytes == 2) launch_hist<uint16_t>(d_seq, p, out->C + 1, status, cnt, rows, false, s);
@@ -1098,10 +1121,12 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
             scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
         }
     }
-    if (p.L > 0) {
-        // Node tables for every level.
+    // Node tables of the heap's first `count` entries (levels below
+    // log2(count)), from C; with `tail`, the directory tails, the matrix
+    // tables and the fusion plan, which need every level.
+    uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
+    auto tables = [&](uint64_t count, bool tail) {
         TableOp top{out->C, D, sigma, p.L};
-        uint64_t count = 1ull << p.L;
         uint64_t chunks = cdiv(count, kScanChunk);
         if (chunks > 1) {
             scan_reduce<TableOp><<<(unsigned)chunks, kBlock, 0, s>>>(top, count, part);
@@ -1110,20 +1135,32 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
         } else {
             scan_final<TableOp><<<1, kBlock, 0, s>>>(top, count, nullptr);
         }
+        if (!tail) return;
         if (dirs) {
             dim3 g((unsigned)cdiv(p.cap, kBlock), p.L);
             dir_finish<<<g, kBlock, 0, s>>>(D, nullptr, n, p.L, out->rank, p.rank_len, out->sel1, out->sel0, p.cap,
                                             out->sel_counts);
         }
         if (matrix) matrix_tables<<<1, kWave, 0, s>>>(D, p.L, Dm, d_zeros);
-    }
-    uint32_t *fused_l0 = (uint32_t *)(sc + p.off_status + kOffFusedL0);
-    if (fuse) {
-        unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
-        const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << p.L, kBlock), 2048));
-        node_max_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(out->C, sigma, p.L, maxnode);
-        fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), fused_l0);
-    }
+        if (fuse) {
+            unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
+            const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << p.L, kBlock), 2048));
+            node_max_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(out->C, sigma, p.L, maxnode);
+            fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), fused_l0);
+        }
+    };
+    auto c_scan = [&]() {
+        CScanOp cop{out->C + 1};
+        uint64_t chunks = cdiv(sigma, kScanChunk);
+        if (chunks > 1) {
+            scan_reduce<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+            scan_partials_seg<CScanOp><<<1, kBlock, 0, s>>>(cop, chunks, part);
+            scan_final<CScanOp><<<(unsigned)chunks, kBlock, 0, s>>>(cop, sigma, part);
+        } else {
+            scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
+        }
+    };
+    if (p.L > 0) tables(two_phase ? (1ull << cbits) : (1ull << p.L), !two_phase);
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     if (n == 0 || p.L == 0) return WT_OK;
     if (pairs) return run_pairs(d_seq, p, out, sc, dirs, s);
@@ -1131,6 +1168,25 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
     const void *cur = d_seq;
     uint32_t cur_w = p.in_bytes;
     for (uint32_t l = 0; l < p.L; ++l) {
+        if (two_phase && l == cbits) {
+            // Fine phase over S_c (in `cur`), into the other buffer: the
+            // rows, the overflow and later-segment counts, the tags; then
+            // every count, C, and the tables of all levels.
+            unsigned char *fb = (unsigned char *)((l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1));
+            uint32_t *rows = (uint32_t *)fb;
+            unsigned long long *extra = (unsigned long long *)(fb + 4 * fine_rows);
+            uint32_t *tags = (uint32_t *)(fb + 4 * fine_rows + 8 * align_up(sigma, 32));
+            zero_fill<<<(unsigned)std::min<uint64_t>(cdiv(sigma, kBlock), 4096), kBlock, 0, s>>>((uint64_t *)extra,
+                                                                                                sigma, nullptr, 0);
+            const uint64_t per = align_up(cdiv(n, fine_blocks), 4);
+            hist_fine<<<fine_blocks, kFineThreads, 0, s>>>((const uint32_t *)cur, n, sigma, cbits, out->C, per, rows,
+                                                           tags, extra, status);
+            hist_fine_reduce<<<(unsigned)std::min<uint64_t>(cdiv(sigma, kBlock), 4096), kBlock, 0, s>>>(
+                rows, tags, fine_blocks, extra, sigma, out->C + 1);
+            c_scan();
+            tables(1ull << p.L, true);
+            if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        }
         const bool scatter = l + 1 < p.L;
         void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
         // Tile prefixes of this level from the counts its predecessor left.
