@@ -264,13 +264,17 @@ __global__ __launch_bounds__(kSliceThreads) void hist_slices(const T *__restrict
     for (uint32_t i = tid; i < nb; i += kSliceThreads) part[row + i] = (bins[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
 }
 
-// Cp1[c] += sum of the chunk rows of `part` at c.
+// Cp1[c] += sum of the chunk rows of `part` at c.  Group blockIdx.y of
+// gridDim.y sums its share of the rows and adds it atomically (Cp1 already
+// holds the counters' overflow hand-overs), so many rows are summed by many
+// threads at once.
 __global__ __launch_bounds__(kBlock) void hist_reduce(const uint32_t *__restrict__ part, uint64_t nchunks,
                                                       uint64_t sigma, uint64_t *Cp1) {
+    const uint64_t per = cdiv(nchunks, gridDim.y), k0 = blockIdx.y * per, k1 = min(nchunks, k0 + per);
     for (uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x; c < sigma; c += (uint64_t)gridDim.x * kBlock) {
-        uint64_t t = Cp1[c];
-        for (uint64_t k = 0; k < nchunks; ++k) t += part[k * sigma + c];
-        Cp1[c] = t;
+        uint64_t t = 0;
+        for (uint64_t k = k0; k < k1; ++k) t += part[k * sigma + c];
+        if (t) atomicAdd((unsigned long long *)(Cp1 + c), (unsigned long long)t);
     }
 }
 
@@ -887,7 +891,8 @@ static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, ui
                                                             shift, p.L - 1, cnt0, (unsigned long long *)Cp1,
                                                             (uint32_t *)rows, status);
     const uint64_t rblocks = std::min<uint64_t>(cdiv(p.sigma, kBlock), 4096);
-    hist_reduce<<<(unsigned)rblocks, kBlock, 0, s>>>((const uint32_t *)rows, nchunks, p.sigma, Cp1);
+    const dim3 rgrid((unsigned)rblocks, (unsigned)std::min<uint64_t>(nchunks, 16));
+    hist_reduce<<<rgrid, kBlock, 0, s>>>((const uint32_t *)rows, nchunks, p.sigma, Cp1);
     return true;
 }
 
