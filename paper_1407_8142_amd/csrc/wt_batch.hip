@@ -46,6 +46,8 @@
 #include "../../include/wt.h"
 #include "wt_device.hpp"
 #include "wt_kernels.hpp"
+#include "wt_u16.hpp"
+#include "wt_u32.hpp"
 
 namespace wt {
 namespace batch {
@@ -127,10 +129,24 @@ struct LdsJobHist {
     BlockScanTmp scan;
 };
 
+// Level items: byte tiles and wider tiles run in launches of their own, each
+// with only its own LDS (the byte pass keeps eight blocks per CU); the
+// persistent form holds every kind.
+union LdsLevels8 {
+    LdsLevelU8 u8;
+    BlockScanTmp scan;
+};
+union LdsLevelsWide {
+    LdsLevelU16 u16;
+    LdsLevelU32 u32;
+    LdsLevel<uint16_t> g16;
+    BlockScanTmp scan;
+};
 union LdsLevels {
     LdsLevelU8 u8;
+    LdsLevelU16 u16;
+    LdsLevelU32 u32;
     LdsLevel<uint16_t> g16;
-    LdsLevel<uint32_t> g32;
     BlockScanTmp scan;
 };
 
@@ -369,8 +385,8 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
     if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
 }
 
-template <uint32_t KINDS>
-__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LdsLevels &s) {
+template <uint32_t KINDS, typename LV>
+__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LV &s) {
     const bool scatter = l + 1 < j.L;
     const uint32_t win = l == 0 ? j.in_bytes : j.mid_bytes, wout = j.mid_bytes;
     LevelArgs a;
@@ -399,15 +415,18 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
         return;
     }
     if constexpr ((KINDS & kHasLevelWide) != 0) {
+        // The SWAR passes of wt_build for 16- and 32-bit levels (a job has
+        // n < 2^32); the generic pass for a 16-bit input with byte levels
+        // after it.
         if (scatter) {
             if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
-            else if (win == 2) level_tile<uint16_t, uint16_t, true, true>(a, tile, s.g16);
-            else if (wout == 1) level_tile<uint32_t, uint8_t, true, true>(a, tile, s.g32);
-            else if (wout == 2) level_tile<uint32_t, uint16_t, true, true>(a, tile, s.g32);
-            else level_tile<uint32_t, uint32_t, true, true>(a, tile, s.g32);
+            else if (win == 2) level_tile_u16<true, true>(a, tile, s.u16);
+            else if (wout == 1) level_tile_u32<uint8_t, true, true>(a, tile, s.u32);
+            else if (wout == 2) level_tile_u32<uint16_t, true, true>(a, tile, s.u32);
+            else level_tile_u32<uint32_t, true, true>(a, tile, s.u32);
         } else {
-            if (win == 2) level_tile<uint16_t, uint16_t, false, true>(a, tile, s.g16);
-            else level_tile<uint32_t, uint32_t, false, true>(a, tile, s.g32);
+            if (win == 2) level_tile_u16<false, true>(a, tile, s.u16);
+            else level_tile_u32<uint32_t, false, true>(a, tile, s.u32);
         }
     }
 }
@@ -494,7 +513,7 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
         }
     } else {
         if constexpr ((KINDS & kHasLevel) != 0) {
-            LdsLevels &lv = [&]() -> LdsLevels & {
+            auto &lv = [&]() -> auto & {
                 if constexpr (KINDS == kHasAll) return s.lv;
                 else return s;
             }();
@@ -820,8 +839,8 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
         else if (phase == 1) work_kernel<kHasJobHist, LdsJobHist><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if (phase == 2) work_kernel<kHasPrep, LdsPrep><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if (phase == last) work_kernel<kHasFused, LdsFusedAll><<<(unsigned)grid, kBlock, 0, s>>>(a);
-        else if ((phase - 3) % 2 == 0) work_kernel<kHasLevel8, LdsLevels><<<(unsigned)grid, kBlock, 0, s>>>(a);
-        else work_kernel<kHasLevelWide, LdsLevels><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if ((phase - 3) % 2 == 0) work_kernel<kHasLevel8, LdsLevels8><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else work_kernel<kHasLevelWide, LdsLevelsWide><<<(unsigned)grid, kBlock, 0, s>>>(a);
     };
     if (t.mode == WT_BATCH_PERSISTENT) {
         launch(0, 0, lay->items);
