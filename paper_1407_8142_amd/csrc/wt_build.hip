@@ -113,7 +113,7 @@ __device__ __forceinline__ std::conditional_t<DIG, uint64_t, uint32_t> hist_coun
 }
 
 template <typename T, bool DIG>
-__global__ __launch_bounds__(kBlock) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void histogram(const T *__restrict__ S, uint64_t n, uint64_t sigma,
                                                     unsigned long long *Cp1, uint32_t *status, uint32_t reps,
                                                     uint32_t ktop, void *cnt0, uint32_t tile_shift,
                                                     uint64_t ntiles) {
