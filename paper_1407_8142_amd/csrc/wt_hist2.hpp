@@ -22,7 +22,7 @@
 namespace wt {
 
 constexpr uint32_t kCoarseMaxBits = 9;    // 2^c + 1 entries of C from one block of 1024 threads
-constexpr uint32_t kCoarseTab = 8192;     // LDS words of the coarse table (replicas x (2^c + 1))
+constexpr uint32_t kCoarseTab = 2048;     // LDS words of the coarse table (replicas x (2^c + 1)): 8 KiB, 8 blocks per CU
 constexpr uint32_t kFineBits = 16;        // symbols per segment: 2^16 packed counters = 128 KiB of LDS
 constexpr int kFineThreads = 1024;
 constexpr uint32_t kNoSeg = 0xFFFFFFFFu;
