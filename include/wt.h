@@ -116,6 +116,23 @@ int wt_build_rank_select(const uint64_t *d_bits, uint64_t n, uint32_t L,
 
 uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L);
 
+/* Which histogram wt_build runs for (n, sigma, sym_bytes) under the calling
+ * thread's settings (host only; for tests and measurement tools).  Every
+ * path gives the same C and outputs; they differ in cost:
+ *   WT_HIST_NONE       n = 0
+ *   WT_HIST_REPLICAS   sigma <= 8192: per-lane LDS replicas of the counts
+ *   WT_HIST_HASH       an LDS hash flushed by global atomics
+ *   WT_HIST_SLICES     sigma > 8192: 2^16-symbol slices of 16-bit LDS counters, a row per chunk
+ *   WT_HIST_TWO_PHASE  more than 16 levels over 32-bit symbols: groups of the top L-16 bits
+ *                      before level 0, the low 16 bits per segment of S_(L-16) later
+ * Returns one of these or WT_ERR_ARG / WT_ERR_RANGE as wt_plan. */
+#define WT_HIST_NONE 0
+#define WT_HIST_REPLICAS 1
+#define WT_HIST_HASH 2
+#define WT_HIST_SLICES 3
+#define WT_HIST_TWO_PHASE 4
+int wt_histogram_path(uint64_t n, uint64_t sigma, int sym_bytes);
+
 /* Wait for `stream`, then return WT_OK or the data error recorded by the
  * last wt_build that used d_scratch (WT_ERR_SYMBOL). */
 int wt_status_get(const void *d_scratch, void *stream);
@@ -397,6 +414,10 @@ int wt_batch_status(const wt_batch_layout *lay, const void *d_scratch, int32_t *
 #define WT_Q_BAD (-2)
 int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tree, const uint8_t *d_kind,
                    const uint64_t *d_a, const uint64_t *d_b, uint64_t m, int64_t *d_out, void *stream);
+
+/* The wt_set_* settings below are per host thread: each applies to the later
+ * launches made from the thread that set it, and other threads keep their
+ * own values (defaults as stated). */
 
 /* Fused tail levels (on by default).  Once every node of a level fits in one
  * block's LDS, wt_build and wt_batch_run run that level and all deeper ones

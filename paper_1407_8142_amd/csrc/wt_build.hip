@@ -714,11 +714,14 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     return WT_OK;
 }
 
-static bool g_timing = false;
-static bool g_fuse = true;
-static bool g_slices = true;  // sliced LDS histogram for wide alphabets
-static bool g_pairs = false;  // two levels per pass for byte alphabets (measured slower: see wt_set_level_pairs)
-static int g_spin_limit = 8;
+// Settings of the wt_set_* calls.  Each host thread has its own copy, so a
+// caller that changes one for a comparison does not change the builds of
+// other threads.
+static thread_local bool g_timing = false;
+static thread_local bool g_fuse = true;
+static thread_local bool g_slices = true;  // sliced LDS histogram for wide alphabets
+static thread_local bool g_pairs = false;  // two levels per pass for byte alphabets (measured slower: see wt_set_level_pairs)
+static thread_local int g_spin_limit = 8;
 constexpr uint64_t kOffMaxNode = 8;   // in the status block: largest node per level (u64 x 30)
 constexpr uint64_t kOffFusedL0 = 248; // in the status block: first fused level (u32)
 
@@ -871,19 +874,28 @@ static void launch_fused(uint32_t in_w, uint32_t mid, const FusedArgs &f, uint64
 // Wide alphabets: the sliced histogram when the S ping-pong (idle until
 // level 0 scatters) holds one row of counts per chunk and the input is long
 // enough to fill a chunk per slice; the LDS-hash histogram otherwise.
-template <typename T>
-static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
-                               void *rows, hipStream_t s) {
+// Input chunks of the sliced histogram (one row of sigma counts each), or 0
+// when it does not apply.
+static uint64_t slice_chunks(const Plan &p, uint32_t in_bytes) {
     constexpr uint64_t kMinChunkTiles = 16;
-    if (p.sigma <= 8192 || p.L < 2) return false;
-    const uint32_t shift = tile_shift_for(sizeof(T));
-    const uint64_t ntiles = cdiv(p.n, 1ull << shift);
+    if (p.sigma <= 8192 || p.L < 2) return 0;
+    const uint64_t ntiles = cdiv(p.n, 1ull << tile_shift_for(in_bytes));
     const uint32_t nslices = (uint32_t)cdiv(p.sigma, kSliceBins);
     const uint64_t row_room = align_up(p.n * p.mid_bytes, 256) / (4 * p.sigma);
     uint64_t nchunks = std::max<uint64_t>(1, (uint64_t)num_cus() / nslices);
     nchunks = std::min(nchunks, row_room);
     nchunks = std::min(nchunks, cdiv(ntiles, kMinChunkTiles));
+    return nchunks;
+}
+
+template <typename T>
+static bool launch_hist_slices(const void *seq, const Plan &p, uint64_t *Cp1, uint32_t *status, uint32_t *cnt0,
+                               void *rows, hipStream_t s) {
+    uint64_t nchunks = slice_chunks(p, sizeof(T));
     if (nchunks == 0) return false;
+    const uint32_t shift = tile_shift_for(sizeof(T));
+    const uint64_t ntiles = cdiv(p.n, 1ull << shift);
+    const uint32_t nslices = (uint32_t)cdiv(p.sigma, kSliceBins);
     const uint64_t per_chunk = cdiv(ntiles, nchunks);
     nchunks = cdiv(ntiles, per_chunk);
     const uint64_t grid = cdiv(nchunks, 8) * 8 * nslices;
@@ -950,6 +962,47 @@ extern "C" uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L) {
     return align_up(8ull * std::max<uint32_t>(L, 1u), 256) + align_up(8ull * L * T, 256);
 }
 
+// Which kernels a build runs, a function of the plan, the kind of build and
+// this thread's settings.
+struct PathChoice {
+    bool fuse, pairs, two_phase;
+    uint32_t lmin, cbits, fine_blocks;
+    int hist;  // WT_HIST_*
+};
+
+static PathChoice choose_path(const Plan &p, bool matrix, bool dirs) {
+    PathChoice c{};
+    const uint64_t n = p.n;
+    // Fused tail levels need the directories (they write their entries) and
+    // at least one split to save.  The 2^l nodes of level l share n symbols,
+    // so its largest node holds at least ceil(n / 2^l): no level below
+    // `lmin` can fuse, and when lmin > L-2 none can, which leaves the level
+    // passes without the per-tile check of the fused level.
+    c.lmin = 0;
+    while (c.lmin < 63 && cdiv(n, 1ull << c.lmin) > fused_half(p.mid_bytes)) ++c.lmin;
+    c.fuse = g_fuse && !matrix && dirs && p.L >= 2 && n > 0 && c.lmin + 2 <= p.L;
+    // Two levels per pass: byte symbols in and between levels, nothing fused
+    // (inputs too small for that are the fused pass's), 32-bit positions.
+    c.pairs = g_pairs && !matrix && !c.fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
+              n < (1ull << 32);
+    // Wide alphabets (more than 16 levels): the two-phase histogram (see
+    // hist_coarse / hist_fine) when its rows, overflow counts and tags fit
+    // the idle ping-pong buffer at level c and no level before c can fuse.
+    c.cbits = p.L > kFineBits ? p.L - kFineBits : 0u;
+    c.fine_blocks = (uint32_t)std::min(num_cus(), 1024);
+    const uint64_t fine_rows = (uint64_t)c.fine_blocks << kFineBits;  // u32 counts
+    const uint64_t fine_bytes = 4 * fine_rows + 8 * align_up(p.sigma, 32) + 4 * 1024;
+    c.two_phase = g_slices && !matrix && !c.pairs && c.cbits >= 1 && c.cbits <= kCoarseMaxBits &&
+                  p.in_bytes == 4 && p.mid_bytes == 4 && n >= (1ull << 20) && n < (1ull << 32) &&
+                  fine_bytes <= align_up(n * p.mid_bytes, 256) && (!c.fuse || c.lmin >= c.cbits);
+    if (n == 0) c.hist = WT_HIST_NONE;
+    else if (c.two_phase) c.hist = WT_HIST_TWO_PHASE;
+    else if (!c.pairs && g_slices && slice_chunks(p, p.in_bytes)) c.hist = WT_HIST_SLICES;
+    else if (p.sigma <= 8192) c.hist = WT_HIST_REPLICAS;
+    else c.hist = WT_HIST_HASH;
+    return c;
+}
+
 static void launch_pair(bool scatter, bool next_pair, bool dirs, uint32_t tiles, hipStream_t s, const PairArgs &a) {
 #define WT_PAIR(SC, NP, DI) \
     if (scatter == SC && next_pair == NP && dirs == DI) return launch_k(pair_pass<SC, NP, DI>, dim3(tiles), dim3(kBlock), s, a);
@@ -967,7 +1020,7 @@ static void launch_pair(bool scatter, bool next_pair, bool dirs, uint32_t tiles,
 // S_l, writes B_l, B_{l+1}, their directory entries and S_{l+2}, and counts
 // ahead for the next pass.
 static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, unsigned char *sc, bool dirs,
-                     hipStream_t s) {
+                     hipStream_t s, bool timed) {
     const uint64_t n = p.n;
     uint32_t *status = (uint32_t *)(sc + p.off_status);
     uint32_t *cnt = (uint32_t *)(sc + p.off_cnt);
@@ -1010,9 +1063,9 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
             a.n = (uint32_t)n;
             a.k = p.L - 1 - l;
             a.level = l;
-            if (g_timing && (rc = timing_begin(s, ev))) return rc;
+            if (timed && (rc = timing_begin(s, ev))) return rc;
             launch_pair(scatter, next_pair, dirs, (uint32_t)Tl, s, a);
-            if (g_timing && (rc = timing_end(s, ev))) return rc;
+            if (timed && (rc = timing_end(s, ev))) return rc;
             if (scatter) {
                 cur = dst;
                 buf ^= 1;
@@ -1037,9 +1090,9 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
             a.level = l;
             a.fused_l0 = nullptr;
             a.qmask = ~0u;
-            if (g_timing && (rc = timing_begin(s, ev))) return rc;
+            if (timed && (rc = timing_begin(s, ev))) return rc;
             launch_level_any(1, 1, false, dirs, s, a);
-            if (g_timing && (rc = timing_end(s, ev))) return rc;
+            if (timed && (rc = timing_end(s, ev))) return rc;
         }
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     }
@@ -1050,7 +1103,8 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
 // every level one node, split with D_l = {0, zeros of the level}; no fused
 // or paired levels; the zero counts also go to d_zeros).
 static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
-                      bool matrix, uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream) {
+                      bool matrix, uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream,
+                      bool timed) {
     Plan p;
     int rc = make_plan(n, sigma, sym_bytes, p);
     if (rc) return rc;
@@ -1069,28 +1123,10 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
     uint64_t *part = (uint64_t *)(sc + p.off_part);
     uint64_t *Dm = (uint64_t *)(sc + p.off_M);
 
-    // Fused tail levels need the directories (they write their entries) and
-    // at least one split to save.  The 2^l nodes of level l share n symbols,
-    // so its largest node holds at least ceil(n / 2^l): no level below
-    // `lmin` can fuse, and when lmin > L-2 none can, which leaves the level
-    // passes without the per-tile check of the fused level.
-    uint32_t lmin = 0;
-    while (lmin < 63 && cdiv(n, 1ull << lmin) > fused_half(p.mid_bytes)) ++lmin;
-    const bool fuse = g_fuse && !matrix && dirs && p.L >= 2 && n > 0 && lmin + 2 <= p.L;
-    // Two levels per pass: byte symbols in and between levels, nothing fused
-    // (inputs too small for that are the fused pass's), 32-bit positions.
-    const bool pairs = g_pairs && !matrix && !fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
-                       n < (1ull << 32);
-    // Wide alphabets (more than 16 levels): the two-phase histogram (see
-    // hist_coarse / hist_fine) when its rows, overflow counts and tags fit
-    // the idle ping-pong buffer at level c and no level before c can fuse.
-    const uint32_t cbits = p.L > kFineBits ? p.L - kFineBits : 0u;
-    const uint32_t fine_blocks = (uint32_t)std::min(num_cus(), 1024);
+    const PathChoice pc = choose_path(p, matrix, dirs);
+    const uint32_t lmin = pc.lmin, cbits = pc.cbits, fine_blocks = pc.fine_blocks;
+    const bool fuse = pc.fuse, pairs = pc.pairs, two_phase = pc.two_phase;
     const uint64_t fine_rows = (uint64_t)fine_blocks << kFineBits;  // u32 counts
-    const uint64_t fine_bytes = 4 * fine_rows + 8 * align_up(sigma, 32) + 4 * 1024;
-    const bool two_phase = g_slices && !matrix && !pairs && cbits >= 1 && cbits <= kCoarseMaxBits &&
-                           sym_bytes == 4 && p.mid_bytes == 4 && n >= (1ull << 20) && n < (1ull << 32) &&
-                           fine_bytes <= align_up(n * p.mid_bytes, 256) && (!fuse || lmin >= cbits);
 
     // Zero: status + per-tile zero counts (one contiguous range), and C.
     {
@@ -1168,7 +1204,7 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
     if (p.L > 0) tables(two_phase ? (1ull << cbits) : (1ull << p.L), !two_phase);
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     if (n == 0 || p.L == 0) return WT_OK;
-    if (pairs) return run_pairs(d_seq, p, out, sc, dirs, s);
+    if (pairs) return run_pairs(d_seq, p, out, sc, dirs, s, timed);
 
     const void *cur = d_seq;
     uint32_t cur_w = p.in_bytes;
@@ -1216,9 +1252,9 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
         a.fused_l0 = (fuse && l >= lmin) ? fused_l0 : nullptr;
         a.qmask = matrix ? 1u : ~0u;
         std::pair<hipEvent_t, hipEvent_t> ev;
-        if (g_timing && (rc = timing_begin(s, ev))) return rc;
+        if (timed && (rc = timing_begin(s, ev))) return rc;
         launch_level_any(cur_w, scatter ? p.mid_bytes : cur_w, scatter, dirs, s, a);
-        if (g_timing && (rc = timing_end(s, ev))) return rc;
+        if (timed && (rc = timing_end(s, ev))) return rc;
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
         cur = dst;
         cur_w = p.mid_bytes;
@@ -1250,13 +1286,13 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
 
 extern "C" int wt_build(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
                         void *d_scratch, uint64_t scratch_bytes, void *stream) {
-    return build_impl(d_seq, n, sigma, sym_bytes, out, false, nullptr, d_scratch, scratch_bytes, stream);
+    return build_impl(d_seq, n, sigma, sym_bytes, out, false, nullptr, d_scratch, scratch_bytes, stream, g_timing);
 }
 
 extern "C" int wt_build_matrix(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
                                uint64_t *d_zeros, void *d_scratch, uint64_t scratch_bytes, void *stream) {
     if (!d_zeros && levels_of(sigma) > 0) return WT_ERR_ARG;
-    return build_impl(d_seq, n, sigma, sym_bytes, out, true, d_zeros, d_scratch, scratch_bytes, stream);
+    return build_impl(d_seq, n, sigma, sym_bytes, out, true, d_zeros, d_scratch, scratch_bytes, stream, g_timing);
 }
 
 extern "C" int wt_build_multiary(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes,
@@ -1571,6 +1607,13 @@ extern "C" int wt_build_sort(const void *d_seq, uint64_t n, uint64_t sigma, int 
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     return wt_build_rank_select(out->bits, n, p.L, out->rank, out->sel1, out->sel0, out->sel_counts,
                                 sc + sp.off_rs, sp.total - sp.off_rs, stream);
+}
+
+extern "C" int wt_histogram_path(uint64_t n, uint64_t sigma, int sym_bytes) {
+    Plan p;
+    const int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    return choose_path(p, false, true).hist;
 }
 
 extern "C" int wt_status_get(const void *d_scratch, void *stream) {

@@ -29,8 +29,9 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
            "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
            "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank",
-           "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort"]
+           "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort", "wt_histogram_path"]
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
+HIST_NONE, HIST_REPLICAS, HIST_HASH, HIST_SLICES, HIST_TWO_PHASE = 0, 1, 2, 3, 4
 
 
 class WTError(RuntimeError):
@@ -136,6 +137,7 @@ def lib() -> ctypes.CDLL:
         L.wt_batch_run.argtypes = [ctypes.POINTER(BatchLayout), ctypes.POINTER(Tune), vp, vp]
         L.wt_batch_status.argtypes = [ctypes.POINTER(BatchLayout), vp, ctypes.POINTER(ctypes.c_int32), vp]
         L.wt_query_multi.argtypes = [vp, u32, vp, vp, vp, vp, u64, vp, vp]
+        L.wt_histogram_path.argtypes = [u64, u64, i32]
         L.wt_set_fused_levels.argtypes = [i32]
         L.wt_set_sliced_histogram.argtypes = [i32]
         L.wt_set_level_pairs.argtypes = [i32]
@@ -163,7 +165,7 @@ def lib() -> ctypes.CDLL:
                   "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
                   "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select", "wt_huffman_plan",
                   "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank", "wt_huffman_select",
-                  "wt_build_sort"):
+                  "wt_build_sort", "wt_histogram_path"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -561,6 +563,14 @@ def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
 
 def set_fused_levels(on: bool):
     _check(lib().wt_set_fused_levels(1 if on else 0), "wt_set_fused_levels")
+
+
+def histogram_path(n: int, sigma: int, sym_bytes: int) -> int:
+    """Which histogram wt_build runs for these sizes (HIST_*), under this thread's settings."""
+    rc = lib().wt_histogram_path(n, sigma, sym_bytes)
+    if rc < 0:
+        raise WTError(rc, "wt_histogram_path")
+    return rc
 
 
 def set_sliced_histogram(on: bool):

@@ -1,15 +1,16 @@
 """Full-size checks: the text-like workload at n = 2^28 (the benchmark's
 input and launch configuration) built as the binary tree, the wavelet
-matrix, the 4-ary tree and the Huffman-shaped tree.  At this size the
-oracle's whole build is too slow for a test, so each build is checked
-against what holds at any size and against answers computed one by one:
-- C against a numpy histogram of S;
-- every level's popcount against the histogram (the count of symbols whose
-  bit, resp. code bit, is set at that level), and the last rank entry;
-- the Huffman code lengths and codes against the oracle's code
-  construction on the same counts, and its level sizes against the weights;
-- sampled access, rank and select answers against S itself;
-- the sortWT construction (sorted copies of S, no level passes) against the
+matrix, the 4-ary tree and the Huffman-shaped tree.
+- The binary tree: every output buffer (bits, C, rank, sel1, sel0,
+  sel_counts) equals the oracle's, bit for bit.
+- The other shapes are checked against what holds at any size and against
+  answers computed one by one: C against a numpy histogram of S; every
+  level's popcount against the histogram (the count of symbols whose bit,
+  resp. code bit, is set at that level), and the last rank entry; the
+  Huffman code lengths and codes against the oracle's code construction on
+  the same counts, and its level sizes against the weights; sampled access,
+  rank and select answers against S itself.
+- The sortWT construction (sorted copies of S, no level passes) against the
   level-pass build, every output buffer bit for bit.
 Integer work: tolerance zero."""
 import sys
@@ -80,7 +81,7 @@ def C_of(hist):
     return np.concatenate([[0], np.cumsum(hist)]).astype(np.uint64)
 
 
-def test_fullsize_tree(wtmod, text):
+def test_fullsize_tree(wtmod, oracle_mod, text):
     S, sigma, hist, d = text
     L = 8
     say("[fullsize] binary tree")
@@ -94,8 +95,17 @@ def test_fullsize_tree(wtmod, text):
         assert int(pc[l]) == ones, l
         assert int(t.rank[l, -1].item()) == ones
     sampled_queries(S, t.access, t.rank_query, t.select_query, 1)
+    got = t.to_numpy()
     del t
     torch.cuda.empty_cache()
+    say("[fullsize] binary tree against the oracle")
+    want = oracle_mod.build_all(S, sigma)
+    for k in ("bits", "C", "rank", "sel1", "sel0", "sel_counts"):
+        g = np.asarray(got[k], dtype=np.uint64).reshape(-1)
+        w = np.asarray(want[k], dtype=np.uint64).reshape(-1)
+        assert g.shape == w.shape, k
+        bad = np.flatnonzero(g != w)
+        assert bad.size == 0, f"{k} differs at {bad.size} entries, first {bad[:5]}"
 
 
 def test_fullsize_matrix(wtmod, text):

@@ -273,3 +273,19 @@ def test_sort_scratch_and_argument_errors_are_synchronous():
     out.bits = out.rank = out.sel1 = out.sel0 = out.sel_counts = ctypes.c_void_p(8192)
     assert lib.wt_build_sort(ctypes.c_void_p(16), 100000, 200, 1, ctypes.byref(out), ctypes.c_void_p(256), 64,
                              None) == wt.WT_ERR_SCRATCH
+
+
+@pytest.mark.parametrize("n,sigma,b,path", [
+    (0, 256, 1, wt.HIST_NONE),
+    (1 << 28, 256, 1, wt.HIST_REPLICAS),
+    (1 << 20, 8192, 2, wt.HIST_REPLICAS),
+    (1 << 27, 1 << 16, 4, wt.HIST_SLICES),
+    (1 << 27, 1 << 20, 4, wt.HIST_TWO_PHASE),
+    ((1 << 25) + 9, (1 << 18) + 1, 4, wt.HIST_TWO_PHASE),
+    (1 << 26, 528155, 4, wt.HIST_TWO_PHASE),
+    (1000, 1 << 20, 4, wt.HIST_HASH),
+])
+def test_histogram_path(n, sigma, b, path):
+    # the host-side choice of histogram (a 256-CU device is assumed without a GPU)
+    assert wt.histogram_path(n, sigma, b) == path
+
