@@ -137,6 +137,27 @@ int wt_histogram_path(uint64_t n, uint64_t sigma, int sym_bytes);
  * last wt_build that used d_scratch (WT_ERR_SYMBOL). */
 int wt_status_get(const void *d_scratch, void *stream);
 
+/* wt_build without any allocation, for callers that cannot call hipMalloc
+ * or an allocating library routine (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The build's scratch is
+ * a file-scope device array of WT_NOALLOC_SCRATCH_BYTES that every GPU the
+ * library runs on holds until the process ends; the caller still passes the
+ * input and the outputs.
+ *   Arguments, layout and outputs: as wt_build (no d_scratch).
+ *   d_status: device int32 (may be NULL): receives WT_OK or WT_ERR_SYMBOL
+ *             once the build has run on `stream` (the data error that
+ *             wt_status_get reports for wt_build).
+ *   Plans whose wt_plan().scratch_bytes exceed WT_NOALLOC_SCRATCH_BYTES are
+ *   refused with WT_ERR_SCRATCH before anything is launched.
+ * The array belongs to the calling thread's current device (the device of
+ * `stream`).  Every call on one GPU shares that GPU's array, which keeps the
+ * previous call's contents (the build clears what must start at zero): calls
+ * that overlap on one GPU, on any streams or threads, race and give
+ * unspecified outputs.  Asynchronous on `stream`. */
+#define WT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int wt_build_noalloc(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                     int32_t *d_status, void *stream);
+
 /* A built tree: device pointers to the outputs of wt_build (with
  * directories) plus its sizes. */
 typedef struct {

@@ -1673,3 +1673,57 @@ extern "C" int wt_timing_collect(float *ms, int cap) {
     g_free.insert(g_free.end(), evs.begin(), evs.end());
     return rc;
 }
+
+// ---------------------------------------------------------------------------
+// wt_build without allocation: the build's scratch is a file-scope device
+// array, one copy per GPU for the life of the process.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol): each device's address is looked up once with
+// hipGetSymbolAddress, with that device current, and that address is what
+// the kernels receive.
+static __device__ __align__(256) unsigned char scratch[WT_NOALLOC_SCRATCH_BYTES];
+
+namespace wt {
+
+__global__ void status_to_code(const uint32_t *word, int32_t *code) {
+    if (threadIdx.x == 0) *code = *word == 0 ? WT_OK : (*word == kStatusSymbol ? WT_ERR_SYMBOL : WT_ERR_HIP);
+}
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kMaxDevices];  // device address of `scratch`, per device, once looked up
+
+static int noalloc_scratch(void **ptr) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return WT_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return WT_ERR_RANGE;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p || ((uintptr_t)p & 255u))
+            return WT_ERR_HIP;
+        g_noalloc_ptr[dev] = p;
+    }
+    *ptr = g_noalloc_ptr[dev];
+    return WT_OK;
+}
+
+}  // namespace wt
+
+extern "C" int wt_build_noalloc(const void *d_seq, uint64_t n, uint64_t sigma, int sym_bytes, const wt_outputs *out,
+                                int32_t *d_status, void *stream) {
+    Plan p;
+    int rc = make_plan(n, sigma, sym_bytes, p);
+    if (rc) return rc;
+    if (p.total > WT_NOALLOC_SCRATCH_BYTES) return WT_ERR_SCRATCH;
+    void *sc = nullptr;
+    if ((rc = noalloc_scratch(&sc))) return rc;
+    // Untimed whatever this thread's timing switch says: timing creates events.
+    rc = build_impl(d_seq, n, sigma, sym_bytes, out, false, nullptr, sc, WT_NOALLOC_SCRATCH_BYTES, stream, false);
+    if (rc) return rc;
+    if (d_status) {
+        status_to_code<<<1, kWave, 0, (hipStream_t)stream>>>((const uint32_t *)sc, d_status);
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+    }
+    return WT_OK;
+}

@@ -29,7 +29,8 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_set_sliced_histogram", "wt_set_level_pairs", "wt_build_matrix", "wt_matrix_access",
            "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary", "wt_multiary_access", "wt_multiary_rank",
            "wt_multiary_select", "wt_huffman_plan", "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank",
-           "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort", "wt_histogram_path"]
+           "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort", "wt_histogram_path", "wt_build_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20  # WT_NOALLOC_SCRATCH_BYTES
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
 HIST_NONE, HIST_REPLICAS, HIST_HASH, HIST_SLICES, HIST_TWO_PHASE = 0, 1, 2, 3, 4
 
@@ -122,6 +123,7 @@ def lib() -> ctypes.CDLL:
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         L.wt_plan.argtypes = [u64, u64, i32, ctypes.POINTER(Layout)]
         L.wt_build.argtypes = [vp, u64, u64, i32, ctypes.POINTER(Outputs), vp, u64, vp]
+        L.wt_build_noalloc.argtypes = [vp, u64, u64, i32, ctypes.POINTER(Outputs), vp, vp]
         L.wt_build_rank_select.argtypes = [vp, u64, u32, vp, vp, vp, vp, vp, u64, vp]
         L.wt_rank_select_scratch_bytes.argtypes = [u64, u32]
         L.wt_rank_select_scratch_bytes.restype = u64
@@ -165,7 +167,7 @@ def lib() -> ctypes.CDLL:
                   "wt_matrix_access", "wt_matrix_rank", "wt_matrix_select", "wt_build_multiary",
                   "wt_multiary_access", "wt_multiary_rank", "wt_multiary_select", "wt_huffman_plan",
                   "wt_build_huffman", "wt_huffman_access", "wt_huffman_rank", "wt_huffman_select",
-                  "wt_build_sort", "wt_histogram_path"):
+                  "wt_build_sort", "wt_histogram_path", "wt_build_noalloc"):
             getattr(L, f).restype = i32
         _lib = L
     return _lib
@@ -250,6 +252,23 @@ class WaveletTree:
         rc = lib().wt_build(_ptr(seq), self.n, self.sigma, self.sym_bytes, ctypes.byref(out),
                             _ptr(self.scratch), self.scratch.numel(), _stream(stream))
         _check(rc, "wt_build")
+        return self
+
+    def build_noalloc_from(self, seq: torch.Tensor, status: torch.Tensor | None = None,
+                           stream=None) -> "WaveletTree":
+        """Launch wt_build_noalloc on ``seq`` into this tree's outputs (the
+        library's static scratch; this tree's scratch is not used).  ``status``
+        (a one-element int32 device tensor) receives WT_OK or WT_ERR_SYMBOL."""
+        if not seq.is_cuda:
+            raise ValueError("seq must be a device tensor")
+        if seq.element_size() != self.sym_bytes or seq.numel() != self.n or not seq.is_contiguous():
+            raise ValueError("seq does not match the allocated layout")
+        if status is not None and (status.dtype != torch.int32 or status.numel() < 1 or not status.is_cuda):
+            raise ValueError("status must be a device int32 tensor")
+        out = self.outputs()
+        rc = lib().wt_build_noalloc(_ptr(seq), self.n, self.sigma, self.sym_bytes, ctypes.byref(out),
+                                    _ptr(status), _stream(stream))
+        _check(rc, "wt_build_noalloc")
         return self
 
     def status(self, stream=None) -> int:
@@ -722,3 +741,4 @@ def build_sort(seq: torch.Tensor, sigma: int, stream=None, tree: WaveletTree | N
     _check(lib().wt_build_sort(_ptr(seq), n, sigma, 1, ctypes.byref(out), _ptr(t.scratch), t.scratch.numel(),
                                _stream(stream)), "wt_build_sort")
     return t
+

@@ -111,6 +111,20 @@ def test_build_argument_errors_are_synchronous():
     assert lib.wt_select(ctypes.byref(v), None, None, 0, None, None) == wt.WT_OK
 
 
+def test_noalloc_refuses_plans_beyond_its_array():
+    """wt_build_noalloc refuses a plan larger than its static array (and bad
+    arguments) synchronously, before touching the device."""
+    lib = wt.lib()
+    out = wt.Outputs()
+    out.C = ctypes.c_void_p(4096)
+    out.bits = ctypes.c_void_p(8192)
+    n = 80 << 20
+    assert wt.plan(n, 256, 1).scratch_bytes > wt.NOALLOC_SCRATCH_BYTES
+    assert lib.wt_build_noalloc(ctypes.c_void_p(16), n, 256, 1, ctypes.byref(out), None, None) == wt.WT_ERR_SCRATCH
+    assert lib.wt_build_noalloc(ctypes.c_void_p(16), 10, 300, 1, ctypes.byref(out), None, None) == wt.WT_ERR_ARG
+    assert lib.wt_build_noalloc(ctypes.c_void_p(16), 10, 0, 1, ctypes.byref(out), None, None) == wt.WT_ERR_ARG
+
+
 def _job(n, sigma, b):
     return wt.Job(None, n, sigma, b, 0, wt.Outputs())
 
