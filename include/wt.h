@@ -125,12 +125,16 @@ uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L);
  *   WT_HIST_SLICES     sigma > 8192: 2^16-symbol slices of 16-bit LDS counters, a row per chunk
  *   WT_HIST_TWO_PHASE  more than 16 levels over 32-bit symbols: groups of the top L-16 bits
  *                      before level 0, the low 16 bits per segment of S_(L-16) later
+ *   WT_HIST_LEVELS     byte symbols, no fused levels: no histogram pass; level 0's tile
+ *                      counts from one read-only pass, every later level's node sizes
+ *                      counted by the level above it while it scatters, C at the last level
  * Returns one of these or WT_ERR_ARG / WT_ERR_RANGE as wt_plan. */
 #define WT_HIST_NONE 0
 #define WT_HIST_REPLICAS 1
 #define WT_HIST_HASH 2
 #define WT_HIST_SLICES 3
 #define WT_HIST_TWO_PHASE 4
+#define WT_HIST_LEVELS 5
 int wt_histogram_path(uint64_t n, uint64_t sigma, int sym_bytes);
 
 /* Wait for `stream`, then return WT_OK or the data error recorded by the

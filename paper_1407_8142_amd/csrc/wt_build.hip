@@ -32,6 +32,7 @@
 #include "wt_hist2.hpp"
 #include "wt_huff.hpp"
 #include "wt_sort.hpp"
+#include "wt_stats.hpp"
 #include "wt_u16.hpp"
 #include "wt_u32.hpp"
 
@@ -432,10 +433,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     level_tile<TIN, TOUT, SCATTER, DIRS>(a, blockIdx.x, s);
 }
 
-template <bool SCATTER, bool DIRS>
+template <bool SCATTER, bool DIRS, bool PIECES = false, bool LASTBITS = false>
 __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
     __shared__ LdsLevelU8 s;
-    level_tile_u8<SCATTER, DIRS>(a, blockIdx.x, s);
+    level_tile_u8<SCATTER, DIRS, PIECES, LASTBITS>(a, blockIdx.x, s);
+}
+
+constexpr int kDirsWaves = 4;  // tiles (one per wave) per block of level_dirs
+
+__global__ __launch_bounds__(kDirsWaves * kWave) void level_dirs(LevelArgs a) {
+    const uint64_t ntiles = cdiv(a.n, 16384);
+    const uint64_t tile = (uint64_t)blockIdx.x * kDirsWaves + threadIdx.x / kWave;
+    if (tile < ntiles) level_dirs_tile(a, tile, ntiles);
 }
 
 template <bool SCATTER, bool DIRS>
@@ -657,6 +666,8 @@ struct Plan {
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
     uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_M, off_S0, off_S1, total;
+    uint64_t off_PZ, off_NZ, off_CL;  // byte alphabets: piece counts, node zeros, node starts (wt_stats.hpp)
+    uint64_t PS;                      // piece counts per level
     uint64_t n_part;
 };
 
@@ -705,6 +716,16 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     o += p.L >= 2 && p.L <= 8 ? kPairTableBytes : 0;
     p.off_M = o;  // wavelet matrix: {0, zeros of level l} per level
     o = align_up(o + 16ull * p.L, 256);
+    // Byte alphabets: the statistics that replace the histogram (every
+    // level's piece counts, node zeros and node starts).
+    const bool byte_stats = p.in_bytes == 1 && p.L >= 1 && p.L <= 8;
+    p.PS = byte_stats ? piece_stride(cdiv(n, 16384), p.L) : 0;
+    p.off_PZ = o;
+    o = align_up(o + 4 * p.PS * p.L, 256);
+    p.off_NZ = o;
+    o = align_up(o + (byte_stats ? 8ull << p.L : 0), 256);
+    p.off_CL = o;
+    o = align_up(o + (byte_stats ? 8 * ((1ull << p.L) + p.L) : 0), 256);
     p.off_S0 = o;
     const uint64_t sbytes = p.L >= 2 ? align_up(n * p.mid_bytes, 256) : 0;
     o += sbytes;
@@ -965,7 +986,7 @@ extern "C" uint64_t wt_rank_select_scratch_bytes(uint64_t n, uint32_t L) {
 // Which kernels a build runs, a function of the plan, the kind of build and
 // this thread's settings.
 struct PathChoice {
-    bool fuse, pairs, two_phase;
+    bool fuse, pairs, two_phase, stats;
     uint32_t lmin, cbits, fine_blocks;
     int hist;  // WT_HIST_*
 };
@@ -995,7 +1016,12 @@ static PathChoice choose_path(const Plan &p, bool matrix, bool dirs) {
     c.two_phase = g_slices && !matrix && !c.pairs && c.cbits >= 1 && c.cbits <= kCoarseMaxBits &&
                   p.in_bytes == 4 && p.mid_bytes == 4 && n >= (1ull << 20) && n < (1ull << 32) &&
                   fine_bytes <= align_up(n * p.mid_bytes, 256) && (!c.fuse || c.lmin >= c.cbits);
+    // Byte alphabets with no fused or paired levels: no histogram pass (the
+    // level passes count what the next level's tables need, wt_stats.hpp).
+    c.stats = !matrix && !c.fuse && !c.pairs && p.in_bytes == 1 && p.L >= 1 && p.L <= 8 && n > 0 &&
+              n < (1ull << 32);
     if (n == 0) c.hist = WT_HIST_NONE;
+    else if (c.stats) c.hist = WT_HIST_LEVELS;
     else if (c.two_phase) c.hist = WT_HIST_TWO_PHASE;
     else if (!c.pairs && g_slices && slice_chunks(p, p.in_bytes)) c.hist = WT_HIST_SLICES;
     else if (p.sigma <= 8192) c.hist = WT_HIST_REPLICAS;
@@ -1099,6 +1125,102 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
     return WT_OK;
 }
 
+// Byte alphabets without a histogram pass (wt_stats.hpp): one read-only
+// pass gives level 0's tile counts and the symbol check; then per level the
+// statistics kernel (tile prefixes and the node table from the piece counts
+// the level above left, the status word at level 0, C at the last level)
+// and the byte level pass, which counts its next level's zeros per piece.
+// Level L-2's pass writes the last level's bits itself (LASTBITS), so the
+// last level reads only its bits, for its directories.
+static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, unsigned char *sc, bool dirs,
+                     hipStream_t s, bool timed) {
+    const uint64_t n = p.n;
+    uint32_t *status = (uint32_t *)(sc + p.off_status);
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
+    uint64_t *D = (uint64_t *)(sc + p.off_D);
+    uint32_t *pz = (uint32_t *)(sc + p.off_PZ);
+    uint64_t *NZ = (uint64_t *)(sc + p.off_NZ), *CL = (uint64_t *)(sc + p.off_CL);
+    const uint32_t Tl = (uint32_t)cdiv(n, 16384);
+    // Level 0's pieces are its tiles; everything after them is cleared.
+    const uint64_t nclear = p.PS * p.L - Tl;
+    if (p.sigma < 256)
+        stats_prep_u8<true><<<Tl, kBlock, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1, (uint32_t)p.sigma,
+                                                  pz, pz + Tl, nclear);
+    else
+        stats_prep_u8<false><<<Tl, kBlock, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1,
+                                                   (uint32_t)p.sigma, pz, pz + Tl, nclear);
+    const void *cur = d_seq;
+    int rc;
+    for (uint32_t l = 0; l < p.L; ++l) {
+        const bool scatter = l + 1 < p.L;
+        StatsArgs sa;
+        sa.pieces = pz + (uint64_t)l * p.PS;
+        sa.pre = pre + (uint64_t)l * p.T;
+        sa.T = Tl;
+        sa.tile_shift = tile_shift_for(1);
+        sa.level = l;
+        sa.L = p.L;
+        sa.n = n;
+        sa.sigma = p.sigma;
+        sa.status = status;
+        sa.NZ = NZ;
+        sa.CL = CL;
+        sa.D = D + ((2ull << l) - 2);
+        sa.C = out->C;
+        stats_scan<<<1, kStatsThreads, 0, s>>>(sa);
+        void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+        LevelArgs a;
+        a.in = cur;
+        a.out = scatter ? dst : nullptr;
+        a.bits = out->bits + (uint64_t)l * p.W;
+        a.D = sa.D;
+        a.nD = 2ull << l;
+        a.tile_prefix = sa.pre;
+        a.next_cnt = scatter ? pz + (uint64_t)(l + 1) * p.PS : nullptr;
+        a.next_shift = tile_shift_for(1);
+        a.status = status;
+        a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
+        a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
+        a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
+        a.n = n;
+        a.k = p.L - 1 - l;
+        a.level = l;
+        a.fused_l0 = nullptr;
+        a.qmask = ~0u;
+        a.tails = dirs ? 1u : 0u;
+        a.L = p.L;
+        a.sel_counts = out->sel_counts;
+        a.rank_len = p.rank_len;
+        a.cap = p.cap;
+        const bool lastbits = l + 2 == p.L;  // this pass writes B_{L-1} too
+        const bool dirs_only = l + 1 == p.L && p.L >= 2;
+        if (lastbits) {
+            a.out = nullptr;
+            a.next_bits = out->bits + (uint64_t)(l + 1) * p.W;
+        }
+        if (dirs_only && !dirs) break;  // the last level's bits are in place
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (timed && (rc = timing_begin(s, ev))) return rc;
+        const dim3 g(Tl), b(kBlock);
+        if (dirs_only) {
+            launch_k(level_dirs, dim3((unsigned)cdiv(Tl, kDirsWaves)), dim3(kDirsWaves * kWave), s, a);
+        } else if (lastbits) {
+            if (dirs) launch_k(level_pass_u8<true, true, true, true>, g, b, s, a);
+            else launch_k(level_pass_u8<true, false, true, true>, g, b, s, a);
+        } else if (scatter) {
+            if (dirs) launch_k(level_pass_u8<true, true, true>, g, b, s, a);
+            else launch_k(level_pass_u8<true, false, true>, g, b, s, a);
+        } else {
+            if (dirs) launch_k(level_pass_u8<false, true>, g, b, s, a);
+            else launch_k(level_pass_u8<false, false>, g, b, s, a);
+        }
+        if (timed && (rc = timing_end(s, ev))) return rc;
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        cur = dst;
+    }
+    return WT_OK;
+}
+
 // The wavelet tree (matrix = false) or the wavelet matrix (matrix = true:
 // every level one node, split with D_l = {0, zeros of the level}; no fused
 // or paired levels; the zero counts also go to d_zeros).
@@ -1124,6 +1246,7 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
     uint64_t *Dm = (uint64_t *)(sc + p.off_M);
 
     const PathChoice pc = choose_path(p, matrix, dirs);
+    if (pc.stats) return run_stats(d_seq, p, out, sc, dirs, s, timed);
     const uint32_t lmin = pc.lmin, cbits = pc.cbits, fine_blocks = pc.fine_blocks;
     const bool fuse = pc.fuse, pairs = pc.pairs, two_phase = pc.two_phase;
     const uint64_t fine_rows = (uint64_t)fine_blocks << kFineBits;  // u32 counts

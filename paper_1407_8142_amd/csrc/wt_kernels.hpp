@@ -133,6 +133,9 @@ __device__ __forceinline__ std::conditional_t<DIG, uint64_t, uint32_t> hist_coun
             add_run(s, 1u);
         } else if ((uint64_t)s >= sigma) {
             bad = true;
+        } else if (s == H::kEmpty) {
+            // 2^32 - 1 (sigma = 2^32) is the table's empty key: counted directly.
+            atomicAdd(counts + s, (CNT)1);
         } else {
             uint32_t h = (s * 0x9E3779B1u) >> (32 - __builtin_ctz(kH));
             bool done = false;
@@ -368,6 +371,7 @@ struct LevelArgs {
     const void *in;          // S_l (TIN), 16-byte aligned
     void *out;               // S_{l+1} (TOUT)
     uint64_t *bits;          // B_l
+    uint64_t *next_bits = nullptr;  // B_{l+1}, written by the pass of level L-2 (LASTBITS)
     const uint64_t *D;       // D_l: 2^(l+1) entries
     uint64_t nD;             // 2^(l+1)
     const uint64_t *tile_prefix;  // zeros of B_l before each tile of this level
@@ -381,6 +385,12 @@ struct LevelArgs {
     const uint32_t *fused_l0;  // levels >= *fused_l0 are done by the fused pass (NULL: none)
     uint32_t qmask;          // node index = (symbol >> k) & qmask: ~0 for the tree (node and bit),
                              // 1 for the wavelet matrix (one node per level, D = {0, zeros})
+    // tails != 0: the blocks also write level l's directory tail (last rank
+    // entry, sample counts, sample entries past the counts), from the level's
+    // zeros = D[nD - 1]; sel_counts is the whole [2L] array.
+    uint32_t tails = 0, L = 0;
+    uint64_t *sel_counts = nullptr;
+    uint64_t rank_len = 0, cap = 0;
 };
 
 // Count-ahead: while level l scatters S_{l+1}, it also counts, for every tile
@@ -733,7 +743,34 @@ struct LdsLevelU8 {
     CountTableN<5> ct;  // with the 16-bit zpre: 8 blocks per CU fit in LDS
 };
 
-template <bool SCATTER, bool DIRS>
+// Bits [lo, hi) of a word, 0 <= lo <= hi <= 64.
+__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi) {
+    const uint64_t h = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return h & ~((1ull << lo) - 1ull);
+}
+
+// Bits of slots [s0, s0 + 64) of a split tile's bit array (256 words, slot
+// i = bit i % 64 of word i / 64); slots outside the tile read as 0.
+__device__ __forceinline__ uint64_t slot_bits64(const uint64_t *SB, int32_t s0) {
+    const int32_t wi = s0 >> 6, sh = s0 & 63;
+    const uint64_t lo = wi >= 0 && wi < 256 ? SB[wi] : 0ull;
+    const uint64_t hi = wi + 1 >= 0 && wi + 1 < 256 ? SB[wi + 1] : 0ull;
+    return sh ? (lo >> sh) | (hi << (64 - sh)) : lo;
+}
+
+// PIECES: the count-ahead counts per piece of the next level, the part of
+// a next-level tile inside one next-level node, at index tile + node (see
+// wt_stats.hpp), instead of per tile.
+// LASTBITS (level L-2): the next level is the last, which splits nothing,
+// so this pass writes B_{L-1} itself instead of S_{L-1}.  In the split tile
+// each run of one node and bit (a "group") lands on consecutive positions of
+// level L-1, and its symbols' bit 0 are the bits there: the words of the
+// group's destination range are funnel shifts of the tile's slot-order bit
+// array, stored whole inside the range and merged into the two words it
+// shares with other groups by atomics on disjoint masks (the analog of the
+// paper's CAS on words shared by nodes).  Level L-1 is then left with its
+// directories (level_dirs_tile).
+template <bool SCATTER, bool DIRS, bool PIECES = false, bool LASTBITS = false>
 __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile, LdsLevelU8 &s) {
     constexpr int kTile = LdsLevelU8::kTile, kRows = LdsLevelU8::kRows, kRowBytes = LdsLevelU8::kRowBytes;
 
@@ -777,6 +814,9 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     // global write: the input was rejected, or the fused pass owns this level.
     if (*a.status) return;
     if (a.fused_l0 && a.level >= *a.fused_l0) return;
+    if (DIRS && a.tails)
+        dir_tail(0, a.D[a.nD - 1], a.n, a.L, a.rank, a.rank_len, a.sel1, a.sel0, a.cap, a.sel_counts + a.level,
+                 (uint64_t)tile * kBlock + tid, (uint64_t)gridDim.x * kBlock);
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
@@ -835,6 +875,8 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     }
     if (!SCATTER) return;
 
+    if (LASTBITS && tid == 0) s.wz[0][0] = 0;  // group count (wz is read only before the last barrier)
+
     // Stable split into LDS (zeros at [0, Zt), ones at [Zt, len)).  The
     // zeros' and ones' cursors of a lane share one word (low and high 16
     // bits); 16 times a byte's level bit selects the half, as the offset of
@@ -880,6 +922,96 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     // the table together (count_add_wave).
     const uint4 *s_st128 = reinterpret_cast<const uint4 *>(s.stage);
     constexpr int kChunksPerWave = kTile / 16 / kWaves;
+    if constexpr (LASTBITS) {
+        // Slot-order bits of the next level (over m16, dead since the
+        // directories), group starts (over zpre: at most 2^(l+1) <= 128
+        // groups for byte symbols), and the count-ahead.
+        uint16_t *SB16 = s.m16, *gstart = s.zpre;
+        uint32_t &ng = s.wz[0][0];
+        LaneCount lc;
+        auto qof = [&](uint32_t b) { return (b >> k) & a.qmask; };
+        auto record = [&](uint32_t slot) {
+            const uint32_t g = atomicAdd(&ng, 1u);
+            if (g < kTile / 64) gstart[g] = (uint16_t)slot;
+        };
+#pragma unroll
+        for (int i = 0; i < kChunksPerWave / kWave; ++i) {
+            const uint32_t j = (uint32_t)(wave * kChunksPerWave + i * kWave + lane), sl = 16u * j;
+            uint32_t ftile = kNoTile, fcnt = 0;
+            if (sl < len) {
+                const uint4 v = s_st128[j];
+                SB16[j] = (uint16_t)mask16_bit(v, kn);
+                const uint32_t q0 = qof(v.x & 0xFFu), q15 = qof(v.w >> 24);
+                const uint32_t qp = sl ? qof(s.stage[sl - 1]) : ~0u;
+                if (sl + 15 < len && q0 == q15) {
+                    if (q0 != qp) record(sl);
+                    const uint32_t dest = s.D[q0] + ((q0 & 1u) ? O0 + sl - Zt : Z0 + sl);
+                    if (dest < n16) {
+                        const uint32_t nt = dest >> a.next_shift;
+                        if (((dest + 15) >> a.next_shift) == nt) {
+                            const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) +
+                                                             __popc(v.z & Mn) + __popc(v.w & Mn));
+                            lc.step(PIECES ? nt + q0 : nt, 16u - ones, ftile, fcnt);
+                        } else {
+                            for (uint32_t c = 0; c < 16; ++c)
+                                if (!((byte_of(v, (int)c) >> kn) & 1u))
+                                    count_add(s.ct, a.next_cnt, ((dest + c) >> a.next_shift) + (PIECES ? q0 : 0u),
+                                              1u);
+                        }
+                    }
+                } else {
+                    const uint32_t nc = clamp_count(len, sl, 16u);
+                    uint32_t qprev = qp;
+                    for (uint32_t c = 0; c < nc; ++c) {
+                        const uint32_t bc = byte_of(v, (int)c), qc = qof(bc), sc = sl + c;
+                        if (qc != qprev) record(sc);
+                        qprev = qc;
+                        const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
+                        if (dest < a.n && !((bc >> kn) & 1u))
+                            count_add(s.ct, a.next_cnt, (dest >> a.next_shift) + (PIECES ? qc : 0u), 1u);
+                    }
+                }
+            }
+            count_add_wave(s.ct, a.next_cnt, fcnt != 0, ftile, fcnt, lane);
+        }
+        lc.flush_wave(s.ct, a.next_cnt, lane);
+        __syncthreads();
+        count_flush(s.ct, a.next_cnt, tid);
+        // Group starts in slot order (ranked in place; few groups).
+        const uint32_t G = min(ng, (uint32_t)(kTile / 64));
+        const uint32_t mine = (uint32_t)tid < G ? gstart[tid] : 0u;
+        uint32_t rank = 0;
+        if ((uint32_t)tid < G)
+            for (uint32_t u = 0; u < G; ++u) rank += gstart[u] < mine ? 1u : 0u;
+        __syncthreads();
+        if ((uint32_t)tid < G) gstart[rank] = (uint16_t)mine;
+        __syncthreads();
+        // Each wave takes groups g = wave, wave + 4, ...; its lanes the
+        // destination words of the group.
+        const uint64_t *SB = reinterpret_cast<const uint64_t *>(s.m16);
+        uint64_t *B = a.next_bits;
+        for (uint32_t g = (uint32_t)wave; g < G; g += kWaves) {
+            const uint32_t sa = gstart[g], se = g + 1 < G ? gstart[g + 1] : len;
+            const uint32_t q = qof(s.stage[sa]);
+            const uint32_t off = s.D[q] + ((q & 1u) ? O0 - Zt : Z0);  // destination of slot x: off + x
+            const uint32_t da = off + sa, de = off + se;             // [da, de)
+            for (uint32_t w = (da >> 6) + (uint32_t)lane; w <= (de - 1) >> 6; w += kWave) {
+                const uint32_t lo = max(da, 64u * w) - 64u * w;
+                const uint32_t hi = min(de, 64u * w + 64u) - 64u * w;
+                const uint64_t own = bit_range(lo, hi);
+                // the group holding position n-1 also clears the padding bits
+                const uint64_t pad = (de == a.n && hi < 64u) ? bit_range(hi, 64u) : 0ull;
+                const uint64_t val = slot_bits64(SB, (int32_t)(64u * w) - (int32_t)off) & own;
+                if ((own | pad) == ~0ull) {
+                    B[w] = val;
+                } else {
+                    atomicAnd((unsigned long long *)(B + w), (unsigned long long)~(own | pad));
+                    if (val) atomicOr((unsigned long long *)(B + w), (unsigned long long)val);
+                }
+            }
+        }
+        return;
+    }
     LaneCount lc;
 #pragma unroll
     for (int i = 0; i < kChunksPerWave / kWave; ++i) {
@@ -897,11 +1029,11 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
                     if (((dest + 15) >> a.next_shift) == nt) {
                         const uint32_t ones = (uint32_t)(__popc(v.x & Mn) + __popc(v.y & Mn) + __popc(v.z & Mn) +
                                                          __popc(v.w & Mn));
-                        lc.step(nt, 16u - ones, ftile, fcnt);
+                        lc.step(PIECES ? nt + q0 : nt, 16u - ones, ftile, fcnt);
                     } else {
                         for (uint32_t c = 0; c < 16; ++c)
                             if (!((byte_of(v, (int)c) >> kn) & 1u))
-                                count_add(s.ct, a.next_cnt, (dest + c) >> a.next_shift, 1u);
+                                count_add(s.ct, a.next_cnt, ((dest + c) >> a.next_shift) + (PIECES ? q0 : 0u), 1u);
                     }
                 }
             } else {
@@ -912,7 +1044,8 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
                     const uint32_t dest = s.D[qc] + ((qc & 1u) ? O0 + sc - Zt : Z0 + sc);
                     if (dest < a.n) {
                         out[dest] = (uint8_t)bc;
-                        if (!((bc >> kn) & 1u)) count_add(s.ct, a.next_cnt, dest >> a.next_shift, 1u);
+                        if (!((bc >> kn) & 1u))
+                            count_add(s.ct, a.next_cnt, (dest >> a.next_shift) + (PIECES ? qc : 0u), 1u);
                     }
                 }
             }
@@ -922,6 +1055,41 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     lc.flush_wave(s.ct, a.next_cnt, lane);
     __syncthreads();
     count_flush(s.ct, a.next_cnt, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Directories of a level whose bits are already in place (the last level,
+// written by the LASTBITS pass of level L-2): one wave per tile of 2^14
+// positions, lane j holding words 4j .. 4j+3 (position order), their zeros,
+// a wave scan, and the entries (emit_directories); with a.tails the level's
+// directory tail too.  a.tile_prefix holds the zeros before each tile (from
+// the count-ahead of level L-2).
+__device__ __forceinline__ void level_dirs_tile(const LevelArgs &a, uint64_t tile, uint64_t ntiles) {
+    constexpr uint32_t kTile = 16384, kWPL = 4;
+    const int lane = lane_id();
+    const uint64_t t0 = tile * kTile;
+    const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
+    if (*a.status) return;
+    if (a.tails)
+        dir_tail(0, a.D[a.nD - 1], a.n, a.L, a.rank, a.rank_len, a.sel1, a.sel0, a.cap, a.sel_counts + a.level,
+                 tile * kWave + lane, ntiles * kWave);
+    const uint64_t Z0 = a.tile_prefix[tile];
+    uint64_t wd[kWPL];
+    uint32_t zp[kWPL], own = 0;
+    const uint64_t *B = a.bits + (t0 >> 6);
+    // (a level's words start 8-byte aligned only: W need not be even)
+#pragma unroll
+    for (int m = 0; m < kWPL; ++m) wd[m] = (uint32_t)(lane * kWPL + m) * 64u < len ? B[lane * kWPL + m] : 0ull;
+#pragma unroll
+    for (int m = 0; m < kWPL; ++m) {
+        zp[m] = own;
+        own += clamp_count(len, (uint32_t)(lane * kWPL + m) * 64u, 64u) - (uint32_t)__popcll(wd[m]);
+    }
+    const uint32_t inc = wave_incl_scan_u32(own, lane);
+    const uint32_t Zt = __shfl(inc, kWave - 1, kWave), ex = inc - own;
+#pragma unroll
+    for (int m = 0; m < kWPL; ++m) zp[m] += ex;
+    emit_directories<kWPL>(wd, zp, Z0, t0, len, Zt, a.n, a.rank, a.sel1, a.sel0, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -974,11 +1142,6 @@ struct FusedArgs {
     const uint32_t *l0;     // first fused level (>= L: no fusion)
 };
 
-// Bits [lo, hi) of a word, 0 <= lo <= hi <= 64.
-__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi) {
-    const uint64_t h = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
-    return h & ~((1ull << lo) - 1ull);
-}
 
 // First fused level from the largest node of each level: the first level
 // whose nodes all fit in kHalf positions, if it leaves a split to do

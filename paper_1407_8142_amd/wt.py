@@ -32,7 +32,7 @@ EXPORTS = ["wt_plan", "wt_build", "wt_build_rank_select", "wt_rank_select_scratc
            "wt_huffman_select", "wt_sort_scratch_bytes", "wt_build_sort", "wt_histogram_path", "wt_build_noalloc"]
 NOALLOC_SCRATCH_BYTES = 64 << 20  # WT_NOALLOC_SCRATCH_BYTES
 Q_ACCESS, Q_RANK, Q_SELECT, Q_BAD = 0, 1, 2, -2
-HIST_NONE, HIST_REPLICAS, HIST_HASH, HIST_SLICES, HIST_TWO_PHASE = 0, 1, 2, 3, 4
+HIST_NONE, HIST_REPLICAS, HIST_HASH, HIST_SLICES, HIST_TWO_PHASE, HIST_LEVELS = 0, 1, 2, 3, 4, 5
 
 
 class WTError(RuntimeError):

@@ -291,7 +291,10 @@ def test_sort_scratch_and_argument_errors_are_synchronous():
 
 @pytest.mark.parametrize("n,sigma,b,path", [
     (0, 256, 1, wt.HIST_NONE),
-    (1 << 28, 256, 1, wt.HIST_REPLICAS),
+    (1 << 28, 256, 1, wt.HIST_LEVELS),
+    (1 << 20, 146, 1, wt.HIST_LEVELS),
+    (1000, 256, 1, wt.HIST_REPLICAS),   # small: fused tail levels, which need C first
+    (1 << 20, 300, 2, wt.HIST_REPLICAS),
     (1 << 20, 8192, 2, wt.HIST_REPLICAS),
     (1 << 27, 1 << 16, 4, wt.HIST_SLICES),
     (1 << 27, 1 << 20, 4, wt.HIST_TWO_PHASE),
