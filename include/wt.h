@@ -89,8 +89,13 @@ typedef struct {
 } wt_outputs;
 
 /* Fill *out with the sizes for (n, sigma, sym_bytes).
- * Valid: sigma >= 1; sym_bytes in {1, 2, 4}; sigma <= 2^(8*sym_bytes);
- * n < 2^40.  Returns WT_ERR_ARG / WT_ERR_RANGE otherwise. */
+ * Valid: sigma >= 1; sym_bytes in {1, 2, 4}; sigma <= 2^(8*sym_bytes) (so
+ * L <= 32); n < 2^40.  Returns WT_ERR_ARG / WT_ERR_RANGE otherwise.
+ * The scratch holds node tables for every node of every level (2^(L+1)
+ * words) when that is small next to the sequence; for 32-bit alphabets
+ * with L > 16 much larger than n, and always for L > 30, it holds tables
+ * for the nonempty nodes of one level at a time (at most min(n, sigma)),
+ * so it grows with n, not with 2^L.  C is always dense (sigma + 1 words). */
 int wt_plan(uint64_t n, uint64_t sigma, int sym_bytes, wt_layout *out);
 
 /* Build the tree of d_seq[0..n) (levelWT, Fig. 1): C, every level bitmap
@@ -171,7 +176,8 @@ typedef struct {
 } wt_view;
 
 /* Batched queries (Preliminaries), one result per query, m queries.
- * wt_access: d_sym[j] = S[d_i[j]]; d_i[j] >= n gives 0xFFFFFFFF.
+ * wt_access: d_sym[j] = S[d_i[j]]; d_i[j] >= n gives 0xFFFFFFFF (which is
+ *            also a valid symbol when sigma = 2^32: check d_i[j] < n).
  * wt_rank:   d_out[j] = number of c = d_c[j] in S[0, min(d_i[j], n))
  *            (the paper's inclusive rank_c(S, i) is wt_rank(c, i+1));
  *            c >= sigma gives 0.

@@ -33,6 +33,7 @@
 #include "wt_huff.hpp"
 #include "wt_sort.hpp"
 #include "wt_stats.hpp"
+#include "wt_sparse.hpp"
 #include "wt_u16.hpp"
 #include "wt_u32.hpp"
 
@@ -442,9 +443,12 @@ __global__ __launch_bounds__(kBlock) void level_pass_u8(LevelArgs a) {
 constexpr int kDirsWaves = 4;  // tiles (one per wave) per block of level_dirs
 
 __global__ __launch_bounds__(kDirsWaves * kWave) void level_dirs(LevelArgs a) {
+    __shared__ uint64_t s_cl[kStatsMaxNodes + 1];
+    for (uint32_t i = threadIdx.x; i < a.nodes; i += kDirsWaves * kWave) s_cl[i] = a.node_starts[i];
+    __syncthreads();
     const uint64_t ntiles = cdiv(a.n, 16384);
     const uint64_t tile = (uint64_t)blockIdx.x * kDirsWaves + threadIdx.x / kWave;
-    if (tile < ntiles) level_dirs_tile(a, tile, ntiles);
+    if (tile < ntiles) level_dirs_tile(a, tile, ntiles, s_cl);
 }
 
 template <bool SCATTER, bool DIRS>
@@ -668,6 +672,9 @@ struct Plan {
     uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_M, off_S0, off_S1, total;
     uint64_t off_PZ, off_NZ, off_CL;  // byte alphabets: piece counts, node zeros, node starts (wt_stats.hpp)
     uint64_t PS;                      // piece counts per level
+    bool sparse;                      // node tables over the nonempty nodes only (wt_sparse.hpp)
+    uint64_t ucap;                    // sparse: most distinct symbols, min(n, sigma)
+    uint64_t off_U, off_NID, off_NS, off_SP;  // sparse: distinct symbols, node ids, node starts, counters
     uint64_t n_part;
 };
 
@@ -684,15 +691,20 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     p.n = n;
     p.sigma = sigma;
     p.L = levels_of(sigma);
-    if (p.L > 30) return WT_ERR_RANGE;  // dense node tables: 2^(L+1) words
     p.in_bytes = (uint32_t)sym_bytes;
+    // Dense node tables hold 2^(L+1) words; past 30 levels, or when they
+    // would dwarf the sequence, only the nonempty nodes (at most min(n, sigma)
+    // per level) get entries.
+    p.ucap = std::min<uint64_t>(n, sigma);
+    p.sparse = p.in_bytes == 4 && p.L > 16 && (p.L > 30 || (2ull << p.L) > 4 * p.ucap + 65536);
     p.mid_bytes = p.L <= 8 ? 1u : (p.L <= 16 ? 2u : 4u);  // width of S_l for l >= 1
     p.W = cdiv(n, 64);
     p.T = cdiv(n, kMinTile);
     p.rank_len = cdiv(n, WT_RANK_BLOCK_BITS) + 1;
     p.cap = cdiv(n, WT_SELECT_SAMPLE) + 1;
-    const uint64_t table_elems = p.L ? (1ull << p.L) : 0;        // node heap indices [0, 2^L)
-    const uint64_t D_len = p.L ? (2ull << p.L) - 2 : 0;          // 2^(l+1) entries per level
+    const uint64_t table_elems = p.L && !p.sparse ? (1ull << p.L) : 0;  // node heap indices [0, 2^L)
+    // 2^(l+1) entries per level, or 2 per nonempty node of one level at a time
+    const uint64_t D_len = p.sparse ? 2 * p.ucap : (p.L ? (2ull << p.L) - 2 : 0);
     const uint64_t part_c = cdiv(sigma, kScanChunk);
     const uint64_t part_t = cdiv(table_elems, kScanChunk);
     p.n_part = std::max<uint64_t>(std::max<uint64_t>(part_c, part_t), 1);
@@ -726,6 +738,15 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     o = align_up(o + (byte_stats ? 8ull << p.L : 0), 256);
     p.off_CL = o;
     o = align_up(o + (byte_stats ? 8 * ((1ull << p.L) + p.L) : 0), 256);
+    const uint64_t uc = p.sparse ? p.ucap : 0;
+    p.off_U = o;
+    o = align_up(o + 4 * uc, 256);
+    p.off_NID = o;
+    o = align_up(o + 4 * uc, 256);
+    p.off_NS = o;
+    o = align_up(o + (p.sparse ? 8 * (uc + 1) : 0), 256);
+    p.off_SP = o;  // |U|, node count, zeros of every level
+    o = align_up(o + (p.sparse ? 8ull * (2 + p.L) : 0), 256);
     p.off_S0 = o;
     const uint64_t sbytes = p.L >= 2 ? align_up(n * p.mid_bytes, 256) : 0;
     o += sbytes;
@@ -1001,7 +1022,7 @@ static PathChoice choose_path(const Plan &p, bool matrix, bool dirs) {
     // passes without the per-tile check of the fused level.
     c.lmin = 0;
     while (c.lmin < 63 && cdiv(n, 1ull << c.lmin) > fused_half(p.mid_bytes)) ++c.lmin;
-    c.fuse = g_fuse && !matrix && dirs && p.L >= 2 && n > 0 && c.lmin + 2 <= p.L;
+    c.fuse = g_fuse && !matrix && !p.sparse && dirs && p.L >= 2 && n > 0 && c.lmin + 2 <= p.L;
     // Two levels per pass: byte symbols in and between levels, nothing fused
     // (inputs too small for that are the fused pass's), 32-bit positions.
     c.pairs = g_pairs && !matrix && !c.fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
@@ -1013,7 +1034,7 @@ static PathChoice choose_path(const Plan &p, bool matrix, bool dirs) {
     c.fine_blocks = (uint32_t)std::min(num_cus(), 1024);
     const uint64_t fine_rows = (uint64_t)c.fine_blocks << kFineBits;  // u32 counts
     const uint64_t fine_bytes = 4 * fine_rows + 8 * align_up(p.sigma, 32) + 4 * 1024;
-    c.two_phase = g_slices && !matrix && !c.pairs && c.cbits >= 1 && c.cbits <= kCoarseMaxBits &&
+    c.two_phase = g_slices && !matrix && !c.pairs && !p.sparse && c.cbits >= 1 && c.cbits <= kCoarseMaxBits &&
                   p.in_bytes == 4 && p.mid_bytes == 4 && n >= (1ull << 20) && n < (1ull << 32) &&
                   fine_bytes <= align_up(n * p.mid_bytes, 256) && (!c.fuse || c.lmin >= c.cbits);
     // Byte alphabets with no fused or paired levels: no histogram pass (the
@@ -1136,7 +1157,6 @@ static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, un
                      hipStream_t s, bool timed) {
     const uint64_t n = p.n;
     uint32_t *status = (uint32_t *)(sc + p.off_status);
-    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
     uint64_t *D = (uint64_t *)(sc + p.off_D);
     uint32_t *pz = (uint32_t *)(sc + p.off_PZ);
     uint64_t *NZ = (uint64_t *)(sc + p.off_NZ), *CL = (uint64_t *)(sc + p.off_CL);
@@ -1155,7 +1175,7 @@ static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, un
         const bool scatter = l + 1 < p.L;
         StatsArgs sa;
         sa.pieces = pz + (uint64_t)l * p.PS;
-        sa.pre = pre + (uint64_t)l * p.T;
+        sa.E = pz + (uint64_t)l * p.PS;  // in place: each thread rewrites only the counts it read
         sa.T = Tl;
         sa.tile_shift = tile_shift_for(1);
         sa.level = l;
@@ -1175,7 +1195,10 @@ static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, un
         a.bits = out->bits + (uint64_t)l * p.W;
         a.D = sa.D;
         a.nD = 2ull << l;
-        a.tile_prefix = sa.pre;
+        a.tile_prefix = nullptr;
+        a.piece_prefix = sa.E;
+        a.node_starts = CL + (1ull << l) - 1 + l;  // CL_l (read by the last level's directory pass)
+        a.nodes = (1u << l) + 1;
         a.next_cnt = scatter ? pz + (uint64_t)(l + 1) * p.PS : nullptr;
         a.next_shift = tile_shift_for(1);
         a.status = status;
@@ -1210,10 +1233,121 @@ static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, un
         } else if (scatter) {
             if (dirs) launch_k(level_pass_u8<true, true, true>, g, b, s, a);
             else launch_k(level_pass_u8<true, false, true>, g, b, s, a);
-        } else {
-            if (dirs) launch_k(level_pass_u8<false, true>, g, b, s, a);
-            else launch_k(level_pass_u8<false, false>, g, b, s, a);
+        } else {  // L = 1: the only level, its tile prefixes from its pieces (no tile_prefix array here)
+            if (dirs) launch_k(level_pass_u8<false, true, true>, g, b, s, a);
+            else launch_k(level_pass_u8<false, false, true>, g, b, s, a);
         }
+        if (timed && (rc = timing_end(s, ev))) return rc;
+        if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
+        cur = dst;
+    }
+    return WT_OK;
+}
+
+// One device-wide scan over `count` values of the functor (see scan_final).
+template <typename F>
+static void run_scan(const F &f, uint64_t count, uint64_t *part, hipStream_t s) {
+    const uint64_t chunks = cdiv(count, kScanChunk);
+    if (chunks > 1) {
+        scan_reduce<F><<<(unsigned)chunks, kBlock, 0, s>>>(f, count, part);
+        scan_partials_seg<F><<<1, kBlock, 0, s>>>(f, chunks, part);
+        scan_final<F><<<(unsigned)chunks, kBlock, 0, s>>>(f, count, part);
+    } else if (count > 0) {
+        scan_final<F><<<1, kBlock, 0, s>>>(f, count, nullptr);
+    }
+}
+
+// The zeros of every level and their {0, zeros} tables for the wavelet
+// matrix, from the symbols present.
+__global__ void matrix_tables_from_zeros(const uint64_t *zeros_l, uint32_t L, uint64_t *Dm, uint64_t *zeros) {
+    const uint32_t l = threadIdx.x;
+    if (l >= L) return;
+    Dm[2 * l] = 0;
+    Dm[2 * l + 1] = zeros_l[l];
+    if (zeros) zeros[l] = zeros_l[l];
+}
+
+struct SparseLevel {
+    LevelArgs a;
+    SparseArgs sp;
+};
+
+template <typename TIN, typename TOUT, bool SCATTER, bool DIRS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void level_pass_sparse(SparseLevel x) {
+    __shared__ LdsSparse<TIN> s;
+    level_tile_sparse<TIN, TOUT, SCATTER, DIRS>(x.a, x.sp, blockIdx.x, s);
+}
+
+// Sparse node tables (wt_sparse.hpp), after C: the distinct symbols, then
+// per level its nonempty nodes, their table and the level's zeros.  For the
+// tree, each level's pass follows its table; for the wavelet matrix only
+// the zeros of every level are needed (its matrix passes run afterwards).
+static int sparse_tables(const Plan &p, const wt_outputs *out, unsigned char *sc, uint32_t l, hipStream_t s) {
+    uint32_t *U = (uint32_t *)(sc + p.off_U), *NID = (uint32_t *)(sc + p.off_NID);
+    uint64_t *NS = (uint64_t *)(sc + p.off_NS), *SP = (uint64_t *)(sc + p.off_SP);
+    uint64_t *D = (uint64_t *)(sc + p.off_D), *part = (uint64_t *)(sc + p.off_part);
+    if (l == 0) run_scan(CompactOp{out->C, p.sigma, U, SP}, p.sigma, part, s);
+    run_scan(NodeIdOp{U, SP, p.L - l, NID, SP + 1}, p.ucap, part, s);
+    run_scan(SparseTableOp{out->C, p.sigma, p.n, NID, SP + 1, p.L - l, NS, D, SP + 2 + l}, p.ucap, part, s);
+    return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
+}
+
+template <typename TIN, typename TOUT>
+static void launch_sparse_t(bool scatter, bool dirs, hipStream_t s, const SparseLevel &x) {
+    const dim3 g((unsigned)cdiv(x.a.n, TileCfg<TIN>::kTile)), b(kBlock);
+    if (scatter) {
+        if (dirs) launch_k(level_pass_sparse<TIN, TOUT, true, true>, g, b, s, x);
+        else launch_k(level_pass_sparse<TIN, TOUT, true, false>, g, b, s, x);
+    } else {
+        if (dirs) launch_k(level_pass_sparse<TIN, TOUT, false, true>, g, b, s, x);
+        else launch_k(level_pass_sparse<TIN, TOUT, false, false>, g, b, s, x);
+    }
+}
+
+static int run_sparse(const void *d_seq, const Plan &p, const wt_outputs *out, unsigned char *sc, bool dirs,
+                      hipStream_t s, bool timed) {
+    const uint64_t n = p.n;
+    uint32_t *status = (uint32_t *)(sc + p.off_status);
+    uint32_t *cnt = (uint32_t *)(sc + p.off_cnt);
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre);
+    uint64_t *D = (uint64_t *)(sc + p.off_D), *SP = (uint64_t *)(sc + p.off_SP);
+    const uint32_t shift = tile_shift_for(4);
+    const uint64_t Tl = cdiv(n, 1ull << shift);
+    const void *cur = d_seq;
+    int rc;
+    for (uint32_t l = 0; l < p.L; ++l) {
+        if ((rc = sparse_tables(p, out, sc, l, s))) return rc;
+        const bool scatter = l + 1 < p.L;
+        void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
+        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
+        LevelArgs a;
+        a.in = cur;
+        a.out = scatter ? dst : nullptr;
+        a.bits = out->bits + (uint64_t)l * p.W;
+        a.D = D;
+        a.nD = 2 * p.ucap;
+        a.tile_prefix = pre + (uint64_t)l * p.T;
+        a.next_cnt = scatter ? cnt + (uint64_t)(l + 1) * p.T : nullptr;
+        a.next_shift = shift;
+        a.status = status;
+        a.rank = dirs ? out->rank + (uint64_t)l * p.rank_len : nullptr;
+        a.sel1 = dirs ? out->sel1 + (uint64_t)l * p.cap : nullptr;
+        a.sel0 = dirs ? out->sel0 + (uint64_t)l * p.cap : nullptr;
+        a.n = n;
+        a.k = p.L - 1 - l;
+        a.level = l;
+        a.fused_l0 = nullptr;
+        a.qmask = ~0u;
+        a.tails = dirs ? 1u : 0u;
+        a.L = p.L;
+        a.sel_counts = out->sel_counts;
+        a.rank_len = p.rank_len;
+        a.cap = p.cap;
+        const SparseLevel x{a, SparseArgs{(const uint32_t *)(sc + p.off_NID), (const uint64_t *)(sc + p.off_NS),
+                                          SP + 1, SP + 2 + l}};
+        std::pair<hipEvent_t, hipEvent_t> ev;
+        if (timed && (rc = timing_begin(s, ev))) return rc;
+        launch_sparse_t<uint32_t, uint32_t>(scatter, dirs, s, x);
         if (timed && (rc = timing_end(s, ev))) return rc;
         if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
         cur = dst;
@@ -1324,7 +1458,27 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
             scan_final<CScanOp><<<1, kBlock, 0, s>>>(cop, sigma, nullptr);
         }
     };
-    if (p.L > 0) tables(two_phase ? (1ull << cbits) : (1ull << p.L), !two_phase);
+    if (p.sparse) {
+        // Sparse node tables: the tree's passes follow them level by level;
+        // the matrix needs only every level's zeros, then its own passes.
+        uint64_t *SP = (uint64_t *)(sc + p.off_SP);
+        if (n == 0) {
+            zero_fill<<<1, kBlock, 0, s>>>(SP + 2, p.L, nullptr, 0);
+        } else if (matrix) {
+            for (uint32_t l = 0; l < p.L; ++l)
+                if ((rc = sparse_tables(p, out, sc, l, s))) return rc;
+        } else {
+            return run_sparse(d_seq, p, out, sc, dirs, s, timed);
+        }
+        if (matrix) matrix_tables_from_zeros<<<1, kWave, 0, s>>>(SP + 2, p.L, Dm, d_zeros);
+        if (dirs) {
+            dim3 g((unsigned)cdiv(p.cap, kBlock), p.L);
+            dir_finish<<<g, kBlock, 0, s>>>(nullptr, SP + 2, n, p.L, out->rank, p.rank_len, out->sel1, out->sel0,
+                                            p.cap, out->sel_counts);
+        }
+    } else if (p.L > 0) {
+        tables(two_phase ? (1ull << cbits) : (1ull << p.L), !two_phase);
+    }
     if (hipGetLastError() != hipSuccess) return WT_ERR_HIP;
     if (n == 0 || p.L == 0) return WT_OK;
     if (pairs) return run_pairs(d_seq, p, out, sc, dirs, s, timed);

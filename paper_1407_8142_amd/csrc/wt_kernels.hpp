@@ -372,6 +372,12 @@ struct LevelArgs {
     void *out;               // S_{l+1} (TOUT)
     uint64_t *bits;          // B_l
     uint64_t *next_bits = nullptr;  // B_{l+1}, written by the pass of level L-2 (LASTBITS)
+    // Byte passes with PIECES: zeros of B_l before each piece of the level
+    // (tile + node; see wt_stats.hpp) instead of tile_prefix: a tile's own
+    // prefix is the one of its first piece, found from its first symbol.
+    const uint32_t *piece_prefix = nullptr;
+    const uint64_t *node_starts = nullptr;  // the last level's directory pass: its node starts
+    uint32_t nodes = 0;                     // (2^(L-1) + 1 of them)
     const uint64_t *D;       // D_l: 2^(l+1) entries
     uint64_t nD;             // 2^(l+1)
     const uint64_t *tile_prefix;  // zeros of B_l before each tile of this level
@@ -741,6 +747,7 @@ struct LdsLevelU8 {
     uint16_t zpre[kTile / 64];  // at most kTile
     uint32_t D[256];
     CountTableN<5> ct;  // with the 16-bit zpre: 8 blocks per CU fit in LDS
+    uint32_t z0;        // PIECES: the tile's zero prefix, looked up by thread 0
 };
 
 // Bits [lo, hi) of a word, 0 <= lo <= hi <= 64.
@@ -778,13 +785,17 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
     const uint32_t t0 = tile * (uint32_t)kTile;
     const uint32_t len = (uint32_t)min((uint64_t)kTile, a.n - t0);
     const uint32_t k = a.k;
-    const uint32_t Z0 = (uint32_t)a.tile_prefix[tile];  // zeros of the level before this tile
+    // Zeros of the level before this tile: from the tile prefixes, or (PIECES)
+    // the prefix of the tile's first piece, whose node is its first symbol's
+    // top l bits (looked up by thread 0, read by all after the first barrier).
+    uint32_t Z0 = PIECES ? 0u : (uint32_t)a.tile_prefix[tile];
+    const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
+    const uint32_t first = PIECES && tid == 0 ? (uint32_t)in[0] : 0u;
 
     // Load: thread t, row r holds positions r*4096 + 16t .. +15.  A whole
     // tile's four loads are issued back to back (no branch between them),
     // so their latencies overlap; the node table follows them.  Positions
     // past the end of a short tile read as 0xFF (see the split).
-    const uint8_t *in = reinterpret_cast<const uint8_t *>(a.in) + t0;
     uint4 d[kRows];
     uint32_t m[kRows], z[kRows];
     if (len == (uint32_t)kTile) {
@@ -835,7 +846,9 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
         s.wz[2][wave] = i23 & 0xFFFFu;
         s.wz[3][wave] = i23 >> 16;
     }
+    if (PIECES && tid == 0) s.z0 = a.piece_prefix[tile + (first >> (k + 1))];
     __syncthreads();
+    if (PIECES) Z0 = s.z0;
     const uint32_t e01 = i01 - v01, e23 = i23 - v23;
     const uint32_t we[kRows] = {e01 & 0xFFFFu, e01 >> 16, e23 & 0xFFFFu, e23 >> 16};
     uint32_t zl[kRows], acc = 0;
@@ -1064,7 +1077,9 @@ __device__ __forceinline__ void level_tile_u8(const LevelArgs &a, uint32_t tile,
 // a wave scan, and the entries (emit_directories); with a.tails the level's
 // directory tail too.  a.tile_prefix holds the zeros before each tile (from
 // the count-ahead of level L-2).
-__device__ __forceinline__ void level_dirs_tile(const LevelArgs &a, uint64_t tile, uint64_t ntiles) {
+// s_cl: the level's node starts (a.nodes of them, the last = n) in LDS.
+__device__ __forceinline__ void level_dirs_tile(const LevelArgs &a, uint64_t tile, uint64_t ntiles,
+                                                const uint64_t *s_cl) {
     constexpr uint32_t kTile = 16384, kWPL = 4;
     const int lane = lane_id();
     const uint64_t t0 = tile * kTile;
@@ -1073,7 +1088,15 @@ __device__ __forceinline__ void level_dirs_tile(const LevelArgs &a, uint64_t til
     if (a.tails)
         dir_tail(0, a.D[a.nD - 1], a.n, a.L, a.rank, a.rank_len, a.sel1, a.sel0, a.cap, a.sel_counts + a.level,
                  tile * kWave + lane, ntiles * kWave);
-    const uint64_t Z0 = a.tile_prefix[tile];
+    // The tile's prefix: its first piece's, whose node is the last one
+    // starting at or before t0.
+    uint32_t lo = 0, hi = a.nodes - 1;  // s_cl[lo] <= t0 < s_cl[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (s_cl[mid] <= t0) lo = mid;
+        else hi = mid;
+    }
+    const uint64_t Z0 = a.piece_prefix[tile + lo];
     uint64_t wd[kWPL];
     uint32_t zp[kWPL], own = 0;
     const uint64_t *B = a.bits + (t0 >> 6);

@@ -105,14 +105,15 @@ __global__ __launch_bounds__(kBlock) void stats_prep_u8(const uint8_t *__restric
 //   E        = exclusive scan of the piece counts (at level 0 the tiles'
 //              kBadTile flags are ORed into the status word);
 //   CL_l     = node starts, from CL_{l-1} and NZ_{l-1} (CL_0 = {0, n});
-//   pre[t]   = zeros of B_l before tile t = E[t + node(t * tile)];
+//   E        also goes to memory: the passes of level l take a tile's zero
+//            prefix as E[t + node of its first position];
 //   ZB[p]    = zeros before node p = E[tile(CL_l[p]) + p], NZ_l[p] = ZB[p+1] - ZB[p];
 //   D_l      = the level pass's node table: D_l[2p] = ones of B_l before
 //              node p = CL_l[p] - ZB[p], D_l[2p+1] = zeros before node p+1;
 //   at the last level, C[c] = CL_L[c] for c <= sigma.
 struct StatsArgs {
     const uint32_t *pieces; // level l's piece counts (T + 2^l + 1 used)
-    uint64_t *pre;          // tile prefixes of level l
+    uint32_t *E;            // their exclusive prefixes (read by the level's passes; may be `pieces`)
     uint64_t T;             // tiles of the level
     uint32_t tile_shift;    // log2 positions per tile
     uint32_t level, L;
@@ -155,10 +156,9 @@ __global__ __launch_bounds__(kStatsThreads) void stats_scan(StatsArgs a) {
     }
 
     // 2. Exclusive scan of the piece counts, a round of kStatsRound at a time
-    //    (one round for up to 2^28 byte symbols), each round's prefixes kept
-    //    in LDS; then the prefixes the level needs are picked from it: tile
-    //    t's (its first piece, index t + node(t) <= t + P - 1) and node p's
-    //    (index tile(CL[p]) + p).
+    //    (one round for up to 2^28 byte symbols), to memory and, for the
+    //    round, to LDS, where node p's prefix (index tile(CL[p]) + p) is
+    //    picked.
     uint64_t carry = 0;
     bool bad = false;
     for (uint64_t c0 = 0; c0 <= npieces; c0 += kStatsRound) {
@@ -197,35 +197,25 @@ __global__ __launch_bounds__(kStatsThreads) void stats_scan(StatsArgs a) {
             total += x;
         }
         uint32_t run = (uint32_t)carry + before + inc - own;  // n < 2^32
+        uint32_t ex[kStatsPer];
 #pragma unroll
         for (int j = 0; j < kStatsPer; ++j) {
+            ex[j] = run;
             s_e[tid * kStatsPer + j] = run;
             run += v[j];
         }
+        if (base + kStatsPer <= npieces + 1) {
+            uint4 *e4 = reinterpret_cast<uint4 *>(a.E + base);
+#pragma unroll
+            for (int q = 0; q < kStatsPer / 4; ++q)
+                e4[q] = make_uint4(ex[4 * q], ex[4 * q + 1], ex[4 * q + 2], ex[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kStatsPer; ++j)
+                if (base + j <= npieces) a.E[base + j] = ex[j];
+        }
         __syncthreads();
         const uint64_t c1 = min(c0 + kStatsRound, npieces + 1);  // this round: indices [c0, c1)
-        // Tiles whose first piece may be in this round, kStatsPer + 1
-        // consecutive ones per thread: one search for the first, then the
-        // node pointer only moves forward.
-        const uint64_t tlo = c0 >= P ? c0 - (P - 1) : 0, thi = min(c1, a.T);
-        const uint64_t tper = (thi > tlo ? thi - tlo + kStatsThreads - 1 : 0) / kStatsThreads;
-        uint64_t t = tlo + (uint64_t)tid * tper;
-        const uint64_t tend = min(t + tper, thi);
-        if (t < tend) {
-            uint32_t lo = 0, hi = P;  // s_cl[lo] <= x < s_cl[hi]
-            const uint64_t x0 = t << a.tile_shift;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) / 2;
-                if (s_cl[mid] <= x0) lo = mid;
-                else hi = mid;
-            }
-            for (; t < tend; ++t) {
-                const uint64_t x = t << a.tile_shift;
-                while (lo + 1 < P && s_cl[lo + 1] <= x) ++lo;
-                const uint64_t f = t + lo;
-                if (f >= c0 && f < c1) a.pre[t] = s_e[f - c0];
-            }
-        }
         if ((uint32_t)tid <= P) {
             const uint64_t g = min((s_cl[tid] >> a.tile_shift) + (uint64_t)tid, npieces);
             if (g >= c0 && g < c1) s_zb[tid] = s_e[g - c0];

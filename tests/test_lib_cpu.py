@@ -44,7 +44,8 @@ def test_header_compiles_as_c():
 @pytest.mark.parametrize("n,sigma,b,L", [(0, 1, 1, 0), (1, 2, 1, 1), (100, 3, 1, 2), (1 << 20, 256, 1, 8),
                                          (1 << 28, 256, 1, 8), (10, 257, 2, 9), (1 << 27, 1 << 16, 4, 16),
                                          (1 << 27, 1 << 20, 4, 20), (5, (1 << 20) + 1, 4, 21),
-                                         (5, 1 << 16, 2, 16)])
+                                         (5, 1 << 16, 2, 16), (10, (1 << 31) + 1, 4, 32), (1000, 1 << 32, 4, 32),
+                                         (1 << 20, 1 << 31, 4, 31)])
 def test_plan_sizes(n, sigma, b, L):
     lay = wt.plan(n, sigma, b)
     assert lay.L == L
@@ -63,7 +64,7 @@ def test_plan_sizes(n, sigma, b, L):
 
 
 @pytest.mark.parametrize("n,sigma,b", [(10, 0, 1), (10, 257, 1), (10, 65537, 2), (10, 5, 3), (1 << 40, 4, 1),
-                                       (10, (1 << 31) + 1, 4)])
+                                       (10, (1 << 32) + 1, 4)])
 def test_plan_rejects(n, sigma, b):
     with pytest.raises(wt.WTError) as e:
         wt.plan(n, sigma, b)
@@ -306,3 +307,14 @@ def test_histogram_path(n, sigma, b, path):
     # the host-side choice of histogram (a 256-CU device is assumed without a GPU)
     assert wt.histogram_path(n, sigma, b) == path
 
+
+
+@pytest.mark.parametrize("n,sigma", [(1 << 12, 1 << 20), (1 << 20, 1 << 32), (100_003, (1 << 31) + 1),
+                                     (1 << 27, 1 << 30)])
+def test_sparse_tables_keep_scratch_small(n, sigma):
+    """Alphabets much larger than n (and every L > 30) get node tables over
+    the nonempty nodes only: the scratch grows with n, not with 2^L."""
+    lay = wt.plan(n, sigma, 4)
+    dense_words = 2 << lay.L
+    assert lay.scratch_bytes < 8 * dense_words or lay.L > 30
+    assert lay.scratch_bytes <= 2 * 4 * n + 64 * n + (64 << 20)
