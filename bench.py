@@ -57,20 +57,29 @@ def source_sha() -> str:
     return h.hexdigest()
 
 
-def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int, passes: int) -> list[float]:
+def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int, passes: int,
+                     lastbits: bool = False) -> list[float]:
     """Algorithmic HBM bytes of each level-pass launch.  One level per pass:
     read the level's sequence, write the next one (not on the last level),
     write the level bits (n/8), the rank directory (8 B per 512 bits) and
-    select samples (8 B per 4096 ones and per 4096 zeros).  Two levels per
-    pass (byte alphabets): read S_l once, write S_{l+2} (not from the last
-    pair), and two levels of bits and directories; an odd last level alone."""
+    select samples (8 B per 4096 ones and per 4096 zeros).  With `lastbits`
+    level L-2 writes the last level's bits (n/8) instead of its sequence,
+    and the last launch reads those bits (n/8) for the directories.  Two
+    levels per pass (byte alphabets): read S_l once, write S_{l+2} (not from
+    the last pair), and two levels of bits and directories; an odd last
+    level alone."""
     dirs = n / 8 + n / 64 + n / 256
     out = []
     if passes == L:
         for l in range(L):
             rd = in_bytes if l == 0 else mid_bytes
             wr = mid_bytes if l + 1 < L else 0
-            out.append(n * (rd + wr) + dirs)
+            if lastbits and l + 2 == L:
+                out.append(n * rd + dirs + n / 8)
+            elif lastbits and l + 1 == L:
+                out.append(n / 8 + dirs)
+            else:
+                out.append(n * (rd + wr) + dirs)
         return out
     l = 0
     while l < L:
@@ -99,16 +108,122 @@ def traffic_per_launch(workload: str):
     return ent.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(S, sigma, L, sample_n):
+def cpu_info():
+    """(model name, online CPUs, CPUs this process may use)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def cpu_baseline(S, sigma, L, sample_n, reps: int = 3):
+    """The oracle (sequential, one thread) on the first sample_n symbols:
+    bits, C and rank/select, the median of `reps` runs."""
     from oracle import oracle
     sub = S[:sample_n].copy()
-    t0 = time.perf_counter()
-    t = oracle.build(sub, sigma)
-    oracle.rank_select(t["bits"], t["n"], t["L"])
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        t = oracle.build(sub, sigma)
+        oracle.rank_select(t["bits"], t["n"], t["L"])
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
+    model, online, avail = cpu_info()
     return {"value": sample_n * L / dt, "unit": "symbols*levels/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_n} symbols of the same workload, bits + C + rank/select, single thread, "
-                      f"{dt:.1f} s"}
+            "sample": f"first {sample_n} symbols of the same workload, bits + C + rank/select, single thread "
+                      f"(1 of {avail} cores), median of {reps} runs: "
+                      + ", ".join(f"{x:.2f}" for x in times) + " s",
+            "cpu_model": model, "nproc": avail, "cpus_online": online, "median_of": reps}
+
+
+PROBE = os.path.join(ROOT, "paper_1407_8142_amd", "bw_probe")
+
+
+def copy_probe():
+    """Achievable streaming rates from the bw_probe executable (a child
+    process): grid-stride copy, one 16 KiB tile per block (the level pass's
+    pattern) and read-only tiles, in GB/s; None when the probe is missing."""
+    import subprocess
+    if not os.path.exists(PROBE):
+        return None
+    try:
+        out = subprocess.run([PROBE, "1024", "20"], capture_output=True, text=True, timeout=120, check=True).stdout
+    except (subprocess.SubprocessError, OSError):
+        return None
+    res = {}
+    for line in out.splitlines():
+        if line.startswith("{"):
+            d = json.loads(line)
+            res[d["probe"]] = d["GBps"]
+    return res or None
+
+
+def model_bytes(n: int, L: int, b: int) -> float:
+    """The levelWT model's algorithmic bytes of one build (one level per
+    pass): the histogram read of S, every level's read of its sequence
+    (b bytes a symbol) and write of the next (not at the last level), its
+    bits, rank entries (1/64 byte a symbol) and select samples left out."""
+    return n * b + L * n * (b + 1 / 8) + (L - 1) * n * b + L * n * (1 / 8 + 1 / 64)
+
+
+def physical_bytes(n: int, L: int, b: int, mid: int) -> float:
+    """The bytes the build actually moves with narrowed levels: the sequence
+    pass before level 0, then level passes at the narrowed width mid."""
+    return n * b + sum(level_pass_bytes(n, L, b, mid, L))
+
+
+def alphabet_leg(workload: str, steps: int, warmup: int):
+    """A large-alphabet workload (n = 2^27 32-bit symbols) built as the tree:
+    ms per build, sym*lvl/s, and the HBM rate of the model's bytes and of
+    the bytes moved at the narrowed widths."""
+    import torch
+
+    from paper_1407_8142_amd import inputs, wt
+
+    desc, n = WORKLOADS[workload]
+    log(f"[{workload}] generating n={n}")
+    S, sigma = inputs.workload(workload, n)
+    L = wt.plan(n, sigma, 4).L
+    mid = 1 if L <= 8 else (2 if L <= 16 else 4)
+    d = wt.to_device(S)
+    del S
+    t = wt.WaveletTree.allocate(n, sigma, 4, True, d.device)
+    for _ in range(warmup):
+        t.build_from(d)
+    torch.cuda.synchronize()
+    if t.status() != wt.WT_OK:
+        raise SystemExit(f"{workload}: input rejected")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        t.build_from(d)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bm, bp = model_bytes(n, L, 4), physical_bytes(n, L, 4, mid)
+    res = {"config": {"workload": desc, "n": n, "sigma": sigma, "levels": L, "sym_bytes": 4,
+                      "level_width_bytes": mid, "histogram": wt.histogram_path(n, sigma, 4)},
+           "value": n * L / (ms / 1e3), "unit": "symbols*levels/s", "ms_per_step": ms, "steps": steps,
+           "model_bytes": bm, "model_GBps": bm / (ms / 1e3) / 1e9,
+           "model_frac_of_hbm_peak": bm / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "physical_bytes": bp, "physical_GBps": bp / (ms / 1e3) / 1e9,
+           "physical_frac_of_hbm_peak": bp / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[{workload}] {ms:.3f} ms/step, {res['value']:.3e} sym*lvl/s, model {res['model_GBps']:.0f} GB/s, "
+        f"physical {res['physical_GBps']:.0f} GB/s")
+    del t, d
+    torch.cuda.empty_cache()
+    return res
 
 
 def batch_model_bytes(jobs) -> float:
@@ -287,39 +402,57 @@ def batch_leg(count: int, steps: int):
     }
 
 
-def serve_leg(seconds: float, budget_gb: float):
-    """Serving loop on a Poisson trace (payloads staged in HBM first)."""
+def serve_leg(seconds: float, budget_gb: float, pool: int, h2d_seconds: float, h2d_pool: int):
+    """Serving loop on a Poisson trace.  Payloads come from a pool of
+    distinct requests (request i carries payload i % pool) staged in HBM
+    before the trace; a second, shorter trace takes them from pinned host
+    memory instead, so the host-to-device copy is part of every latency."""
     import torch
 
     from paper_1407_8142_amd import inputs, serve
 
-    def one(sec, index, max_requests=None):
-        reqs, qtimes = inputs.serving_arrivals(sec, index=index, max_requests=max_requests)
-        log(f"[serve] staging {len(reqs)} requests ({sum(r.n for r in reqs) / 1e9:.2f} G symbols), "
-            f"{len(qtimes)} query batches")
-        slab, layout, views = inputs.stage_requests(reqs)
+    def one(sec, index, pool_size, h2d=False, max_requests=None):
+        reqs, qtimes = inputs.serving_arrivals(sec, index=index, max_requests=max_requests, pool=pool_size)
+        P = min(pool_size, len(reqs))
+        log(f"[serve] {len(reqs)} requests over a pool of {P} payloads "
+            f"({sum(r.n for r in reqs[:P]) / 1e9:.2f} G symbols staged), {len(qtimes)} query batches"
+            + (", payloads in pinned host memory" if h2d else ""))
+        slab, layout0, views0 = inputs.stage_requests(reqs[:P])
+        host = None
+        if h2d:
+            host, hviews = inputs.stage_pinned(slab, reqs[:P], layout0)
+            payloads = [hviews[i % P] for i in range(len(reqs))]
+        else:
+            payloads = [views0[i % P] for i in range(len(reqs))]
+        layout = [layout0[i % P] for i in range(len(reqs))]
         torch.cuda.synchronize()
         srv = serve.Server(budget_bytes=int(budget_gb * 2**30))
         t0 = time.perf_counter()
-        stats = serve.run_trace(srv, reqs, views, qtimes, slab, layout, qsize=100_000, seed=index)
+        stats = serve.run_trace(srv, reqs, payloads, qtimes, slab, layout, qsize=100_000, seed=index)
         elapsed = time.perf_counter() - t0
         out = serve.summary(stats, elapsed)
         out["requests"] = len(reqs)
+        out["payload_pool"] = P
         out["offered_symbols_levels"] = sum(r.n * (0 if r.sigma == 1 else (r.sigma - 1).bit_length()) for r in reqs)
-        del srv, slab, views
+        out["budget_gb"] = budget_gb
+        out["streams"] = {"single_builds": len(srv.streams), "batched_builds": 1, "queries": 1}
+        log(f"[serve] {out['builds']} builds in {elapsed:.2f} s, {out['evictions']} evictions, build p50/p99 "
+            f"{out['build_latency_ms']['p50']}/{out['build_latency_ms']['p99']} ms, query batch p50/p99 "
+            f"{out['query_batch_latency_ms']['p50']}/{out['query_batch_latency_ms']['p99']} ms")
+        del srv, slab, views0, payloads, host
         torch.cuda.empty_cache()
         return out
 
-    one(0.05, 1, max_requests=60)  # warm-up: kernel loading, allocator growth
-    res = one(seconds, 0)
-    log(f"[serve] {res['builds']} builds in {res['elapsed_s']:.2f} s, build p50/p99 "
-        f"{res['build_latency_ms']['p50']}/{res['build_latency_ms']['p99']} ms, query batch p50/p99 "
-        f"{res['query_batch_latency_ms']['p50']}/{res['query_batch_latency_ms']['p99']} ms")
+    one(0.05, 1, 60, max_requests=60)  # warm-up: kernel loading, allocator growth
+    res = one(seconds, 0, pool)
+    res["h2d_included"] = one(h2d_seconds, 2, h2d_pool, h2d=True)
     res["config"] = {"workload": "serving: Poisson build requests at 2000/s, n log-uniform in [2^12, 2^26], sigma "
                                  "log-uniform in [2^2, 2^20], Zipf(1.1) symbols permuted; Poisson query batches at "
                                  "100/s of 10^5 queries (half access, half rank with c = S[j]) over the resident "
                                  f"trees; {budget_gb:g} GB resident budget, LRU eviction",
-                     "trace_seconds": seconds, "h2d": "excluded: payloads staged in HBM before their arrival"}
+                     "trace_seconds": seconds, "h2d": "excluded: payloads staged in HBM before their arrival "
+                                                      "(the h2d_included object copies them from pinned host "
+                                                      "memory after admission)"}
     return res
 
 
@@ -339,9 +472,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-alphabets", action="store_true",
+                    help="skip the large-alphabet builds (n = 2^27 32-bit symbols, sigma 2^16 and 2^20)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
-    ap.add_argument("--serve-seconds", type=float, default=0.5)
-    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-pool", type=int, default=1000, help="distinct payloads the trace cycles over")
+    ap.add_argument("--serve-h2d-seconds", type=float, default=1.5)
+    ap.add_argument("--serve-h2d-pool", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -408,23 +546,38 @@ def main():
     mid = 1 if L <= 8 else (2 if L <= 16 else 4)
     passes = len(launches) // args.steps
     assert passes * args.steps == len(launches) and passes in (L, (L + 1) // 2), (len(launches), L, args.steps)
-    per_pass = level_pass_bytes(n, L, S.dtype.itemsize, mid, passes)
-    lp_ms = sum(launches)
-    lp_bytes = sum(per_pass) * args.steps
-    avg_launch_ms = lp_ms / len(launches)
-    avg_bytes = lp_bytes / len(launches)
-    achieved = avg_bytes / (avg_launch_ms / 1e3) / 1e9
+    # Byte alphabets without a histogram pass: level L-2 writes the last
+    # level's bits, and the last launch is a directory pass over them.
+    lastbits = passes == L and L >= 2 and wt.histogram_path(n, sigma, S.dtype.itemsize) == wt.HIST_LEVELS
+    per_pass = level_pass_bytes(n, L, S.dtype.itemsize, mid, passes, lastbits)
     per_pass_ms = [sum(launches[i::passes]) / args.steps for i in range(passes)]
+    # The dominant kernel: the level passes (the last level's directory
+    # pass, when there is one, is a different and much lighter kernel).
+    npass = passes - 1 if lastbits else passes
+    lp_ms = sum(per_pass_ms[:npass]) * args.steps
+    lp_bytes = sum(per_pass[:npass]) * args.steps
+    avg_launch_ms = lp_ms / (npass * args.steps)
+    avg_bytes = lp_bytes / (npass * args.steps)
+    achieved = avg_bytes / (avg_launch_ms / 1e3) / 1e9
     log(f"[bench] {'levels per pass: 1' if passes == L else 'levels per pass: 2'}; ms per pass: "
         + " ".join(f"{x:.4f}" for x in per_pass_ms))
     traffic = traffic_per_launch(args.workload if n == n_default else "")
+    probe = copy_probe()
+    step_bytes = model_bytes(n, L, S.dtype.itemsize)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "level_pass (all levels)" if passes == L else
+            "achievable": probe, "frac_of_tile_copy": round(achieved / probe["copy_tile"], 4) if probe else None,
+            "step_model_bytes": step_bytes,
+            "step_frac": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel": ("level_pass (levels 0..L-2; level L-2 also writes the last level's bits)" if lastbits
+                       else "level_pass (all levels)") if passes == L else
                       "pair_pass (two levels per launch; an odd last level by level_pass)",
             "passes_per_build": passes, "avg_launch_ms": round(avg_launch_ms, 5),
             "algorithmic_bytes_per_launch": round(avg_bytes), "level_pass_share_of_step":
                 round(lp_ms / args.steps / ms_per_step_timed, 3),
+            "ms_per_launch": [round(x, 5) for x in per_pass_ms],
+            "last_level": ({"kernel": "level_dirs (directories over the last level's bits)",
+                            "ms": round(per_pass_ms[-1], 5), "bytes": per_pass[-1]} if lastbits else None),
             "launch_timing": "K steps before the timed ones, each level-pass launch carrying its start and "
                              f"stop events in its dispatch ({ms_per_step_timed:.3f} ms/step there)"}
 
@@ -441,8 +594,12 @@ def main():
         d_seq, n, sigma, L, args.steps, ms_per_step)
     sortwt = None if args.no_matrix or S.dtype.itemsize != 1 or sigma > 256 else sort_leg(
         d_seq, n, sigma, L, args.steps, ms_per_step)
+    alphabets = None
+    if not args.no_alphabets and args.workload == "text256":
+        alphabets = {w: alphabet_leg(w, 10, 10) for w in ("alpha16", "alpha20")}
     batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
-    served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb)
+    served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb, args.serve_pool,
+                                                  args.serve_h2d_seconds, args.serve_h2d_pool)
 
     line = {
         "metric": METRIC, "value": value, "unit": "symbols*levels/s", "n_gpus": 1, "steps": args.steps,
@@ -457,6 +614,7 @@ def main():
         "multiary": multiary,
         "huffman": huffman,
         "sort": sortwt,
+        "alphabets": alphabets,
         "batch": batch,
         "serve": served,
     }

@@ -1163,12 +1163,13 @@ static int run_stats(const void *d_seq, const Plan &p, const wt_outputs *out, un
     const uint32_t Tl = (uint32_t)cdiv(n, 16384);
     // Level 0's pieces are its tiles; everything after them is cleared.
     const uint64_t nclear = p.PS * p.L - Tl;
+    const unsigned pg = (unsigned)cdiv(Tl, kPrepWaves), pb = kPrepWaves * kWave;
     if (p.sigma < 256)
-        stats_prep_u8<true><<<Tl, kBlock, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1, (uint32_t)p.sigma,
-                                                  pz, pz + Tl, nclear);
+        stats_prep_u8<true><<<pg, pb, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1, (uint32_t)p.sigma, pz,
+                                              pz + Tl, nclear);
     else
-        stats_prep_u8<false><<<Tl, kBlock, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1,
-                                                   (uint32_t)p.sigma, pz, pz + Tl, nclear);
+        stats_prep_u8<false><<<pg, pb, 0, s>>>((const uint8_t *)d_seq, (uint32_t)n, p.L - 1, (uint32_t)p.sigma,
+                                               pz, pz + Tl, nclear);
     const void *cur = d_seq;
     int rc;
     for (uint32_t l = 0; l < p.L; ++l) {

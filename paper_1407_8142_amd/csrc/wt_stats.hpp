@@ -41,45 +41,51 @@ __host__ __device__ inline uint64_t piece_stride(uint64_t T, uint32_t L) {
 }
 
 // ---------------------------------------------------------------------------
-// One block per level-0 tile (the level pass's 16 KiB tiles and layout):
-// cnt0[tile] = zeros of bit k in the tile, with kBadTile set when CHECK
-// (sigma < 256) finds a byte >= sigma.  The blocks also clear [0, nclear)
-// of `clear`, counters that the level passes accumulate into.
+// One wave per level-0 tile of 16 KiB (kPrepWaves tiles per block, no
+// barrier): sixteen 16-byte loads per lane in flight, cnt0[tile] = zeros of
+// bit k in the tile, with kBadTile set when CHECK (sigma < 256) finds a
+// byte >= sigma.  The threads also clear [0, nclear) of `clear`, counters
+// that the level passes accumulate into.
+constexpr int kPrepWaves = 4;
+
 template <bool CHECK>
-__global__ __launch_bounds__(kBlock) void stats_prep_u8(const uint8_t *__restrict__ S, uint32_t n, uint32_t k,
-                                                        uint32_t sigma, uint32_t *cnt0, uint32_t *clear,
-                                                        uint64_t nclear) {
-    __shared__ uint32_t red[kWaves];
-    constexpr int kRows = 4, kRowBytes = 4096;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    const uint32_t tile = blockIdx.x, t0 = tile * 16384u;
+__global__ __launch_bounds__(kPrepWaves * kWave) void stats_prep_u8(const uint8_t *__restrict__ S, uint32_t n,
+                                                                    uint32_t k, uint32_t sigma, uint32_t *cnt0,
+                                                                    uint32_t *clear, uint64_t nclear) {
+    constexpr int kLoads = 16384 / 16 / kWave;  // 16
+    const int lane = lane_id();
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Counters for the level passes (nothing reads them before this kernel ends).
+    for (uint64_t i = gtid; i < nclear; i += (uint64_t)gridDim.x * blockDim.x) clear[i] = 0;
+    const uint32_t tile = blockIdx.x * kPrepWaves + threadIdx.x / kWave;
+    const uint32_t ntiles = (n + 16383u) / 16384u;
+    if (tile >= ntiles) return;
+    const uint32_t t0 = tile * 16384u;
     const uint32_t len = min(16384u, n - t0);
-    const uint8_t *in = S + t0;
-    uint4 d[kRows];
+    const uint4 *in = reinterpret_cast<const uint4 *>(S + t0) + lane;
+    uint4 d[kLoads];
     if (len == 16384u) {
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) d[r] = *reinterpret_cast<const uint4 *>(in + r * kRowBytes + 16 * tid);
+        for (int r = 0; r < kLoads; ++r) d[r] = in[r * kWave];
     } else {
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t p = (uint32_t)(r * kRowBytes + 16 * tid);
+        for (int r = 0; r < kLoads; ++r) {
+            const uint32_t p = (uint32_t)(r * kWave + lane) * 16u;
             if (p + 16 <= len) {
-                d[r] = *reinterpret_cast<const uint4 *>(in + p);
+                d[r] = in[r * kWave];
             } else {
                 const uint32_t nv = clamp_count(len, p, 16u);
                 uint32_t w[4] = {0, 0, 0, 0};  // past the end: byte 0, no one and no bad symbol
-                for (uint32_t j = 0; j < nv; ++j) w[j >> 2] |= (uint32_t)in[p + j] << (8 * (j & 3));
+                for (uint32_t j = 0; j < nv; ++j) w[j >> 2] |= (uint32_t)S[t0 + p + j] << (8 * (j & 3));
                 d[r] = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
     }
-    // Counters for the level passes (nothing reads them before this kernel ends).
-    for (uint64_t i = (uint64_t)tile * kBlock + tid; i < nclear; i += (uint64_t)gridDim.x * kBlock) clear[i] = 0;
     const uint32_t M = 0x01010101u << k;
     uint32_t ones = 0;
     uint32_t hi = 0;  // largest byte seen (CHECK)
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) {
+    for (int r = 0; r < kLoads; ++r) {
         const uint32_t w[4] = {d[r].x, d[r].y, d[r].z, d[r].w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -88,16 +94,9 @@ __global__ __launch_bounds__(kBlock) void stats_prep_u8(const uint8_t *__restric
                 hi = max(hi, max(max(w[j] & 0xFFu, (w[j] >> 8) & 0xFFu), max((w[j] >> 16) & 0xFFu, w[j] >> 24)));
         }
     }
-    const bool bad = __syncthreads_or(CHECK && hi >= sigma);
-    const uint32_t wsum = (uint32_t)wave_sum_u64(ones);
-    if (lane == 0) red[wave] = wsum;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t t = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) t += red[w];
-        cnt0[tile] = (len - t) | (bad ? kBadTile : 0u);
-    }
+    const bool bad = __ballot(CHECK && hi >= sigma) != 0;
+    const uint32_t t = wave_sum_u32(ones);
+    if (lane == 0) cnt0[tile] = (len - t) | (bad ? kBadTile : 0u);
 }
 
 // ---------------------------------------------------------------------------

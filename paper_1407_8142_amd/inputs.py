@@ -172,15 +172,22 @@ class TraceRequest:
 
 
 def serving_arrivals(seconds: float, rate: float = 2000.0, qrate: float = 100.0, n_exp=(12.0, 26.0),
-                     sigma_exp=(2.0, 20.0), index: int = 0, max_requests: int | None = None):
+                     sigma_exp=(2.0, 20.0), index: int = 0, max_requests: int | None = None,
+                     pool: int | None = None):
     """Poisson build arrivals (mean rate/s) with n = floor(2^U(n_exp)) and
-    sigma = floor(2^U(sigma_exp)), and Poisson query-batch arrivals."""
+    sigma = floor(2^U(sigma_exp)), and Poisson query-batch arrivals.  With
+    `pool`, request i carries the payload of request i % pool (the first
+    `pool` draws: the same size distribution, payloads staged once)."""
     rng = rng_for(5, index)
     reqs, t = [], 0.0
     while True:
         t += float(rng.exponential(1.0 / rate))
         if t > seconds or (max_requests is not None and len(reqs) >= max_requests):
             break
+        if pool is not None and len(reqs) >= pool:
+            src = reqs[len(reqs) % pool]
+            reqs.append(TraceRequest(t, src.n, src.sigma, src.seed))
+            continue
         n = int(np.floor(2.0 ** rng.uniform(*n_exp)))
         sigma = max(2, int(np.floor(2.0 ** rng.uniform(*sigma_exp))))
         reqs.append(TraceRequest(t, n, sigma, int(rng.integers(0, 2**62))))
@@ -217,6 +224,15 @@ def zipf_device(n: int, sigma: int, s: float, seed: int, out, device="cuda"):
             out[o:o + m] = v.to(torch.int32).view(torch.int16)[::2].view(out.dtype)
         else:
             out[o:o + m] = v.to(torch.int32).view(out.dtype)
+
+
+def stage_pinned(slab, reqs, layout):
+    """A pinned host copy of a staged slab and per-request host views."""
+    import torch
+    host = torch.empty(slab.numel(), dtype=torch.uint8, pin_memory=True)
+    host.copy_(slab)
+    dt = {1: torch.uint8, 2: torch.int16, 4: torch.int32}
+    return host, [host[o:o + r.n * w].view(dt[w]) for r, (o, w) in zip(reqs, layout)]
 
 
 def stage_requests(reqs, s: float = 1.1, device="cuda"):

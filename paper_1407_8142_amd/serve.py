@@ -16,8 +16,14 @@ runs in the library's kernels):
               pinned (not evicted) until its single wt_query_multi launch
               completes
 Latency is arrival -> completion as seen by the host loop (polling HIP
-events); inputs are in HBM before their arrival time (staged by the
-client), so host-to-device transfer is not part of it.
+events).  A request's payload is either a device tensor (staged in HBM by
+the client before its arrival: no host-to-device transfer in the latency)
+or a pinned host tensor, copied to the device on the build's stream after
+admission (the transfer is part of the latency and of the footprint).
+
+Streams: two for single builds, one for batched builds, one for query
+batches (the device's four hardware queues), plus a copy-only stream for
+the batches' job tables and one for status reads.
 """
 from __future__ import annotations
 
@@ -34,7 +40,7 @@ from . import wt
 @dataclass
 class BuildRequest:
     rid: int
-    seq: torch.Tensor  # device symbols (1-, 2- or 4-byte), 16-byte aligned
+    seq: torch.Tensor  # symbols (1-, 2- or 4-byte): a device tensor, 16-byte aligned, or a pinned host tensor
     sigma: int
     arrival: float     # seconds on the server clock
 
@@ -68,7 +74,8 @@ class _InflightBuild:
     owner: object
     batch: "wt.Batch | None" = None
     status_host: torch.Tensor | None = None
-    scratch_bytes: int = 0
+    scratch_bytes: int = 0   # build scratch and device copies of host payloads, freed when it completes
+    payloads: list = field(default_factory=list)
 
 
 @dataclass
@@ -89,15 +96,17 @@ def _levels(sigma: int) -> int:
 
 
 class _Slab:
-    """Reference count of trees living in one allocation (a batch slab)."""
+    """The trees of one batched build share one allocation: it stays
+    charged to the budget, whole, until its last tree is gone."""
 
-    def __init__(self, tensors):
+    def __init__(self, tensors, nbytes: int, members: int):
         self.tensors = tensors
-        self.live = 0
+        self.nbytes = nbytes
+        self.live = members
 
 
 class Server:
-    def __init__(self, budget_bytes: int, build_streams: int = 4, small_n: int = 1 << 20, small_sigma: int = 1 << 14,
+    def __init__(self, budget_bytes: int, build_streams: int = 2, small_n: int = 1 << 20, small_sigma: int = 1 << 14,
                  max_batch: int = 1024, tune: "wt.Tune | None" = None, clock=time.perf_counter):
         self.budget = int(budget_bytes)
         self.small_n, self.small_sigma, self.max_batch = small_n, small_sigma, max_batch
@@ -162,6 +171,17 @@ class Server:
             out += 8 * (-(-w // 32) * 32)
         return out, int(lay.scratch_bytes)
 
+    def _release(self, owner, nbytes: int):
+        """A tree is gone: its own bytes, or its slab's once the slab's last
+        tree is gone."""
+        if isinstance(owner, _Slab):
+            owner.live -= 1
+            if owner.live == 0:
+                owner.tensors = None
+                self.in_use -= owner.nbytes
+        else:
+            self.in_use -= nbytes
+
     def _evict_for(self, need: int) -> bool:
         for rid in list(self.resident.keys()):
             if self.in_use + need <= self.budget:
@@ -170,12 +190,8 @@ class Server:
             if r.pins:
                 continue
             del self.resident[rid]
-            self.in_use -= r.nbytes
+            self._release(r.owner, r.nbytes)
             self.stats.evictions += 1
-            if isinstance(r.owner, _Slab):
-                r.owner.live -= 1
-                if r.owner.live == 0:
-                    r.owner.tensors = None
         return self.in_use + need <= self.budget
 
     # -- scheduler -----------------------------------------------------------
@@ -185,6 +201,8 @@ class Server:
             req = self.pending[0]
             n, sb = req.seq.numel(), req.seq.element_size()
             out_b, scr_b = self.footprint(n, req.sigma, sb)
+            if not req.seq.is_cuda:
+                scr_b += -(-(n * sb) // 256) * 256  # the device copy of the payload
             need = out_b + scr_b
             if need > self.budget:
                 self.pending.popleft()
@@ -200,35 +218,52 @@ class Server:
                 large.append((req, out_b, scr_b))
         return small, large
 
+    @staticmethod
+    def _on_device(seq: torch.Tensor, stream) -> torch.Tensor:
+        """The payload on the device: itself, or its copy made on `stream`."""
+        if seq.is_cuda:
+            return seq
+        with torch.cuda.stream(stream):
+            return seq.to("cuda", non_blocking=True)
+
     def _launch_large(self, req, out_b, scr_b):
         s = self.streams[self._next_stream]
         self._next_stream = (self._next_stream + 1) % len(self.streams)
         n, sb = req.seq.numel(), req.seq.element_size()
+        seq = self._on_device(req.seq, s)
         with torch.cuda.stream(s):
-            t = wt.WaveletTree.allocate(n, req.sigma, sb, True, req.seq.device)
-            t.build_from(req.seq, stream=s)
+            t = wt.WaveletTree.allocate(n, req.sigma, sb, True, seq.device)
+            t.build_from(seq, stream=s)
             st = torch.empty(1, dtype=torch.int32, pin_memory=True)
             st.copy_(t.scratch[:4].view(torch.int32), non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(s)
-        self.inflight.append(_InflightBuild([req], ev, [t], [out_b], None, None, st, scr_b))
+        self.inflight.append(_InflightBuild([req], ev, [t], [out_b], None, None, st, scr_b, [seq]))
         self.stats.singles += 1
 
     def _launch_small(self, group):
         reqs = [g[0] for g in group]
         s = self.batch_stream
-        b = wt.Batch([r.seq for r in reqs], [r.sigma for r in reqs], stream=self.upload_stream)
+        # Host payloads are copied on the batch stream, ahead of the batch's
+        # launches there (its job tables, on the upload stream, hold only
+        # their addresses).
+        seqs = [self._on_device(r.seq, s) for r in reqs]
+        b = wt.Batch(seqs, [r.sigma for r in reqs], stream=self.upload_stream)
         with torch.cuda.stream(s):
             b.run(self.tune, stream=s)
         ev = torch.cuda.Event()
         ev.record(s)
-        scr = int(b.layout.scratch_bytes)
-        # Outputs of the whole group share one slab; the group's scratch
-        # estimate is replaced by the batch's own.
+        # Outputs of the whole group share one slab (charged whole until its
+        # last tree goes); the group's scratch estimate is replaced by the
+        # batch's own scratch plus its payload copies.
+        copies = sum(-(-(q.numel() * q.element_size()) // 256) * 256 for r, q in zip(reqs, seqs)
+                     if not r.seq.is_cuda)
+        scr = int(b.layout.scratch_bytes) + copies
         est_scr = sum(g[2] for g in group)
         self.in_use += scr - est_scr
-        self.inflight.append(_InflightBuild(reqs, ev, b.trees, [g[1] for g in group], _Slab([b.slab]), b, None,
-                                            scr))
+        est_out = sum(g[1] for g in group)
+        self.inflight.append(_InflightBuild(reqs, ev, b.trees, [g[1] for g in group],
+                                            _Slab([b.slab], est_out, len(reqs)), b, None, scr, seqs))
         self.stats.batches += 1
 
     def _retire(self) -> bool:
@@ -245,16 +280,14 @@ class Server:
                 f.batch.scratch = None
             else:
                 codes = [wt.WT_OK if int(f.status_host[0]) == 0 else wt.WT_ERR_SYMBOL]
-                f.trees[0].scratch = f.trees[0].scratch[:0]
+                # drop the scratch (a slice would keep its storage alive)
+                f.trees[0].scratch = torch.empty(0, dtype=torch.uint8, device=f.trees[0].scratch.device)
             self.in_use -= f.scratch_bytes
-            if isinstance(f.owner, _Slab):
-                f.owner.live = len(f.reqs)
+            f.payloads = []
             for req, t, nb, code in zip(f.reqs, f.trees, f.nbytes, codes):
                 if code != wt.WT_OK:
                     self.stats.failed.append((req.rid, wt.STATUS_NAMES.get(code, code)))
-                    self.in_use -= nb
-                    if isinstance(f.owner, _Slab):
-                        f.owner.live -= 1
+                    self._release(f.owner, nb)
                     continue
                 sl = t.n * t.L
                 self.resident[req.rid] = _Resident(t, nb, f.owner, 0, sl)

@@ -24,11 +24,14 @@ def mods():
     return wt, serve
 
 
-def test_serving_mix_equals_alone(mods, oracle_mod):
+@pytest.mark.parametrize("h2d", [False, True], ids=["staged", "h2d"])
+def test_serving_mix_equals_alone(mods, oracle_mod, h2d):
+    """h2d: payloads in pinned host memory, copied after admission."""
     wt, serve = mods
     reqs, qtimes = inputs.serving_arrivals(0.05, rate=2000.0, qrate=120.0, n_exp=(10.0, 17.0), sigma_exp=(2.0, 20.0),
                                            index=7, max_requests=80)
     slab, layout, views = inputs.stage_requests(reqs)
+    payloads = inputs.stage_pinned(slab, reqs, layout)[1] if h2d else views
     torch.cuda.synchronize()
     total = sum(sum(serve.Server.footprint(r.n, r.sigma, layout[i][1])) for i, r in enumerate(reqs))
     srv = serve.Server(budget_bytes=max(total // 3, 1 << 26), build_streams=3, small_n=1 << 14,
@@ -42,7 +45,7 @@ def test_serving_mix_equals_alone(mods, oracle_mod):
         orig(qb)
 
     srv.submit_queries = capture
-    stats = serve.run_trace(srv, reqs, views, qtimes, slab, layout, qsize=3000, seed=3, select_share=0.3)
+    stats = serve.run_trace(srv, reqs, payloads, qtimes, slab, layout, qsize=3000, seed=3, select_share=0.3)
     torch.cuda.synchronize()
     print(f"[serve] built {stats.built} of {len(reqs)}, batches {stats.batches}, singles {stats.singles}, "
           f"evictions {stats.evictions}, query batches {len(stats.query_latency)}", flush=True)
@@ -81,3 +84,28 @@ def test_serving_mix_equals_alone(mods, oracle_mod):
                 pos = np.flatnonzero(S == a[q])
                 want = int(pos[b[q] - 1]) if 1 <= b[q] <= pos.size else -1
             assert got[q] == want, (qid, q, int(kind[q]), int(a[q]), int(b[q]), int(got[q]), want)
+
+
+def test_serving_budget_holds_under_eviction(mods):
+    """Device memory held by the server (resident trees, batch slabs, builds
+    in flight) stays within its budget while it evicts: a batch slab stays
+    charged whole until its last tree is evicted."""
+    wt, serve = mods
+    reqs, qtimes = inputs.serving_arrivals(0.08, rate=2000.0, qrate=100.0, n_exp=(10.0, 18.0),
+                                           sigma_exp=(2.0, 16.0), index=11, max_requests=150)
+    slab, layout, views = inputs.stage_requests(reqs)
+    torch.cuda.synchronize()
+    outputs = sum(serve.Server.footprint(r.n, r.sigma, layout[i][1])[0] for i, r in enumerate(reqs))
+    budget = outputs // 4  # a quarter of the trees fit: the server must evict
+    srv = serve.Server(budget_bytes=budget, small_n=1 << 15, small_sigma=1 << 12)
+    torch.cuda.empty_cache()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    stats = serve.run_trace(srv, reqs, views, qtimes, slab, layout, qsize=2000, seed=5)
+    torch.cuda.synchronize()
+    peak = torch.cuda.max_memory_allocated() - base
+    print(f"[serve] budget {budget >> 20} MiB, peak {peak >> 20} MiB, evictions {stats.evictions}, "
+          f"batches {stats.batches}", flush=True)
+    assert stats.failed == [] and stats.evictions > 0 and stats.batches > 0
+    assert srv.in_use <= budget
+    assert peak <= budget + (8 << 20), (peak, budget)
