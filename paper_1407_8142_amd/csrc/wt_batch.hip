@@ -118,7 +118,8 @@ struct LdsHistB {
 
 struct LdsPrep {
     BlockScanTmp scan;
-    unsigned long long nmax[32];
+    unsigned long long nmax[32];  // wave maxima of a level's node sizes
+    uint64_t lmax[32];            // every level's largest node
 };
 
 // Whole-job histogram: two 16-bit counters per word.
@@ -362,12 +363,11 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
         __syncthreads();  // the block reads C back below (workgroup scope)
     }
     if (j.L == 0) return;
-    const TableOp top{j.C, j.D, j.sigma, j.L};
+    // Node tables level by level, with each level's largest node (the
+    // fusion plan's input).
     for (uint32_t l = 0; l < j.L; ++l) {
-        const uint64_t g0 = 1ull << l;
-        block_scan_all<N>(
-            g0, tmp, [&](uint64_t i) -> uint64_t { return top.value(g0 + i); },
-            [&](uint64_t i, uint64_t ex) { top.store(g0 + i, ex); });
+        const uint64_t m = table_level_block<N>(j.C, j.sigma, j.L, l, j.D, tmp, lp.nmax);
+        if (threadIdx.x == 0) lp.lmax[l] = m;
     }
     __syncthreads();
     for (uint32_t l = 0; l < j.L; ++l)
@@ -375,13 +375,7 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
                  threadIdx.x, kBlock);
     tile_prefix_block(j.cnt, j.pre, j.T0, tmp);
     uint32_t l0 = j.L;
-    if (fuse && j.L >= 2 && j.n > 0) {
-        if (threadIdx.x < 32) lp.nmax[threadIdx.x] = 0;
-        __syncthreads();
-        node_max_range(j.C, j.sigma, j.L, 1, 1ull << j.L, kBlock, lp.nmax, nullptr);
-        __syncthreads();
-        l0 = fused_from(reinterpret_cast<const uint64_t *>(lp.nmax), j.L, fused_half(j.mid_bytes));
-    }
+    if (fuse && j.L >= 2 && j.n > 0) l0 = fused_from(lp.lmax, j.L, fused_half(j.mid_bytes));
     if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
 }
 

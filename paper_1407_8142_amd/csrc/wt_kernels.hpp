@@ -328,6 +328,61 @@ struct TableOp {
     }
 };
 
+// Level l's node table (the values TableOp gives) for one job by one block,
+// and the level's largest node.  Each node's C values are loaded once, a
+// whole round's loads issued before any is used (the loads are the latency
+// of this loop, not the arithmetic).  Returns the largest node in every
+// thread.
+template <int N>
+__device__ __forceinline__ uint64_t table_level_block(const uint64_t *C, uint64_t sigma, uint32_t L, uint32_t l,
+                                                      uint64_t *D, BlockScanTmp &tmp, unsigned long long *red) {
+    const uint32_t k = L - 1 - l;
+    const uint64_t P = 1ull << l;
+    uint64_t *Dl = D + (2ull << l) - 2;  // D_l[2p] = ones before node p, D_l[2p+1] = zeros before node p+1
+    auto Cc = [&](uint64_t x) { return C[x < sigma ? x : sigma]; };
+    uint64_t carry = 0, big = 0;
+    for (uint64_t c0 = 0; c0 < P; c0 += (uint64_t)kBlock * N) {
+        const uint64_t base = c0 + (uint64_t)threadIdx.x * N;
+        uint64_t ce[N], cm[N], v[N];
+        const uint64_t cs = base < P ? Cc(base << (k + 1)) : 0;  // start of the thread's first node
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const uint64_t p = base + j < P ? base + j : P - 1;
+            ce[j] = Cc((p + 1) << (k + 1));
+            cm[j] = Cc((2 * p + 1) << k);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            v[j] = base + j < P ? ce[j] - cm[j] : 0;  // ones of node p
+            const uint64_t start = j == 0 ? cs : ce[j - 1];
+            if (base + j < P) big = max(big, ce[j] - start);
+        }
+        uint64_t ones[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) ones[j] = v[j];
+        uint64_t total;
+        block_excl_scan<N>(v, tmp, total);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            if (base + j >= P) continue;
+            const uint64_t p = base + j, ex = carry + v[j];
+            Dl[2 * p] = ex;
+            Dl[2 * p + 1] = ce[j] - (ex + ones[j]);
+        }
+        carry += total;
+    }
+    // largest node: wave maxima, then the block's
+    for (int d = kWave / 2; d >= 1; d >>= 1) big = max(big, (uint64_t)__shfl_xor(big, d, kWave));
+    __syncthreads();
+    if (lane_id() == 0) red[threadIdx.x / kWave] = big;
+    __syncthreads();
+    uint64_t m = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) m = max(m, (uint64_t)red[w]);
+    __syncthreads();
+    return m;
+}
+
 // Directory tail of level l: rank[last] = ones of the level, the sample
 // counts, and the sample entries at or past the counts set to n.  Thread t
 // of `nthreads` handles sample entries t, t + nthreads, ...
