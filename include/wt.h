@@ -404,6 +404,7 @@ typedef struct {
     uint64_t scratch_bytes;   /* device scratch of wt_batch_prepare / wt_batch_run (256-byte aligned) */
     uint64_t clear_bytes;     /* leading scratch bytes every run clears */
     uint64_t off_jobs, off_segs, off_seg_of; /* offsets of the tables wt_batch_prepare writes */
+    uint64_t off_list;        /* lists of live items that per-phase runs build on the device */
     uint32_t njobs;
     uint32_t nsegs;           /* queue segments: (job, phase) pairs with work */
     uint32_t items;           /* work items in the queue */

@@ -68,9 +68,11 @@ constexpr uint32_t kHasTileHist = 1, kHasJobHist = 2, kHasPrep = 4, kHasLevel8 =
                    kHasFused = 32, kHasAll = 63;
 constexpr uint32_t kHasLevel = kHasLevel8 | kHasLevelWide;
 
-// Waves per SIMD each kernel is compiled for (what its LDS lets reside).
+// Waves per SIMD each kernel is compiled for: the register budget that
+// keeps its code free of spills (the per-phase kernels inline several tile
+// variants, and the job records take many scalar registers).
 constexpr int waves_for(uint32_t kinds) {
-    return kinds == kHasJobHist ? 1 : ((kinds & kHasFused) != 0 ? 4 : 5);
+    return kinds == kHasPrep ? 2 : (kinds == kHasLevelWide ? 5 : 4);
 }
 
 // Control words of one job (cleared by every run): status, done counters
@@ -78,8 +80,9 @@ constexpr int waves_for(uint32_t kinds) {
 constexpr int kCtlWords = 64;
 constexpr int kCtlStatus = 0, kCtlDone = 1, kCtlReady = 32, kCtlCDone = 62, kCtlFusedL0 = 63;
 constexpr int kMaxLevels = 30;
-constexpr uint64_t kHeaderBytes = 256;  // queue heads [0, 32), abort flag [32]
+constexpr uint64_t kHeaderBytes = 512;  // queue heads [0, 32), abort flag [32], live counts [64, 128)
 constexpr int kAbortWord = 32;
+constexpr int kLiveWord = 64;  // entries of each phase's list (per-phase launches)
 
 struct JobDev {
     const void *seq;
@@ -91,6 +94,9 @@ struct JobDev {
     uint32_t *ctl, *symcnt, *cnt;
     uint64_t *pre, *D;
     void *S0, *S1;
+    uint32_t *segb;  // first position of every fused segment, and n (nseg + 1 entries)
+    uint32_t nseg;
+    uint32_t id;     // the job's index
 };
 
 struct Seg {
@@ -108,6 +114,15 @@ struct Args {
     uint32_t spin_limit;
     uint32_t fenced;         // items of one launch depend on each other's writes
     uint32_t fuse;           // run the tail levels of a job fused in LDS once its nodes fit
+    // Per-phase launches: every level and fused launch takes its items from
+    // a list of the live ones, (job, tile or segment), that the tables phase
+    // (level 0, fused segments) and the level set-up launches (level l >= 1)
+    // append to; the list of a phase sits in that phase's item range.
+    uint2 *list;
+    uint32_t *live;             // entries of each phase's list
+    uint32_t phase, level;      // this launch's phase, and its level (level launches)
+    uint32_t base0[2];          // list bases of level 0 (byte tiles, wider tiles)
+    uint32_t base_fused, phase_fused;
 };
 
 struct LdsHistB {
@@ -116,18 +131,29 @@ struct LdsHistB {
     uint32_t nused;
 };
 
+// Node tables by chunks of C: a chunk of 2^12 symbols holds every node of
+// the 12 deepest levels whole, so those levels' tables come from one read of
+// C (into LDS) per chunk.
+constexpr uint32_t kTabChunkLog = 12, kTabChunk = 1u << kTabChunkLog;
+constexpr uint32_t kTabPer = 16;  // chunk symbols per thread
+static_assert(kTabChunk == kTabPer * kBlock, "a chunk is 16 symbols per thread");
+
 struct LdsPrep {
     BlockScanTmp scan;
-    unsigned long long nmax[32];  // wave maxima of a level's node sizes
-    uint64_t lmax[32];            // every level's largest node
+    uint32_t at;                                 // first list entry the block reserved
+    unsigned long long nmax[32];                 // wave maxima of a level's node sizes
+    uint64_t lmax[32];                           // every level's largest node
+    uint32_t cl[kTabChunk + kTabChunk / 16 + 1]; // C over the chunk and the next chunk's first (padded)
+    uint32_t wtot[kWaves][5];                    // wave totals of the five scanned values
+    uint32_t xs[kBlock];                         // block prefix of the deep nodes' ones
+    uint32_t big[32];                            // largest node of each chunked level
 };
 
 // Whole-job histogram: two 16-bit counters per word.
 struct LdsJobHist {
     uint32_t bins[kJobHistMaxSigma / 2];
-    uint32_t red[kWaves];
+    uint32_t wtot[16];  // wave totals of the C scan (1024-thread blocks)
     uint32_t overflow;
-    BlockScanTmp scan;
 };
 
 // Level items: byte tiles and wider tiles run in launches of their own, each
@@ -261,22 +287,28 @@ __device__ __forceinline__ void hist_item(const JobDev &j, uint32_t tile, LdsHis
     }
 }
 
-// A whole job's histogram in one block (alphabets of up to 2^16 symbols
-// whose counters do not fit as LDS replicas): packed 16-bit counters in LDS,
-// so no global atomic is needed; the block then writes C itself.  A counter
+// A whole job's histogram in one block of 1024 threads (alphabets of up to
+// 2^16 symbols whose counters do not fit as LDS replicas; 16 waves cover the
+// latency of the LDS atomics): packed 16-bit counters in LDS, so no global
+// atomic is needed per symbol, and the block writes C itself.  A counter
 // that reaches 2^15 gives 2^15 to the job's global count of that symbol
 // (the thread whose add crossed the mark does it, so a half never carries
-// into its neighbour).  Also the per-tile zeros of the top bit.
+// into its neighbour).  Also the per-tile zeros of the top bit (one atomic
+// per wave into the cleared counts).
+constexpr int kJHThreads = 1024, kJHWaves = kJHThreads / kWave;
+constexpr int kJHTiles = 4;  // 16 KiB tiles in flight per group (one 16-byte vector per thread each)
+
 template <typename T>
-__device__ __forceinline__ void job_hist_big(const JobDev &j, LdsJobHist &s) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ void job_hist_block(const JobDev &j, LdsJobHist &s) {
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t nwords = (uint32_t)((j.sigma + 1) / 2);
-    for (uint32_t i = tid; i < nwords; i += kBlock) s.bins[i] = 0;
+    for (uint32_t i = tid; i < nwords; i += kJHThreads) s.bins[i] = 0;
     if (tid == 0) s.overflow = 0;
     __syncthreads();
     const T *S = reinterpret_cast<const T *>(j.seq);
     const uint32_t shift = tile_shift_for(sizeof(T)), ktop = j.L ? j.L - 1 : 0u;
     constexpr int V = 16 / sizeof(T);
+    static_assert((16384 / 16) == kJHThreads, "one vector per thread and tile");
     bool bad = false, ovf = false;
     auto count = [&](uint32_t x) -> uint32_t {
         if (x >= j.sigma) {
@@ -292,45 +324,92 @@ __device__ __forceinline__ void job_hist_big(const JobDev &j, LdsJobHist &s) {
         }
         return ((x >> ktop) & 1u) ^ 1u;
     };
-    for (uint32_t tile = 0; tile < j.T0; ++tile) {
-        const uint64_t base = (uint64_t)tile << shift;
-        const uint32_t len = (uint32_t)min(1ull << shift, j.n - base);
-        uint32_t zeros = 0;
-        if (len % V == 0) {
-            for (uint32_t v = tid; v < len / V; v += kBlock) {
-                union {
-                    uint4 q;
-                    T e[V];
-                } u;
-                u.q = *reinterpret_cast<const uint4 *>(S + base + (uint64_t)v * V);
+    union Vec {
+        uint4 q;
+        T e[V];
+    };
+    const uint32_t Tfull = (uint32_t)(j.n >> shift);
+    Vec cur[kJHTiles], nxt[kJHTiles];
+    auto load = [&](uint32_t t0, Vec (&q)[kJHTiles]) {
 #pragma unroll
-                for (int e = 0; e < V; ++e) zeros += count((uint32_t)u.e[e]);
-            }
-        } else {
-            for (uint32_t e = tid; e < len; e += kBlock) zeros += count((uint32_t)S[base + e]);
+        for (int r = 0; r < kJHTiles; ++r)
+            if (t0 + r < Tfull) q[r].q = reinterpret_cast<const uint4 *>(S + ((uint64_t)(t0 + r) << shift))[tid];
+    };
+    if (Tfull) load(0, cur);
+    for (uint32_t t0 = 0; t0 < Tfull; t0 += kJHTiles) {
+        if (t0 + kJHTiles < Tfull) load(t0 + kJHTiles, nxt);
+#pragma unroll
+        for (int r = 0; r < kJHTiles; ++r) {
+            if (t0 + r >= Tfull) break;
+            uint32_t zeros = 0;
+#pragma unroll
+            for (int e = 0; e < V; ++e) zeros += count((uint32_t)cur[r].e[e]);
+            const uint32_t wz = wave_sum_u32(zeros);
+            if (j.L && lane == 0) atomicAdd(j.cnt + t0 + r, wz);
         }
-        if (j.L) {
-            const uint32_t t = block_sum_u32(zeros, s.red);
-            if (tid == 0) j.cnt[tile] = t;
-        }
+#pragma unroll
+        for (int r = 0; r < kJHTiles; ++r) cur[r] = nxt[r];
     }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(j.ctl + kCtlStatus, kStatusSymbol);
-    if (__ballot(ovf) && lane_id() == 0) atomicOr(&s.overflow, 1u);
+    if (Tfull < j.T0) {  // the ragged last tile
+        const uint64_t base = (uint64_t)Tfull << shift;
+        const uint32_t len = (uint32_t)(j.n - base);
+        uint32_t zeros = 0;
+        for (uint32_t e = tid; e < len; e += kJHThreads) zeros += count((uint32_t)S[base + e]);
+        const uint32_t wz = wave_sum_u32(zeros);
+        if (j.L && lane == 0) atomicAdd(j.cnt + Tfull, wz);
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(j.ctl + kCtlStatus, kStatusSymbol);
+    if (__ballot(ovf) && lane == 0) atomicOr(&s.overflow, 1u);
     __syncthreads();
     // C = exclusive prefix of the counts (plus what reached the global
-    // counters), written straight to the output.
+    // counters): wave w takes bins [4096 w, 4096 w + 4096), first its total,
+    // then 64-bin rounds of wave scans stored coalesced.
     const bool spill = s.overflow != 0;
-    const uint64_t total = block_scan_all<16>(
-        j.sigma, s.scan,
-        [&](uint64_t g) -> uint64_t {
-            const uint32_t w = s.bins[g >> 1];
-            return (uint64_t)((w >> (16 * (g & 1))) & 0xFFFFu) +
-                   (spill ? __hip_atomic_load(j.symcnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u);
-        },
-        [&](uint64_t g, uint64_t ex) { j.C[g] = ex; });
+    auto value = [&](uint64_t g) -> uint32_t {
+        if (g >= j.sigma) return 0u;
+        const uint32_t w = s.bins[g >> 1];
+        return ((w >> (16 * (g & 1))) & 0xFFFFu) +
+               (spill ? __hip_atomic_load(j.symcnt + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u);
+    };
+    constexpr uint32_t kPerWave = kJobHistMaxSigma / kJHWaves;
+    const uint64_t g0 = (uint64_t)wave * kPerWave;
+    uint32_t own = 0;
+    for (uint32_t r = 0; r < kPerWave; r += kWave) own += value(g0 + r + lane);
+    own = wave_sum_u32(own);
+    if (lane == 0) s.wtot[wave] = own;
+    __syncthreads();
+    uint64_t carry = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kJHWaves; ++w) {
+        const uint32_t t = s.wtot[w];
+        carry += w < wave ? t : 0u;
+        total += t;
+    }
+    for (uint32_t r = 0; r < kPerWave && g0 + r < j.sigma; r += kWave) {
+        const uint64_t g = g0 + r + lane;
+        const uint32_t v = value(g), inc = wave_incl_scan_u32(v, lane);
+        if (g < j.sigma) j.C[g] = carry + inc - v;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
     if (tid == 0) {
         j.C[j.sigma] = total;
         j.ctl[kCtlCDone] = 1;
+    }
+}
+
+// Per-phase launches: the whole-job histogram items, one block each.
+__global__ __launch_bounds__(kJHThreads) void job_hist_kernel(Args b) {
+    __shared__ LdsJobHist s;
+    for (uint32_t it = b.lo + blockIdx.x; it < b.hi; it += gridDim.x) {
+        __syncthreads();  // the previous job is done with the LDS
+        const uint32_t si = __builtin_amdgcn_readfirstlane(b.seg_of[it]);
+        const Seg sg = load_const(b.segs + si);
+        const JobDev j = load_const(b.jobs + __builtin_amdgcn_readfirstlane(sg.job));
+        if (j.in_bytes == 2) job_hist_block<uint16_t>(j, s);
+        else job_hist_block<uint32_t>(j, s);
+        wait_own_stores();
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(j.ctl + kCtlDone, 1u);
     }
 }
 
@@ -349,11 +428,207 @@ __host__ __device__ inline uint64_t fused_half(uint32_t mid) {
                     : (mid == 2 ? FusedCfg<uint16_t, kFusedBytes>::kHalf : FusedCfg<uint32_t, kFusedBytes>::kHalf);
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    for (int m = kWave / 2; m >= 1; m >>= 1) v = max(v, (uint32_t)__shfl_xor(v, m, kWave));
+    return v;
+}
+
+// Node tables of every level and each level's largest node, for one job by
+// one block.  The levels whose nodes span at most 2^12 symbols go chunk by
+// chunk (C of the chunk into LDS: one coalesced read of C in all):
+//  * thread t owns the chunk's symbols [16t, 16t + 16); the nodes of depth
+//    d <= 3 (2^(d+1) symbols, level L-1-d) inside them come from its 17 C
+//    values in registers;
+//  * each deeper node of the chunk (255 of them for a full chunk) belongs to
+//    one thread, depth by depth, and reads its three C values from LDS;
+// then one block scan of five values per thread (the ones of its depth-0..3
+// nodes, its deep node's ones) gives every node's ones before it in the
+// chunk; a deep depth's own prefix is the scan minus the scan at its first
+// thread.  Each thread carries its depths' totals from chunk to chunk.  The
+// few levels above (nodes wider than a chunk) come straight from C.  Counts
+// fit 32 bits (n < 2^32); the tables are 64-bit.
+__device__ __forceinline__ uint32_t tab_pad(uint32_t i) { return i + (i >> 4); }  // conflict-free strided reads
+
+__device__ __forceinline__ void tables_chunked(const JobDev &j, LdsPrep &lp) {
+    const uint32_t L = j.L, CHL = min(kTabChunkLog, L), lc = L - CHL;
+    const uint32_t CH = 1u << CHL, S = min(kTabPer, CH), nloc = min(4u, CHL);
+    const uint64_t nchunks = 1ull << lc;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    for (uint32_t l = 0; l < lc; ++l) {
+        const uint64_t m = table_level_block<4>(j.C, j.sigma, L, l, j.D, lp.scan, lp.nmax);
+        if (tid == 0) lp.lmax[l] = m;
+    }
+    // This thread's deep node: depth dd, index ii; depth dd's nodes are the
+    // threads [off, off + nk).
+    uint32_t dd = 0, ii = 0, off = 0, nk = 0;
+    bool deep = false;
+    for (uint32_t d = 4, o = 0; d < CHL; ++d) {
+        const uint32_t k = CH >> (d + 1);
+        if ((uint32_t)tid >= o && (uint32_t)tid < o + k) {
+            dd = d;
+            ii = tid - o;
+            off = o;
+            nk = k;
+            deep = true;
+        }
+        o += k;
+    }
+    const bool owner = (uint32_t)tid * kTabPer < CH;
+    uint64_t carry[4] = {0, 0, 0, 0}, dcarry = 0;
+    uint32_t bigloc[4] = {0, 0, 0, 0}, bigdeep = 0;
+    if (tid < 32) lp.big[tid] = 0;
+    // A chunk's C in registers: every load of it in flight at once, the
+    // next chunk's issued before this one's tables are computed.
+    constexpr int kPer = kTabChunk / kBlock + 1;
+    uint32_t cv[kPer];
+    auto load_chunk = [&](uint64_t c0) {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint64_t i = (uint64_t)r * kBlock + tid, c = min(c0 + i, j.sigma);
+            cv[r] = i <= CH ? (uint32_t)j.C[c] : 0u;
+        }
+    };
+    load_chunk(0);
+    for (uint64_t ch = 0; ch < nchunks; ++ch) {
+        __syncthreads();  // the previous chunk is done with cl and xs
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint32_t i = (uint32_t)r * kBlock + tid;
+            if (i <= CH) lp.cl[tab_pad(i)] = cv[r];
+        }
+        if (ch + 1 < nchunks) load_chunk((ch + 1) << CHL);
+        __syncthreads();
+        uint32_t c[kTabPer + 1];
+#pragma unroll
+        for (uint32_t q = 0; q <= kTabPer; ++q) c[q] = owner && q <= S ? lp.cl[tab_pad(tid * kTabPer + q)] : 0u;
+        uint32_t v[5];
+#pragma unroll
+        for (uint32_t d = 0; d < 4; ++d) {
+            v[d] = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < (kTabPer >> (d + 1)); ++i)
+                if (owner && d < nloc && i < (S >> (d + 1))) {
+                    v[d] += c[(i + 1) << (d + 1)] - c[(2 * i + 1) << d];
+                    bigloc[d] = max(bigloc[d], c[(i + 1) << (d + 1)] - c[i << (d + 1)]);
+                }
+        }
+        uint32_t dce = 0;
+        v[4] = 0;
+        if (deep) {
+            dce = lp.cl[tab_pad((ii + 1) << (dd + 1))];
+            v[4] = dce - lp.cl[tab_pad((2 * ii + 1) << dd)];
+            bigdeep = max(bigdeep, dce - lp.cl[tab_pad(ii << (dd + 1))]);
+        }
+        uint32_t inc[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) inc[q] = wave_incl_scan_u32(v[q], lane);
+        if (lane == kWave - 1)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) lp.wtot[wave][q] = inc[q];
+        __syncthreads();
+        uint32_t ex[5], tot[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            uint32_t before = 0, all = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                const uint32_t t = lp.wtot[w][q];
+                before += w < wave ? t : 0u;
+                all += t;
+            }
+            ex[q] = before + inc[q] - v[q];
+            tot[q] = all;
+        }
+        lp.xs[tid] = ex[4];
+        __syncthreads();
+        // Depths 0..3: the thread's nodes, in order.
+#pragma unroll
+        for (uint32_t d = 0; d < 4; ++d) {
+            if (d >= nloc) continue;
+            if (owner) {
+                uint64_t *Dl = j.D + (2ull << (L - 1 - d)) - 2;
+                const uint64_t p0 = (ch * CH + (uint64_t)tid * kTabPer) >> (d + 1);
+                uint64_t run = carry[d] + ex[d];
+#pragma unroll
+                for (uint32_t i = 0; i < (kTabPer >> (d + 1)); ++i)
+                    if (i < (S >> (d + 1))) {
+                        const uint32_t ce = c[(i + 1) << (d + 1)], ones = ce - c[(2 * i + 1) << d];
+                        ulonglong2 e;
+                        e.x = run;                          // ones of the level before the node
+                        e.y = (uint64_t)ce - (run + ones);  // zeros before the next node
+                        *reinterpret_cast<ulonglong2 *>(Dl + 2 * (p0 + i)) = e;
+                        run += ones;
+                    }
+            }
+            carry[d] += tot[d];
+        }
+        // The deep node.
+        if (deep) {
+            const uint32_t first = lp.xs[off];
+            const uint64_t run = dcarry + (ex[4] - first);
+            uint64_t *Dl = j.D + (2ull << (L - 1 - dd)) - 2;
+            const uint64_t p = ch * nk + ii;
+            ulonglong2 e;
+            e.x = run;
+            e.y = (uint64_t)dce - (run + v[4]);
+            *reinterpret_cast<ulonglong2 *>(Dl + 2 * p) = e;
+            dcarry += lp.xs[off + nk] - first;
+        }
+    }
+    // Largest node of each chunked level.
+#pragma unroll
+    for (uint32_t d = 0; d < 4; ++d) {
+        const uint32_t m = wave_max_u32(bigloc[d]);
+        if (lane == 0 && d < nloc) atomicMax(&lp.big[d], m);
+    }
+    if (deep) atomicMax(&lp.big[dd], bigdeep);
+    __syncthreads();
+    if ((uint32_t)tid < CHL) lp.lmax[L - 1 - tid] = lp.big[tid];
+    __syncthreads();
+}
+
+// Segments of a job whose levels from l0 on run fused in LDS.  Segment s
+// starts at the first node start of level l0 at or after s * half (n if
+// none), so each node lies in exactly one segment.  Segment s is empty when
+// its start is n or lies at or beyond (s + 1) * half (the next segment then
+// starts at the same node).  With lists, the nonempty ones are appended to
+// the fused list.
+__device__ __forceinline__ void fused_segments(const JobDev &j, uint32_t l0, const Args &b, LdsPrep &lp) {
+    const uint64_t half = fused_half(j.mid_bytes), n = j.n, P = 1ull << l0;
+    const uint32_t shift = j.L - l0;
+    auto Cc = [&](uint64_t x) { return j.C[x < j.sigma ? x : j.sigma]; };
+    // Thread t handles nodes p = t + 1, t + 1 + kBlock, ...: segments s with
+    // start(p - 1) < s * half <= start(p) start at start(p).
+    auto visit = [&](auto &&fn) {
+        for (uint64_t p = 1 + threadIdx.x; p <= P; p += kBlock) {
+            const uint64_t c0 = Cc((p - 1) << shift), c = Cc(p << shift);
+            for (uint64_t sg = c0 / half + 1; sg * half <= c && sg <= j.nseg; ++sg) fn(sg, c);
+        }
+    };
+    if (threadIdx.x == 0) {
+        j.segb[0] = 0;
+        j.segb[j.nseg] = (uint32_t)n;
+    }
+    visit([&](uint64_t sg, uint64_t c) { j.segb[sg] = (uint32_t)c; });
+    if (!b.list) return;
+    uint32_t mine = threadIdx.x == 0 && n > 0 ? 1u : 0u;  // segment 0 starts at 0 < half
+    visit([&](uint64_t sg, uint64_t c) { mine += c < n && c < (sg + 1) * half ? 1u : 0u; });
+    uint64_t v[1] = {mine}, total;
+    block_excl_scan<1>(v, lp.scan, total);
+    if (threadIdx.x == 0) lp.at = total ? atomicAdd(b.live + b.phase_fused, (uint32_t)total) : 0u;
+    __syncthreads();
+    uint2 *out = b.list + b.base_fused + lp.at + v[0];
+    if (threadIdx.x == 0 && n > 0) *out++ = make_uint2(j.id, 0u);
+    visit([&](uint64_t sg, uint64_t c) {
+        if (c < n && c < (sg + 1) * half) *out++ = make_uint2(j.id, (uint32_t)sg);
+    });
+}
+
 // C (unless the job's histogram already wrote it), node tables, directory
 // tails, level-0 tile prefixes and the first fused level of one job.  N:
 // values per thread in the block scans (more is faster, and costs registers).
 template <int N>
-__device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fuse) {
+__device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fuse, const Args &b) {
     BlockScanTmp &tmp = lp.scan;
     if (!__hip_atomic_load(j.ctl + kCtlCDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         const uint64_t total = block_scan_all<N>(
@@ -363,13 +638,8 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
         __syncthreads();  // the block reads C back below (workgroup scope)
     }
     if (j.L == 0) return;
-    // Node tables level by level, with each level's largest node (the
-    // fusion plan's input).
-    for (uint32_t l = 0; l < j.L; ++l) {
-        const uint64_t m = table_level_block<N>(j.C, j.sigma, j.L, l, j.D, tmp, lp.nmax);
-        if (threadIdx.x == 0) lp.lmax[l] = m;
-    }
-    __syncthreads();
+    // Node tables, with each level's largest node (the fusion plan's input).
+    tables_chunked(j, lp);
     for (uint32_t l = 0; l < j.L; ++l)
         dir_tail(l, j.D[(1ull << (l + 2)) - 3], j.n, j.L, j.rank, j.rank_len, j.sel1, j.sel0, j.cap, j.sel_counts,
                  threadIdx.x, kBlock);
@@ -377,10 +647,19 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
     uint32_t l0 = j.L;
     if (fuse && j.L >= 2 && j.n > 0) l0 = fused_from(lp.lmax, j.L, fused_half(j.mid_bytes));
     if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
+    if (l0 < j.L) fused_segments(j, l0, b, lp);
+    if (b.list && j.n > 0 && l0 > 0) {
+        // Level 0's tiles are live.
+        __syncthreads();  // every thread has read lp.at of the fused list
+        const uint32_t wide = j.in_bytes > 1 ? 1u : 0u;
+        if (threadIdx.x == 0) lp.at = atomicAdd(b.live + 3 + wide, j.T0);
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < j.T0; t += kBlock) b.list[b.base0[wide] + lp.at + t] = make_uint2(j.id, t);
+    }
 }
 
 template <uint32_t KINDS, typename LV>
-__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LV &s) {
+__device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LV &s, bool listed) {
     const bool scatter = l + 1 < j.L;
     const uint32_t win = l == 0 ? j.in_bytes : j.mid_bytes, wout = j.mid_bytes;
     LevelArgs a;
@@ -399,7 +678,7 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
     a.n = j.n;
     a.k = j.L - 1 - l;
     a.level = l;
-    a.fused_l0 = j.ctl + kCtlFusedL0;
+    a.fused_l0 = listed ? nullptr : j.ctl + kCtlFusedL0;  // a listed tile is live
     a.qmask = ~0u;
     if (win == 1) {
         if constexpr ((KINDS & kHasLevel8) != 0) {
@@ -444,6 +723,7 @@ __device__ __forceinline__ void fused_item(const JobDev &j, uint32_t seg, LdsFus
     f.cap = j.cap;
     f.status = j.ctl + kCtlStatus;
     f.l0 = j.ctl + kCtlFusedL0;
+    f.segb = j.segb;
     const uint32_t wi = j.in_bytes, wm = j.mid_bytes;
     if (wm == 1) {
         if (wi == 1) fused_segment<uint8_t, uint8_t, kFusedBytes>(f, seg, s.f8);
@@ -480,11 +760,7 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
             finish_item(b, ctl + kCtlDone, count, s_flag);
         }
     } else if (kind == kKindJobHist) {
-        if constexpr (KINDS == kHasJobHist) {
-            if (j.in_bytes == 2) job_hist_big<uint16_t>(j, s);
-            else job_hist_big<uint32_t>(j, s);
-            finish_item(b, ctl + kCtlDone, count, s_flag);
-        } else if constexpr (KINDS == kHasAll) {
+        if constexpr (KINDS == kHasAll) {
             if (j.in_bytes == 2) job_hist_small<uint16_t>(j, s.hist);
             else job_hist_small<uint32_t>(j, s.hist);
             finish_item(b, ctl + kCtlDone, count, s_flag);
@@ -492,8 +768,8 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
     } else if (kind == kKindPrep) {
         if constexpr ((KINDS & kHasPrep) != 0) {
             wait_for(b, ctl + kCtlDone, j.hist_items, ctl + kCtlStatus);
-            if constexpr (KINDS == kHasAll) prep_item<4>(j, s.prep, b.fuse != 0);
-            else prep_item<16>(j, s, b.fuse != 0);
+            if constexpr (KINDS == kHasAll) prep_item<4>(j, s.prep, b.fuse != 0, b);
+            else prep_item<4>(j, s, b.fuse != 0, b);
             publish(b, ctl + kCtlReady);
         }
     } else if (kind == kKindFused) {
@@ -513,7 +789,7 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
             }();
             const uint32_t l = kind - kKindLevel;
             wait_for(b, ctl + kCtlReady + l, 1u, ctl + kCtlStatus);
-            level_item<KINDS>(j, l, tile, lv);
+            level_item<KINDS>(j, l, tile, lv, false);
             if (finish_item(b, ctl + kCtlDone + 1 + l, count, s_flag) && l + 1 < j.L) {
                 tile_prefix_block(j.cnt + (uint64_t)(l + 1) * j.Tpad, j.pre + (uint64_t)(l + 1) * j.Tpad, j.Tm,
                                   lv.scan);
@@ -523,11 +799,38 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
     }
 }
 
+// A listed item of a per-phase level or fused launch: (job, tile or segment).
+template <uint32_t KINDS, typename LDS>
+__device__ __forceinline__ void run_listed(const Args &b, uint2 e, LDS &s) {
+    const uint32_t jid = __builtin_amdgcn_readfirstlane(e.x), it = __builtin_amdgcn_readfirstlane(e.y);
+    const JobDev j = load_const(b.jobs + jid);
+    if constexpr (KINDS == kHasFused) {
+        fused_item(j, it, s);
+    } else if constexpr ((KINDS & kHasLevel) != 0 && (KINDS & ~kHasLevel) == 0) {
+        level_item<KINDS>(j, b.level, it, s, true);
+    }
+}
+
 template <uint32_t KINDS, typename LDS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_for(KINDS)))) void
 work_kernel(Args b) {
     __shared__ LDS s;
     __shared__ uint32_t s_first, s_flag;
+    if constexpr (KINDS == kHasFused || ((KINDS & kHasLevel) != 0 && (KINDS & ~kHasLevel) == 0)) {
+        if (b.list) {
+            // The phase's live items, a chunk per block and grid stride.
+            const uint32_t count = __builtin_amdgcn_readfirstlane(ld_u32(b.live + b.phase));
+            for (uint64_t first = (uint64_t)blockIdx.x * b.chunk; first < count;
+                 first += (uint64_t)gridDim.x * b.chunk) {
+                const uint32_t last = (uint32_t)min(first + b.chunk, (uint64_t)count);
+                for (uint32_t i = (uint32_t)first; i < last; ++i) {
+                    __syncthreads();  // the previous item's LDS is free
+                    run_listed<KINDS, LDS>(b, load_const(b.list + b.lo + i), s);
+                }
+            }
+            return;
+        }
+    }
     if (!b.fenced) {
         // One launch per phase: no item waits for another of the same
         // launch, so blocks take their chunks by index (no shared queue head,
@@ -564,20 +867,48 @@ __global__ void clear_kernel(uint64_t *a, uint64_t na) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) a[i] = 0;
 }
 
+// Per-phase launches, before level l >= 1: one wave per job scans the
+// level's count-ahead totals (atomics of the previous launch) into its tile
+// prefixes and lists the level's tiles unless the level is fused.
+__global__ __launch_bounds__(kBlock) void level_setup_kernel(Args b, uint32_t njobs, uint32_t l, uint32_t base_byte,
+                                                             uint32_t base_wide) {
+    const uint32_t jid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + threadIdx.x / kWave);
+    if (jid >= njobs) return;
+    const JobDev j = load_const(b.jobs + jid);
+    if (j.n == 0 || l >= j.L || ld_u32(j.ctl + kCtlFusedL0) <= l) return;
+    const uint32_t lane = lane_id(), T = j.Tm;
+    const uint32_t *cnt = j.cnt + (uint64_t)l * j.Tpad;
+    uint64_t *pre = j.pre + (uint64_t)l * j.Tpad;
+    uint64_t carry = 0;
+    for (uint32_t t0 = 0; t0 < T; t0 += kWave) {
+        const uint32_t t = t0 + lane, c = t < T ? ld_u32(cnt + t) : 0u;
+        const uint32_t inc = wave_incl_scan_u32(c, lane);
+        if (t < T) pre[t] = carry + inc - c;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    const uint32_t wide = j.mid_bytes > 1 ? 1u : 0u;
+    uint32_t at = 0;
+    if (lane == 0) at = atomicAdd(b.live + 3 + 2 * l + wide, T);
+    at = __shfl(at, 0, kWave);
+    uint2 *out = b.list + (wide ? base_wide : base_byte) + at;
+    for (uint32_t t = lane; t < T; t += kWave) out[t] = make_uint2(jid, t);
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 struct HostJob {
     uint64_t n, sigma;
     uint32_t L, in_bytes, mid_bytes, reps, T0, Tm, Tpad;
     bool job_hist;  // counted by one whole-job item (large alphabet that fits packed LDS bins)
-    uint64_t off_ctl, off_symcnt, off_cnt, off_pre, off_D, off_S0, off_S1;
+    uint64_t off_ctl, off_symcnt, off_cnt, off_pre, off_D, off_S0, off_S1, off_segb;
+    uint32_t nseg;
 };
 
 struct HostPlan {
     std::vector<HostJob> jobs;
     std::vector<Seg> segs;
     std::vector<uint32_t> phase_first;
-    uint64_t items = 0, off_jobs = 0, off_segs = 0, off_seg_of = 0, clear_bytes = 0, total = 0;
+    uint64_t items = 0, off_jobs = 0, off_segs = 0, off_seg_of = 0, off_list = 0, clear_bytes = 0, total = 0;
 };
 
 static uint32_t levels_of(uint64_t sigma) {
@@ -655,8 +986,9 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
     }
     hp.phase_first.push_back((uint32_t)items);
     for (uint32_t i = 0; i < njobs; ++i) {  // fused tail levels: one item per segment
-        const HostJob &h = hp.jobs[i];
-        if (h.n > 0 && h.L >= 2) add(i, kKindFused, (uint32_t)cdiv(h.n, fused_half(h.mid_bytes)));
+        HostJob &h = hp.jobs[i];
+        h.nseg = h.n > 0 && h.L >= 2 ? (uint32_t)cdiv(h.n, fused_half(h.mid_bytes)) : 0u;
+        add(i, kKindFused, h.nseg);
     }
     if (items >= (1ull << 31)) return WT_ERR_RANGE;
     hp.phase_first.push_back((uint32_t)items);
@@ -668,6 +1000,8 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
     o = align_up(o + sizeof(Seg) * hp.segs.size(), 256);
     hp.off_seg_of = o;
     o = align_up(o + 4 * items, 256);
+    hp.off_list = o;
+    o = align_up(o + 8 * items, 256);
     for (auto &h : hp.jobs) {
         h.off_pre = o;
         o = align_up(o + 8ull * h.L * h.Tpad, 256);
@@ -678,6 +1012,8 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
         o += sbytes;
         h.off_S1 = o;
         o += h.L >= 3 ? sbytes : 0;
+        h.off_segb = o;
+        o = align_up(o + 4ull * (h.nseg + 1), 256);
     }
     hp.total = std::max<uint64_t>(o, 256);
     return WT_OK;
@@ -726,6 +1062,7 @@ extern "C" int wt_batch_plan(const wt_job *jobs, uint32_t njobs, wt_batch_layout
     out->off_jobs = hp.off_jobs;
     out->off_segs = hp.off_segs;
     out->off_seg_of = hp.off_seg_of;
+    out->off_list = hp.off_list;
     return WT_OK;
 }
 
@@ -735,7 +1072,8 @@ extern "C" int wt_batch_prepare(const wt_job *jobs, uint32_t njobs, const wt_bat
     HostPlan hp;
     int rc = make_batch_plan(jobs, njobs, hp);
     if (rc) return rc;
-    if (lay->njobs != njobs || lay->items != hp.items || lay->scratch_bytes != hp.total) return WT_ERR_ARG;
+    if (lay->njobs != njobs || lay->items != hp.items || lay->scratch_bytes != hp.total || lay->off_list != hp.off_list)
+        return WT_ERR_ARG;
     if (scratch_bytes < hp.total) return WT_ERR_SCRATCH;
     unsigned char *sc = (unsigned char *)d_scratch;
     std::vector<JobDev> dev(njobs);
@@ -776,6 +1114,9 @@ extern "C" int wt_batch_prepare(const wt_job *jobs, uint32_t njobs, const wt_bat
         d.D = (uint64_t *)(sc + h.off_D);
         d.S0 = sc + h.off_S0;
         d.S1 = sc + h.off_S1;
+        d.segb = (uint32_t *)(sc + h.off_segb);
+        d.nseg = h.nseg;
+        d.id = i;
     }
     std::vector<uint32_t> seg_of(hp.items);
     for (uint32_t s = 0; s < hp.segs.size(); ++s)
@@ -817,20 +1158,32 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
     a.spin_limit = spin;
     a.fenced = t.mode == WT_BATCH_PERSISTENT ? 1u : 0u;
     a.fuse = fused_levels_enabled() ? 1u : 0u;
+    const uint32_t last = lay->phases - 1;
+    // Lists of live items (per-phase launches only).
+    a.list = a.fenced ? nullptr : (uint2 *)(sc + lay->off_list);
+    a.live = (uint32_t *)sc + kLiveWord;
+    a.base0[0] = lay->phase_first[std::min(3u, last)];
+    a.base0[1] = lay->phase_first[std::min(4u, last)];
+    a.base_fused = lay->phase_first[last];
+    a.phase_fused = last;
     auto launch = [&](uint32_t phase, uint32_t lo, uint32_t hi) {
         if (hi <= lo) return;
         a.head = (uint32_t *)sc + phase;
         a.lo = lo;
         a.hi = hi;
+        a.phase = phase;
+        a.level = phase >= 3 && phase < last ? (phase - 3) / 2 : 0u;
         // Persistent launch: resident blocks take items from the queue.  One
-        // launch per phase: one block per chunk unless blocks_per_cu caps it.
+        // launch per phase: one block per chunk unless blocks_per_cu caps it;
+        // a listed launch (levels, fused) at most two rounds of resident
+        // blocks, which stride over the live items.
         const uint64_t chunks = cdiv(hi - lo, chunk);
-        const uint64_t cap = (a.fenced || t.blocks_per_cu) ? resident : (1ull << 31) - 1;
+        const bool listed = !a.fenced && phase >= 3;
+        const uint64_t cap = (a.fenced || t.blocks_per_cu) ? resident : (listed ? 2 * resident : (1ull << 31) - 1);
         const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(cap, chunks));
-        const uint32_t last = lay->phases - 1;
         if (a.fenced) work_kernel<kHasAll, LdsBatch><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if (phase == 0) work_kernel<kHasTileHist, LdsHistB><<<(unsigned)grid, kBlock, 0, s>>>(a);
-        else if (phase == 1) work_kernel<kHasJobHist, LdsJobHist><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (phase == 1) job_hist_kernel<<<(unsigned)std::min<uint64_t>(hi - lo, 1u << 20), kJHThreads, 0, s>>>(a);
         else if (phase == 2) work_kernel<kHasPrep, LdsPrep><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if (phase == last) work_kernel<kHasFused, LdsFusedAll><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if ((phase - 3) % 2 == 0) work_kernel<kHasLevel8, LdsLevels8><<<(unsigned)grid, kBlock, 0, s>>>(a);
@@ -839,7 +1192,14 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
     if (t.mode == WT_BATCH_PERSISTENT) {
         launch(0, 0, lay->items);
     } else {
-        for (uint32_t p = 0; p < lay->phases; ++p) launch(p, lay->phase_first[p], lay->phase_first[p + 1]);
+        for (uint32_t p = 0; p < lay->phases; ++p) {
+            if (p >= 5 && p < last && (p - 3) % 2 == 0 && lay->phase_first[p] < lay->phase_first[p + 2]) {
+                const uint32_t l = (p - 3) / 2;  // level l >= 1 has tiles: prefixes and lists first
+                level_setup_kernel<<<(unsigned)std::max<uint64_t>(1, cdiv(lay->njobs, kWaves)), kBlock, 0, s>>>(
+                    a, lay->njobs, l, lay->phase_first[p], lay->phase_first[p + 1]);
+            }
+            launch(p, lay->phase_first[p], lay->phase_first[p + 1]);
+        }
     }
     return hipGetLastError() == hipSuccess ? WT_OK : WT_ERR_HIP;
 }

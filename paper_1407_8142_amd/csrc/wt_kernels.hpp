@@ -1218,6 +1218,7 @@ struct FusedArgs {
     uint64_t *sel1, *sel0, cap;
     const uint32_t *status;
     const uint32_t *l0;     // first fused level (>= L: no fusion)
+    const uint32_t *segb = nullptr;  // segment starts (and n), when known; else found by search
 };
 
 
@@ -1275,16 +1276,54 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         }
         return Cc(lo << shift) >= target ? Cc(lo << shift) : Cc(hi << shift);
     };
-    const uint64_t a = boundary(seg * Cfg::kHalf), e = boundary((seg + 1) * Cfg::kHalf);
+    const uint64_t a = f.segb ? f.segb[seg] : boundary(seg * Cfg::kHalf);
+    const uint64_t e = f.segb ? f.segb[seg + 1] : boundary((seg + 1) * Cfg::kHalf);
     if (a >= e || e - a > (uint64_t)Cfg::kCap) return;  // empty (or tables inconsistent with the input)
     const uint32_t m = (uint32_t)(e - a);
-    if (l0 == 0) {
-        const TIN0 *src = reinterpret_cast<const TIN0 *>(f.in0) + a;
-        for (uint32_t j = tid; j < m; j += kBlock) s.buf[0][j] = (T)src[j];
-    } else {
-        const T *src = reinterpret_cast<const T *>((l0 - 1) % 2 == 0 ? f.S0 : f.S1) + a;
-        for (uint32_t j = tid; j < m; j += kBlock) s.buf[0][j] = src[j];
-    }
+    // The segment into LDS: the 16-byte vectors that cover [a, e), four per
+    // thread in flight at a time (the sequences are 16-byte aligned; a
+    // vector that runs past the sequence's end is read symbol by symbol).
+    auto load_segment = [&](auto src_tag) {
+        using TS = decltype(src_tag);
+        constexpr int V = 16 / (int)sizeof(TS), kG = 4;
+        const TS *src = l0 == 0 ? reinterpret_cast<const TS *>(f.in0)
+                                : reinterpret_cast<const TS *>((l0 - 1) % 2 == 0 ? f.S0 : f.S1);
+        const uint64_t va = a / V;
+        const uint32_t nv = (uint32_t)(cdiv(e, (uint64_t)V) - va);
+        for (uint32_t g0 = 0; g0 < nv; g0 += kBlock * kG) {
+            union {
+                uint4 q;
+                TS x[V];
+            } u[kG];
+#pragma unroll
+            for (int r = 0; r < kG; ++r) {
+                const uint32_t vi = g0 + r * kBlock + tid;
+                if (vi < nv) {
+                    if ((va + vi + 1) * V <= n) {
+                        u[r].q = reinterpret_cast<const uint4 *>(src)[va + vi];
+                    } else {
+#pragma unroll
+                        for (int x = 0; x < V; ++x) {
+                            const uint64_t pos = (va + vi) * V + x;
+                            u[r].x[x] = pos < n ? src[pos] : TS{};
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kG; ++r) {
+                const uint32_t vi = g0 + r * kBlock + tid;
+                if (vi < nv)
+#pragma unroll
+                    for (int x = 0; x < V; ++x) {
+                        const uint64_t pos = (va + vi) * V + x;
+                        if (pos >= a && pos < e) s.buf[0][pos - a] = (T)u[r].x[x];
+                    }
+            }
+        }
+    };
+    if (l0 == 0) load_segment(TIN0{});
+    else load_segment(T{});
     __syncthreads();
     const uint32_t a63 = (uint32_t)(a & 63);
     const uint32_t nvw = (a63 + m + 63) / 64;
@@ -1301,21 +1340,71 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         const int32_t hi = (int32_t)(a63 + m) - (int32_t)(64 * vw);
         return bit_range(lo, e == n && hi > 0 ? 64u : (uint32_t)min(max(hi, 0), 64));
     };
+    // Node-table state of the current level: Za (zeros of the level before
+    // the segment) and the cached window D_l[qlo, qlo + nq) of the keys
+    // q = symbol >> k the split looks up.  Level l0's is loaded here; each
+    // later level's is loaded while the level before it runs: the segment's
+    // nodes at level l+1 are the children of its nodes [pa, pz] at level l,
+    // so its keys lie in [4 pa, 4 pz + 3] and the zeros before it are
+    // D_{l+1}[4 pa - 1] (the first child may be empty: the zeros before an
+    // empty node equal those before the next).
+    constexpr int kPf = kFusedDCache / kBlock;  // window entries per thread
+    uint64_t pa = (uint64_t)((uint32_t)s.buf[0][0] >> (L - l0));  // nodes of level l0 the segment spans
+    uint64_t pz = (uint64_t)((uint32_t)s.buf[0][m - 1] >> (L - l0));
+    uint64_t Za = 0, qlo = 0, nq = 0;
+    {
+        const uint64_t *Dl = f.D + ((2ull << l0) - 2);
+        Za = pa ? Dl[2 * pa - 1] : 0;
+        if (l0 + 1 < L) {
+            qlo = 2 * pa;
+            nq = min(2 * (pz - pa) + 2, (uint64_t)kFusedDCache);
+            for (uint32_t i = tid; i < nq; i += kBlock) s.dcache[i] = Dl[qlo + i];
+        }
+    }
     int cur = 0;
     for (uint32_t l = l0; l < L; ++l) {
         const uint32_t k = L - 1 - l;
         const T *A = s.buf[cur];
         const uint64_t *Dl = f.D + ((2ull << l) - 2);
-        // 1. Bit words, wave w taking words w, w + 4, ...; zeros per word.
-        for (uint32_t vw = wave; vw < nvw; vw += kWaves) {
-            const int32_t j = (int32_t)(vw * 64 + lane) - (int32_t)a63;
-            const bool valid = j >= 0 && j < (int32_t)m;
-            const uint32_t v = valid ? (uint32_t)A[j] : 0u;
-            const uint64_t wb = __ballot(valid && ((v >> k) & 1u));
-            const uint64_t vb = __ballot(valid);
-            if (lane == 0) {
-                s.words[vw] = wb;
-                s.zpre[vw] = (uint32_t)(__popcll(vb) - __popcll(wb));
+        // Next level's table entries, in flight while this level runs.
+        uint64_t ZaN = 0, qloN = 0, nqN = 0, pf[kPf];
+        if (l + 1 < L) {
+            const uint64_t *Dn = f.D + ((2ull << (l + 1)) - 2);
+            ZaN = pa ? Dn[4 * pa - 1] : 0;
+            if (l + 2 < L) {
+                qloN = 4 * pa;
+                nqN = min(4 * (pz - pa) + 4, (uint64_t)kFusedDCache);
+#pragma unroll
+                for (int r = 0; r < kPf; ++r) {
+                    const uint64_t i = (uint64_t)r * kBlock + tid;
+                    pf[r] = i < nqN ? Dn[qloN + i] : 0;
+                }
+            }
+        }
+        // 1. Bit words, wave w taking words w, w + 4, ...; zeros per word
+        //    (four words' symbols read before any is used).
+        constexpr int U1 = 4;
+        for (uint32_t vw0 = wave; vw0 < nvw; vw0 += kWaves * U1) {
+            uint32_t v[U1];
+            bool valid[U1];
+#pragma unroll
+            for (int u = 0; u < U1; ++u) {
+                const uint32_t vw = vw0 + u * kWaves;
+                const int32_t j = (int32_t)(vw * 64 + lane) - (int32_t)a63;
+                valid[u] = vw < nvw && j >= 0 && j < (int32_t)m;
+                v[u] = valid[u] ? (uint32_t)A[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U1; ++u) {
+                const uint32_t vw = vw0 + u * kWaves;
+                if (vw < nvw) {
+                    const uint64_t wb = __ballot(valid[u] && ((v[u] >> k) & 1u));
+                    const uint64_t vb = __ballot(valid[u]);
+                    if (lane == 0) {
+                        s.words[vw] = wb;
+                        s.zpre[vw] = (uint32_t)(__popcll(vb) - __popcll(wb));
+                    }
+                }
             }
         }
         __syncthreads();
@@ -1336,17 +1425,6 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
             __syncthreads();
         }
         const uint32_t Zseg = s.red[0] + s.red[1] + s.red[2] + s.red[3];
-        const uint64_t pa = (uint64_t)((uint32_t)A[0] >> (k + 1));  // node of the first position
-        const uint64_t Za = pa && pa < (1ull << l) ? Dl[2 * pa - 1] : 0;  // zeros of the level before the segment
-        // Table entries of the segment's key range [2 pa, 2 pz + 1] into LDS
-        // (a key past the cached window reads the table in HBM).
-        const uint64_t qlo = 2 * pa;
-        uint64_t nq = 0;  // cached entries
-        if (l + 1 < L) {
-            const uint64_t qhi = min(2 * (uint64_t)((uint32_t)A[m - 1] >> (k + 1)) + 1, (2ull << l) - 1);
-            nq = qhi >= qlo ? min(qhi - qlo + 1, (uint64_t)kFusedDCache) : 0;
-            for (uint32_t i = tid; i < nq; i += kBlock) s.dcache[i] = Dl[qlo + i];
-        }
         const uint64_t Oa = a - Za;
         uint64_t *B = f.bits + (uint64_t)l * f.W;
         uint64_t *R = f.rank + (uint64_t)l * f.rank_len;
@@ -1387,20 +1465,54 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         }
         if (l + 1 == L) break;
         // 5. Stable split into the other buffer (the global pass's
-        //    destinations minus the segment start).
+        //    destinations minus the segment start), four symbols per
+        //    thread at a time: their LDS reads issued before any is used.
         T *Bn = s.buf[cur ^ 1];
-        __syncthreads();  // the table cache is filled
-        for (uint32_t j = tid; j < m; j += kBlock) {
-            const uint32_t v = (uint32_t)A[j];
-            const uint32_t pos = a63 + j, vw = pos >> 6, ln = pos & 63;
-            const uint64_t before = vmask_of(vw) & ((1ull << ln) - 1ull);
-            const uint64_t zl = s.zpre[vw] + (uint64_t)__popcll(~s.words[vw] & before);
-            const uint64_t q = v >> k;
-            const uint64_t dq = q - qlo < nq ? s.dcache[q - qlo] : (q < (2ull << l) ? Dl[q] : ~0ull);
-            const uint64_t dest = (q & 1u) ? dq + j - Za - zl : dq + Za + zl - a;
-            if (dest < m) Bn[dest] = (T)v;
+        constexpr int U5 = 4;
+        for (uint32_t j0 = tid; j0 < m; j0 += kBlock * U5) {
+            uint32_t v[U5], zl[U5];
+            uint64_t w[U5], dq[U5];
+#pragma unroll
+            for (int u = 0; u < U5; ++u) {
+                const uint32_t j = j0 + u * kBlock;
+                v[u] = j < m ? (uint32_t)A[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U5; ++u) {
+                const uint32_t j = j0 + u * kBlock, vw = (a63 + j) >> 6;
+                w[u] = j < m ? s.words[vw] : 0ull;
+                zl[u] = j < m ? s.zpre[vw] : 0u;
+                const uint64_t q = v[u] >> k;
+                dq[u] = j < m && q - qlo < nq ? s.dcache[q - qlo] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < U5; ++u) {
+                const uint32_t j = j0 + u * kBlock;
+                if (j < m) {
+                    const uint32_t pos = a63 + j, vw = pos >> 6, ln = pos & 63;
+                    const uint64_t before = vmask_of(vw) & ((1ull << ln) - 1ull);
+                    const uint64_t z = zl[u] + (uint64_t)__popcll(~w[u] & before);
+                    const uint64_t q = v[u] >> k;
+                    const uint64_t d = q - qlo < nq ? dq[u] : (q < (2ull << l) ? Dl[q] : ~0ull);
+                    const uint64_t dest = (q & 1u) ? d + j - Za - z : d + Za + z - a;
+                    if (dest < m) Bn[dest] = (T)v[u];
+                }
+            }
         }
         __syncthreads();
+        // The next level's state: its window into the cache (free now; the
+        // next level's first barrier orders these writes before its split).
+        if (l + 2 < L)
+#pragma unroll
+            for (int r = 0; r < kPf; ++r) {
+                const uint64_t i = (uint64_t)r * kBlock + tid;
+                if (i < nqN) s.dcache[i] = pf[r];
+            }
+        Za = ZaN;
+        qlo = qloN;
+        nq = nqN;
+        pa = (uint64_t)((uint32_t)Bn[0] >> k);  // nodes of level l+1 (k_{l+1} = k - 1, node = symbol >> k)
+        pz = (uint64_t)((uint32_t)Bn[m - 1] >> k);
         cur ^= 1;
     }
 }

@@ -105,7 +105,8 @@ class Tune(ctypes.Structure):
 
 class BatchLayout(ctypes.Structure):
     _fields_ = [("scratch_bytes", ctypes.c_uint64), ("clear_bytes", ctypes.c_uint64), ("off_jobs", ctypes.c_uint64),
-                ("off_segs", ctypes.c_uint64), ("off_seg_of", ctypes.c_uint64), ("njobs", ctypes.c_uint32),
+                ("off_segs", ctypes.c_uint64), ("off_seg_of", ctypes.c_uint64), ("off_list", ctypes.c_uint64),
+                ("njobs", ctypes.c_uint32),
                 ("nsegs", ctypes.c_uint32), ("items", ctypes.c_uint32), ("phases", ctypes.c_uint32),
                 ("phase_first", ctypes.c_uint32 * 72)]
 
