@@ -411,6 +411,7 @@ typedef struct {
     uint32_t phases;          /* tile histograms, whole-job histograms, tables, then per level of the
                                  deepest job byte-symbol and wider tiles, then fused tail levels */
     uint32_t phase_first[72]; /* first item of each phase; phase_first[phases] = items */
+    uint32_t phase_var[72];   /* level phases: the one tile variant of their items, 0 when mixed */
 } wt_batch_layout;
 
 /* Host only.  WT_ERR_ARG / WT_ERR_RANGE as wt_plan (and n >= 2^32). */

@@ -68,11 +68,19 @@ constexpr uint32_t kHasTileHist = 1, kHasJobHist = 2, kHasPrep = 4, kHasLevel8 =
                    kHasFused = 32, kHasAll = 63;
 constexpr uint32_t kHasLevel = kHasLevel8 | kHasLevelWide;
 
+// Tile variants of the level pass: input and output widths and whether it
+// scatters (every level but the last).  A level launch whose items all take
+// one variant is built for that variant alone (its registers, no others').
+constexpr uint32_t vcode(uint32_t win, uint32_t wout, bool scatter) {
+    return 1u + (win << 8) + (scatter ? (wout << 4) + 1u : 0u);
+}
+constexpr bool var_has(uint32_t var, uint32_t code) { return var == 0 || var == code; }
+
 // Waves per SIMD each kernel is compiled for: the register budget that
 // keeps its code free of spills (the per-phase kernels inline several tile
 // variants, and the job records take many scalar registers).
-constexpr int waves_for(uint32_t kinds) {
-    return kinds == kHasPrep ? 2 : (kinds == kHasLevelWide ? 5 : 4);
+constexpr int waves_for(uint32_t kinds, uint32_t var = 0) {
+    return kinds == kHasPrep ? 2 : (var != 0 ? (var == vcode(1, 1, true) ? 4 : 5) : (kinds == kHasLevelWide ? 5 : 4));
 }
 
 // Control words of one job (cleared by every run): status, done counters
@@ -658,7 +666,7 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
     }
 }
 
-template <uint32_t KINDS, typename LV>
+template <uint32_t KINDS, uint32_t VAR = 0, typename LV>
 __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t tile, LV &s, bool listed) {
     const bool scatter = l + 1 < j.L;
     const uint32_t win = l == 0 ? j.in_bytes : j.mid_bytes, wout = j.mid_bytes;
@@ -682,8 +690,11 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
     a.qmask = ~0u;
     if (win == 1) {
         if constexpr ((KINDS & kHasLevel8) != 0) {
-            if (scatter) level_tile_u8<true, true>(a, tile, s.u8);
-            else level_tile_u8<false, true>(a, tile, s.u8);
+            if (scatter) {
+                if constexpr (var_has(VAR, vcode(1, 1, true))) level_tile_u8<true, true>(a, tile, s.u8);
+            } else {
+                if constexpr (var_has(VAR, vcode(1, 0, false))) level_tile_u8<false, true>(a, tile, s.u8);
+            }
         }
         return;
     }
@@ -692,14 +703,23 @@ __device__ __forceinline__ void level_item(const JobDev &j, uint32_t l, uint32_t
         // n < 2^32); the generic pass for a 16-bit input with byte levels
         // after it.
         if (scatter) {
-            if (win == 2 && wout == 1) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
-            else if (win == 2) level_tile_u16<true, true>(a, tile, s.u16);
-            else if (wout == 1) level_tile_u32<uint8_t, true, true>(a, tile, s.u32);
-            else if (wout == 2) level_tile_u32<uint16_t, true, true>(a, tile, s.u32);
-            else level_tile_u32<uint32_t, true, true>(a, tile, s.u32);
+            if (win == 2 && wout == 1) {
+                if constexpr (var_has(VAR, vcode(2, 1, true))) level_tile<uint16_t, uint8_t, true, true>(a, tile, s.g16);
+            } else if (win == 2) {
+                if constexpr (var_has(VAR, vcode(2, 2, true))) level_tile_u16<true, true>(a, tile, s.u16);
+            } else if (wout == 1) {
+                if constexpr (var_has(VAR, vcode(4, 1, true))) level_tile_u32<uint8_t, true, true>(a, tile, s.u32);
+            } else if (wout == 2) {
+                if constexpr (var_has(VAR, vcode(4, 2, true))) level_tile_u32<uint16_t, true, true>(a, tile, s.u32);
+            } else {
+                if constexpr (var_has(VAR, vcode(4, 4, true))) level_tile_u32<uint32_t, true, true>(a, tile, s.u32);
+            }
         } else {
-            if (win == 2) level_tile_u16<false, true>(a, tile, s.u16);
-            else level_tile_u32<uint32_t, false, true>(a, tile, s.u32);
+            if (win == 2) {
+                if constexpr (var_has(VAR, vcode(2, 0, false))) level_tile_u16<false, true>(a, tile, s.u16);
+            } else {
+                if constexpr (var_has(VAR, vcode(4, 0, false))) level_tile_u32<uint32_t, false, true>(a, tile, s.u32);
+            }
         }
     }
 }
@@ -800,19 +820,19 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
 }
 
 // A listed item of a per-phase level or fused launch: (job, tile or segment).
-template <uint32_t KINDS, typename LDS>
+template <uint32_t KINDS, typename LDS, uint32_t VAR>
 __device__ __forceinline__ void run_listed(const Args &b, uint2 e, LDS &s) {
     const uint32_t jid = __builtin_amdgcn_readfirstlane(e.x), it = __builtin_amdgcn_readfirstlane(e.y);
     const JobDev j = load_const(b.jobs + jid);
     if constexpr (KINDS == kHasFused) {
         fused_item(j, it, s);
     } else if constexpr ((KINDS & kHasLevel) != 0 && (KINDS & ~kHasLevel) == 0) {
-        level_item<KINDS>(j, b.level, it, s, true);
+        level_item<KINDS, VAR>(j, b.level, it, s, true);
     }
 }
 
-template <uint32_t KINDS, typename LDS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_for(KINDS)))) void
+template <uint32_t KINDS, typename LDS, uint32_t VAR = 0>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(waves_for(KINDS, VAR)))) void
 work_kernel(Args b) {
     __shared__ LDS s;
     __shared__ uint32_t s_first, s_flag;
@@ -825,12 +845,13 @@ work_kernel(Args b) {
                 const uint32_t last = (uint32_t)min(first + b.chunk, (uint64_t)count);
                 for (uint32_t i = (uint32_t)first; i < last; ++i) {
                     __syncthreads();  // the previous item's LDS is free
-                    run_listed<KINDS, LDS>(b, load_const(b.list + b.lo + i), s);
+                    run_listed<KINDS, LDS, VAR>(b, load_const(b.list + b.lo + i), s);
                 }
             }
             return;
         }
     }
+    if constexpr (VAR != 0) return;  // built for listed launches only
     if (!b.fenced) {
         // One launch per phase: no item waits for another of the same
         // launch, so blocks take their chunks by index (no shared queue head,
@@ -908,6 +929,7 @@ struct HostPlan {
     std::vector<HostJob> jobs;
     std::vector<Seg> segs;
     std::vector<uint32_t> phase_first;
+    std::vector<uint32_t> phase_var;  // per phase: the one tile variant of a level phase, else 0
     uint64_t items = 0, off_jobs = 0, off_segs = 0, off_seg_of = 0, off_list = 0, clear_bytes = 0, total = 0;
 };
 
@@ -976,11 +998,18 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
     for (uint32_t l = 0; l < maxL; ++l) {
         for (int wide = 0; wide < 2; ++wide) {  // byte-symbol tiles, then wider ones
             hp.phase_first.push_back((uint32_t)items);
+            uint32_t var = ~0u;  // the one variant of the phase's tiles, 0 when they mix
             for (uint32_t i = 0; i < njobs; ++i) {
                 const HostJob &h = hp.jobs[i];
                 const uint32_t win = l == 0 ? h.in_bytes : h.mid_bytes;
-                if (h.n > 0 && l < h.L && (win > 1) == (wide != 0)) add(i, kKindLevel + l, l == 0 ? h.T0 : h.Tm);
+                if (h.n > 0 && l < h.L && (win > 1) == (wide != 0)) {
+                    add(i, kKindLevel + l, l == 0 ? h.T0 : h.Tm);
+                    const bool scatter = l + 1 < h.L;
+                    const uint32_t v = vcode(win, scatter ? h.mid_bytes : 0u, scatter);
+                    var = var == ~0u || var == v ? v : 0u;
+                }
             }
+            hp.phase_var.push_back(var == ~0u ? 0u : var);
         }
         if (items >= (1ull << 31)) return WT_ERR_RANGE;
     }
@@ -1059,6 +1088,7 @@ extern "C" int wt_batch_plan(const wt_job *jobs, uint32_t njobs, wt_batch_layout
     out->items = (uint32_t)hp.items;
     out->phases = (uint32_t)hp.phase_first.size() - 1;
     for (size_t i = 0; i < hp.phase_first.size(); ++i) out->phase_first[i] = hp.phase_first[i];
+    for (size_t i = 0; i < hp.phase_var.size(); ++i) out->phase_var[3 + i] = hp.phase_var[i];
     out->off_jobs = hp.off_jobs;
     out->off_segs = hp.off_segs;
     out->off_seg_of = hp.off_seg_of;
@@ -1186,6 +1216,16 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
         else if (phase == 1) job_hist_kernel<<<(unsigned)std::min<uint64_t>(hi - lo, 1u << 20), kJHThreads, 0, s>>>(a);
         else if (phase == 2) work_kernel<kHasPrep, LdsPrep><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if (phase == last) work_kernel<kHasFused, LdsFusedAll><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (listed && lay->phase_var[phase] == vcode(1, 1, true))
+            work_kernel<kHasLevel8, LdsLevels8, vcode(1, 1, true)><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (listed && lay->phase_var[phase] == vcode(1, 0, false))
+            work_kernel<kHasLevel8, LdsLevels8, vcode(1, 0, false)><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (listed && lay->phase_var[phase] == vcode(2, 2, true))
+            work_kernel<kHasLevelWide, LdsLevelsWide, vcode(2, 2, true)><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (listed && lay->phase_var[phase] == vcode(2, 0, false))
+            work_kernel<kHasLevelWide, LdsLevelsWide, vcode(2, 0, false)><<<(unsigned)grid, kBlock, 0, s>>>(a);
+        else if (listed && lay->phase_var[phase] == vcode(4, 4, true))
+            work_kernel<kHasLevelWide, LdsLevelsWide, vcode(4, 4, true)><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else if ((phase - 3) % 2 == 0) work_kernel<kHasLevel8, LdsLevels8><<<(unsigned)grid, kBlock, 0, s>>>(a);
         else work_kernel<kHasLevelWide, LdsLevelsWide><<<(unsigned)grid, kBlock, 0, s>>>(a);
     };

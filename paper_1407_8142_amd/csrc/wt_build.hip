@@ -484,7 +484,7 @@ __global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, 
 }
 
 template <typename TIN0, typename T>
-__global__ __launch_bounds__(kBlock) void fused_pass(FusedArgs f, uint64_t nseg) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void fused_pass(FusedArgs f, uint64_t nseg) {
     __shared__ LdsFused<T, kFusedBytes> s;
     for (uint64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
         fused_segment<TIN0, T, kFusedBytes>(f, seg, s);

@@ -1179,27 +1179,36 @@ __device__ __forceinline__ void level_dirs_tile(const LevelArgs &a, uint64_t til
 // (consecutive boundaries are at most kHalf apart) and no node of level l0
 // crosses it.  Deeper nodes refine those of level l0, so the segment stays
 // whole at every later level, and each block finds its own bounds by a
-// binary search over C.  One block loads its segment once and runs every
-// remaining level in LDS: the bits and directory entries of each level go
-// to HBM, the stable split goes from one LDS buffer to the other, and no
-// sequence traffic is left for those levels.  Destinations are those of
-// the global pass (the node tables), rebased to the segment; the zeros of a
-// level before the segment are the zeros before its first node, a table
-// entry.  A bit word shared with the neighbouring segment is cleared and
-// set over this segment's bit range only, with atomics (the two ranges are
-// disjoint, so the order of the two segments does not matter).
+// binary search over C (or takes them from a table).  One block loads its
+// segment once and runs every remaining level on it: the bits and
+// directory entries of each level go to HBM, and no sequence traffic is
+// left for those levels.  Destinations are those of the global pass (the
+// node tables), rebased to the segment; the zeros of a level before the
+// segment are the zeros before its first node, a table entry.  A bit word
+// shared with the neighbouring segment is cleared and set over this
+// segment's bit range only, with atomics (the two ranges are disjoint, so
+// the order of the two segments does not matter).
+//
+// The segment lives in registers between levels, in a frame of kCap
+// positions aligned to its first bit word (frame position a63 + j holds
+// position a + j): item r of thread t is frame position r*256 + t, so the
+// ballot of item r in wave w is the segment's bit word 4r + w, as in the
+// level pass's tile.  The split goes through one LDS stage and back.
 template <typename T, int kBytes>
 struct FusedCfg {
-    static constexpr int kCap = kBytes / (int)sizeof(T);  // positions of a segment, at most
-    static constexpr int kHalf = kCap / 2;                // segment stride
-    static constexpr int kVWords = kCap / 64 + 2;         // words a segment touches (its start is not aligned)
+    static constexpr int kCap = kBytes / (int)sizeof(T);  // frame positions
+    static constexpr int kHalf = kCap / 2 - 32;           // segment stride: a segment and its offset fit the frame
+    static constexpr int kVWords = kCap / 64;             // bit words of the frame
+    static constexpr int kItems = kCap / kBlock;          // frame positions per thread
+    static constexpr int kPer = 4 / (int)sizeof(T);       // items per packed register
+    static constexpr int kRegs = kItems / kPer;
 };
 
 constexpr int kFusedDCache = 512;  // node-table entries of a segment's key range kept in LDS
 
 template <typename T, int kBytes>
 struct LdsFused {
-    T buf[2][FusedCfg<T, kBytes>::kCap];
+    T stage[FusedCfg<T, kBytes>::kCap];
     uint64_t words[FusedCfg<T, kBytes>::kVWords];
     uint32_t zpre[FusedCfg<T, kBytes>::kVWords];  // zeros of the segment before each word
     uint64_t dcache[kFusedDCache];                // D_l[qlo + i]
@@ -1252,6 +1261,8 @@ __device__ __forceinline__ void node_max_range(const uint64_t *C, uint64_t sigma
 template <typename TIN0, typename T, int kBytes>
 __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, LdsFused<T, kBytes> &s) {
     using Cfg = FusedCfg<T, kBytes>;
+    constexpr int kIt = Cfg::kItems, kPer = Cfg::kPer, kRegs = Cfg::kRegs;
+    constexpr uint32_t kBitsPer = 8 * sizeof(T), kMask = (uint32_t)(((uint64_t)1 << kBitsPer) - 1);
     if (*f.status) return;
     const uint32_t L = f.L, l0 = *f.l0;
     if (l0 >= L) return;
@@ -1269,20 +1280,22 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
             const uint64_t step = (hi - lo + kWave - 1) / kWave;
             const uint64_t p = min(lo + (uint64_t)(lane + 1) * step, hi);
             const uint64_t ge = __ballot(Cc(p << shift) >= target);  // lane 63 probes hi: always set
-            const int f = __ffsll((unsigned long long)ge) - 1;
-            hi = min(lo + (uint64_t)(f + 1) * step, hi);
-            lo = f == 0 ? lo : lo + (uint64_t)f * step;
-            if (f == 0 && Cc(lo << shift) >= target) hi = lo;
+            const int fi = __ffsll((unsigned long long)ge) - 1;
+            hi = min(lo + (uint64_t)(fi + 1) * step, hi);
+            lo = fi == 0 ? lo : lo + (uint64_t)fi * step;
+            if (fi == 0 && Cc(lo << shift) >= target) hi = lo;
         }
         return Cc(lo << shift) >= target ? Cc(lo << shift) : Cc(hi << shift);
     };
     const uint64_t a = f.segb ? f.segb[seg] : boundary(seg * Cfg::kHalf);
     const uint64_t e = f.segb ? f.segb[seg + 1] : boundary((seg + 1) * Cfg::kHalf);
-    if (a >= e || e - a > (uint64_t)Cfg::kCap) return;  // empty (or tables inconsistent with the input)
+    const uint32_t a63 = (uint32_t)(a & 63);
+    if (a >= e || e - a + a63 > (uint64_t)Cfg::kCap) return;  // empty (or tables inconsistent with the input)
     const uint32_t m = (uint32_t)(e - a);
-    // The segment into LDS: the 16-byte vectors that cover [a, e), four per
-    // thread in flight at a time (the sequences are 16-byte aligned; a
-    // vector that runs past the sequence's end is read symbol by symbol).
+    // The segment into the stage at frame offset a63: the 16-byte vectors
+    // that cover [a, e), four per thread in flight at a time (the sequences
+    // are 16-byte aligned; a vector that runs past the sequence's end is
+    // read symbol by symbol).
     auto load_segment = [&](auto src_tag) {
         using TS = decltype(src_tag);
         constexpr int V = 16 / (int)sizeof(TS), kG = 4;
@@ -1317,7 +1330,7 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
 #pragma unroll
                     for (int x = 0; x < V; ++x) {
                         const uint64_t pos = (va + vi) * V + x;
-                        if (pos >= a && pos < e) s.buf[0][pos - a] = (T)u[r].x[x];
+                        if (pos >= a && pos < e) s.stage[pos - a + a63] = (T)u[r].x[x];
                     }
             }
         }
@@ -1325,7 +1338,25 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
     if (l0 == 0) load_segment(TIN0{});
     else load_segment(T{});
     __syncthreads();
-    const uint32_t a63 = (uint32_t)(a & 63);
+    // Registers: item r of this thread (frame position r*256 + tid), kPer
+    // items per register.  valid(r): the position is in the segment.
+    uint32_t pk[kRegs];
+    auto valid = [&](int r) { return (uint32_t)(r * kBlock + tid) - a63 < m; };
+    auto item = [&](int r) { return kPer == 1 ? pk[r] : (pk[r / kPer] >> (kBitsPer * (r % kPer))) & kMask; };
+    auto reload = [&]() {
+#pragma unroll
+        for (int g = 0; g < kRegs; ++g) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) {
+                const int r = g * kPer + x;
+                const uint32_t v = valid(r) ? (uint32_t)s.stage[r * kBlock + tid] : 0u;
+                w |= v << (kBitsPer * x);
+            }
+            pk[g] = w;
+        }
+    };
+    reload();
     const uint32_t nvw = (a63 + m + 63) / 64;
     const uint64_t gw0 = a >> 6;
     // Positions of word vw inside the segment; the segment that ends the
@@ -1349,8 +1380,8 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
     // D_{l+1}[4 pa - 1] (the first child may be empty: the zeros before an
     // empty node equal those before the next).
     constexpr int kPf = kFusedDCache / kBlock;  // window entries per thread
-    uint64_t pa = (uint64_t)((uint32_t)s.buf[0][0] >> (L - l0));  // nodes of level l0 the segment spans
-    uint64_t pz = (uint64_t)((uint32_t)s.buf[0][m - 1] >> (L - l0));
+    uint64_t pa = (uint64_t)((uint32_t)s.stage[a63] >> shift);  // nodes of level l0 the segment spans
+    uint64_t pz = (uint64_t)((uint32_t)s.stage[a63 + m - 1] >> shift);
     uint64_t Za = 0, qlo = 0, nq = 0;
     {
         const uint64_t *Dl = f.D + ((2ull << l0) - 2);
@@ -1361,10 +1392,9 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
             for (uint32_t i = tid; i < nq; i += kBlock) s.dcache[i] = Dl[qlo + i];
         }
     }
-    int cur = 0;
+    const uint64_t lt = lanemask_lt(lane);
     for (uint32_t l = l0; l < L; ++l) {
         const uint32_t k = L - 1 - l;
-        const T *A = s.buf[cur];
         const uint64_t *Dl = f.D + ((2ull << l) - 2);
         // Next level's table entries, in flight while this level runs.
         uint64_t ZaN = 0, qloN = 0, nqN = 0, pf[kPf];
@@ -1381,47 +1411,41 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
                 }
             }
         }
-        // 1. Bit words, wave w taking words w, w + 4, ...; zeros per word
-        //    (four words' symbols read before any is used).
-        constexpr int U1 = 4;
-        for (uint32_t vw0 = wave; vw0 < nvw; vw0 += kWaves * U1) {
-            uint32_t v[U1];
-            bool valid[U1];
+        // 1. Bit words straight from the registers: the ballot of item r in
+        //    wave w is word 4r + w; zeros per word.
 #pragma unroll
-            for (int u = 0; u < U1; ++u) {
-                const uint32_t vw = vw0 + u * kWaves;
-                const int32_t j = (int32_t)(vw * 64 + lane) - (int32_t)a63;
-                valid[u] = vw < nvw && j >= 0 && j < (int32_t)m;
-                v[u] = valid[u] ? (uint32_t)A[j] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < U1; ++u) {
-                const uint32_t vw = vw0 + u * kWaves;
-                if (vw < nvw) {
-                    const uint64_t wb = __ballot(valid[u] && ((v[u] >> k) & 1u));
-                    const uint64_t vb = __ballot(valid[u]);
-                    if (lane == 0) {
-                        s.words[vw] = wb;
-                        s.zpre[vw] = (uint32_t)(__popcll(vb) - __popcll(wb));
-                    }
-                }
+        for (int r = 0; r < kIt; ++r) {
+            const bool ok = valid(r);
+            const uint64_t wb = __ballot(ok && ((item(r) >> k) & 1u));
+            const uint64_t vb = __ballot(ok);
+            if (lane == 0) {
+                s.words[r * kWaves + wave] = wb;
+                s.zpre[r * kWaves + wave] = (uint32_t)(__popcll(vb) - __popcll(wb));
             }
         }
         __syncthreads();
-        // 2. Exclusive scan of the zero counts (two words per thread).
+        // 2. Exclusive scan of the zero counts of the segment's words.
         {
-            const uint32_t w0 = 2 * tid, w1 = 2 * tid + 1;
-            const uint32_t c0 = w0 < nvw ? s.zpre[w0] : 0u, c1 = w1 < nvw ? s.zpre[w1] : 0u;
-            const uint32_t own = c0 + c1;
+            constexpr int kWPT = (Cfg::kVWords + kBlock - 1) / kBlock;  // words per thread
+            uint32_t c[kWPT], own = 0;
+#pragma unroll
+            for (int x = 0; x < kWPT; ++x) {
+                const uint32_t w = kWPT * tid + x;
+                c[x] = w < nvw ? s.zpre[w] : 0u;
+                own += c[x];
+            }
             const uint32_t inc = wave_incl_scan_u32(own, lane);
             if (lane == kWave - 1) s.red[wave] = inc;
             __syncthreads();
-            uint32_t before = 0;
+            uint32_t ex = inc - own;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) before += w < wave ? s.red[w] : 0u;
-            const uint32_t ex = before + inc - own;
-            if (w0 < nvw) s.zpre[w0] = ex;
-            if (w1 < nvw) s.zpre[w1] = ex + c0;
+            for (int w = 0; w < kWaves; ++w) ex += w < wave ? s.red[w] : 0u;
+#pragma unroll
+            for (int x = 0; x < kWPT; ++x) {
+                const uint32_t w = kWPT * tid + x;
+                if (w < nvw) s.zpre[w] = ex;
+                ex += c[x];
+            }
             __syncthreads();
         }
         const uint32_t Zseg = s.red[0] + s.red[1] + s.red[2] + s.red[3];
@@ -1464,44 +1488,30 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
             }
         }
         if (l + 1 == L) break;
-        // 5. Stable split into the other buffer (the global pass's
-        //    destinations minus the segment start), four symbols per
-        //    thread at a time: their LDS reads issued before any is used.
-        T *Bn = s.buf[cur ^ 1];
-        constexpr int U5 = 4;
-        for (uint32_t j0 = tid; j0 < m; j0 += kBlock * U5) {
-            uint32_t v[U5], zl[U5];
-            uint64_t w[U5], dq[U5];
+        // 5. Stable split into the stage (free: the level is in registers),
+        //    at the global pass's destinations minus the segment start.
+        //    Destinations are below m < 2^32, so 32-bit wrapping arithmetic
+        //    gives them exactly: a zero goes to D[q] + Za + z - a, a one to
+        //    D[q] + j - Za - z (z: zeros of the segment before it).
+        const uint32_t add0 = (uint32_t)(Za - a), add1 = (uint32_t)(0 - Za);
 #pragma unroll
-            for (int u = 0; u < U5; ++u) {
-                const uint32_t j = j0 + u * kBlock;
-                v[u] = j < m ? (uint32_t)A[j] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < U5; ++u) {
-                const uint32_t j = j0 + u * kBlock, vw = (a63 + j) >> 6;
-                w[u] = j < m ? s.words[vw] : 0ull;
-                zl[u] = j < m ? s.zpre[vw] : 0u;
-                const uint64_t q = v[u] >> k;
-                dq[u] = j < m && q - qlo < nq ? s.dcache[q - qlo] : 0ull;
-            }
-#pragma unroll
-            for (int u = 0; u < U5; ++u) {
-                const uint32_t j = j0 + u * kBlock;
-                if (j < m) {
-                    const uint32_t pos = a63 + j, vw = pos >> 6, ln = pos & 63;
-                    const uint64_t before = vmask_of(vw) & ((1ull << ln) - 1ull);
-                    const uint64_t z = zl[u] + (uint64_t)__popcll(~w[u] & before);
-                    const uint64_t q = v[u] >> k;
-                    const uint64_t d = q - qlo < nq ? dq[u] : (q < (2ull << l) ? Dl[q] : ~0ull);
-                    const uint64_t dest = (q & 1u) ? d + j - Za - z : d + Za + z - a;
-                    if (dest < m) Bn[dest] = (T)v[u];
-                }
+        for (int r = 0; r < kIt; ++r) {
+            const bool ok = valid(r);
+            const uint32_t v = item(r), vw = (uint32_t)(r * kWaves + wave);
+            const uint64_t vb = __ballot(ok), word = s.words[vw];
+            const uint32_t z = s.zpre[vw] + (uint32_t)__popcll(~word & vb & lt);
+            const uint32_t j = (uint32_t)(r * kBlock + tid) - a63;
+            const uint64_t q = (uint64_t)(v >> k);
+            if (ok) {
+                const uint64_t d = q - qlo < nq ? s.dcache[q - qlo] : (q < (2ull << l) ? Dl[q] : ~0ull);
+                const uint32_t dest = (q & 1u) ? (uint32_t)d + j + add1 - z : (uint32_t)d + z + add0;
+                if (dest < m) s.stage[a63 + dest] = (T)v;
             }
         }
         __syncthreads();
-        // The next level's state: its window into the cache (free now; the
-        // next level's first barrier orders these writes before its split).
+        reload();
+        // The next level's state: its window into the cache (the next
+        // level's first barrier orders these writes before its split).
         if (l + 2 < L)
 #pragma unroll
             for (int r = 0; r < kPf; ++r) {
@@ -1511,9 +1521,8 @@ __device__ __forceinline__ void fused_segment(const FusedArgs &f, uint64_t seg, 
         Za = ZaN;
         qlo = qloN;
         nq = nqN;
-        pa = (uint64_t)((uint32_t)Bn[0] >> k);  // nodes of level l+1 (k_{l+1} = k - 1, node = symbol >> k)
-        pz = (uint64_t)((uint32_t)Bn[m - 1] >> k);
-        cur ^= 1;
+        pa = (uint64_t)((uint32_t)s.stage[a63] >> k);  // nodes of level l+1 (node = symbol >> k_{l+1} + 1 = symbol >> k)
+        pz = (uint64_t)((uint32_t)s.stage[a63 + m - 1] >> k);
     }
 }
 

@@ -108,7 +108,7 @@ class BatchLayout(ctypes.Structure):
                 ("off_segs", ctypes.c_uint64), ("off_seg_of", ctypes.c_uint64), ("off_list", ctypes.c_uint64),
                 ("njobs", ctypes.c_uint32),
                 ("nsegs", ctypes.c_uint32), ("items", ctypes.c_uint32), ("phases", ctypes.c_uint32),
-                ("phase_first", ctypes.c_uint32 * 72)]
+                ("phase_first", ctypes.c_uint32 * 72), ("phase_var", ctypes.c_uint32 * 72)]
 
 
 _lib = None
