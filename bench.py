@@ -309,8 +309,10 @@ def sort_leg(d_seq, n: int, sigma: int, L: int, steps: int, tree_ms: float):
                        "wt_build_sort (every level from S stably sorted by its top l bits) on the same input")
 
 
-def batch_leg(count: int, steps: int):
-    """Batched build vs one wt_build per sequence, same outputs, same GPU."""
+def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
+    """Batched build vs one wt_build per sequence, same outputs, same GPU.
+    ``tune`` (mode, blocks_per_cu, chunk) skips the autotuner; without the
+    per-sequence check only the batched build runs (for profiling it)."""
     import ctypes
 
     import torch
@@ -326,7 +328,10 @@ def batch_leg(count: int, steps: int):
     b.slab.fill_(-1)  # padding between buffers is never written: keep it equal in both runs
     log(f"[batch] {b.layout.items} work items, scratch {b.layout.scratch_bytes / 2**30:.2f} GiB, "
         f"outputs {b.slab.numel() * 8 / 2**30:.2f} GiB; autotuning")
-    best, table = autotune.autotune(b)
+    if tune is None:
+        best, table = autotune.autotune(b)
+    else:
+        best, table = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), []
     log(f"[batch] best tune {best.as_dict()}: " + ", ".join(f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/"
                                                            f"{r['tune']['chunk']}={r['ms']}" for r in table))
     stream = torch.cuda.Stream()
@@ -352,6 +357,12 @@ def batch_leg(count: int, steps: int):
     e1.record(cur)
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / steps
+    model = batch_model_bytes(jobs)
+    if not per_seq_check:
+        log(f"[batch] batched {batch_ms:.3f} ms ({best.as_dict()})")
+        return {"ms_per_step": batch_ms, "value": sym_lvl / (batch_ms / 1e3), "unit": "symbols*levels/s",
+                "tune": best.as_dict(), "model_bytes": model,
+                "model_frac_of_hbm_peak": model / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
     want = b.slab.clone()
 
     # One wt_build per sequence into the same output buffers, one scratch
@@ -383,7 +394,6 @@ def batch_leg(count: int, steps: int):
     per_seq_ms = e0.elapsed_time(e1) / reps
     per_seq_wall_ms = (time.perf_counter() - w0) * 1e3 / reps
     identical = bool(torch.equal(b.slab, want))
-    model = batch_model_bytes(jobs)
     log(f"[batch] batched {batch_ms:.3f} ms, per-sequence {per_seq_ms:.3f} ms (wall {per_seq_wall_ms:.3f}), "
         f"identical={identical}")
     return {
@@ -472,6 +482,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-build comparison")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched build (no per-sequence comparison) and print its object")
+    ap.add_argument("--batch-tune", default=None, help="MODE,BLOCKS_PER_CU,CHUNK instead of autotuning")
     ap.add_argument("--no-alphabets", action="store_true",
                     help="skip the large-alphabet builds (n = 2^27 32-bit symbols, sigma 2^16 and 2^20)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -490,6 +503,10 @@ def main():
 
     from paper_1407_8142_amd import inputs, wt
 
+    batch_tune = tuple(int(x) for x in args.batch_tune.split(",")) if args.batch_tune else None
+    if args.batch_only:
+        print(json.dumps(batch_leg(args.batch_count, args.batch_steps, batch_tune, per_seq_check=False)), flush=True)
+        return
     desc, n_default = WORKLOADS[args.workload]
     n = args.n or n_default
     log(f"[bench] generating {args.workload} n={n}")
@@ -597,7 +614,7 @@ def main():
     alphabets = None
     if not args.no_alphabets and args.workload == "text256":
         alphabets = {w: alphabet_leg(w, 10, 10) for w in ("alpha16", "alpha20")}
-    batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps)
+    batch = None if args.no_batch else batch_leg(args.batch_count, args.batch_steps, batch_tune)
     served = None if args.no_serve else serve_leg(args.serve_seconds, args.serve_budget_gb, args.serve_pool,
                                                   args.serve_h2d_seconds, args.serve_h2d_pool)
 

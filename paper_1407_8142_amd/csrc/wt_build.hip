@@ -338,6 +338,72 @@ __global__ __launch_bounds__(kScanThreads) void tile_prefix_scan(const uint32_t 
     }
 }
 
+// The same prefix over many tiles in one pass of several blocks: block b
+// scans counts [4096 b, 4096 b + 4096) and takes the zeros before them from
+// its predecessors' published totals (decoupled look-back with fallback;
+// `state` holds one word per block and is zeroed with the counts).
+constexpr int kTpItems = 16, kTpSpan = kBlock * kTpItems;  // tiles per block
+__global__ __launch_bounds__(kBlock) void tile_prefix_multi(const uint32_t *cnt, uint64_t *pre, uint64_t T,
+                                                            uint64_t *state, int spin_limit) {
+    __shared__ uint32_t s_w[kWaves];
+    __shared__ uint64_t s_excl;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint64_t blk = blockIdx.x, base = blk * kTpSpan + (uint64_t)tid * kTpItems;
+    uint32_t v[kTpItems], own = 0;
+    if (base + kTpItems <= T) {
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(cnt + base);
+#pragma unroll
+        for (int q = 0; q < kTpItems / 4; ++q) {
+            const uint4 x = p4[q];
+            v[4 * q] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kTpItems; ++j) v[j] = base + j < T ? cnt[base + j] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kTpItems; ++j) own += v[j];
+    const uint32_t inc = wave_incl_scan_u32(own, lane);
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t x = s_w[w];
+        before += w < wave ? x : 0u;
+        total += x;
+    }
+    if (wave == 0) {
+        auto agg_of = [&](uint64_t b) -> uint64_t {  // a predecessor's total, recounted
+            uint64_t t = 0;
+            for (uint64_t i = b * kTpSpan + lane; i < min((b + 1) * kTpSpan, T); i += kWave) t += cnt[i];
+            return wave_sum_u64(t);
+        };
+        const uint64_t ex = lookback_exclusive<1>(state, blk, total, lane, spin_limit, agg_of);
+        if (lane == 0) s_excl = ex;
+    }
+    __syncthreads();
+    uint64_t run = s_excl + before + inc - own;
+    uint64_t o[kTpItems];
+#pragma unroll
+    for (int j = 0; j < kTpItems; ++j) {
+        o[j] = run;
+        run += v[j];
+    }
+    if (base + kTpItems <= T) {
+        ulonglong2 *q2 = reinterpret_cast<ulonglong2 *>(pre + base);
+#pragma unroll
+        for (int q = 0; q < kTpItems / 2; ++q) q2[q] = make_ulonglong2(o[2 * q], o[2 * q + 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kTpItems; ++j)
+            if (base + j < T) pre[base + j] = o[j];
+    }
+}
+
 // Generic reduce-then-scan over values produced by a functor, cut into
 // chunks of kScanChunk elements; exclusive sums restart at segment heads
 // (the node tables use one segment per level).
@@ -475,8 +541,9 @@ __global__ __launch_bounds__(kBlock) void node_max_kernel(const uint64_t *C, uin
     __shared__ unsigned long long red[32];
     if (threadIdx.x < 32) red[threadIdx.x] = 0;
     __syncthreads();
-    node_max_range(C, sigma, L, 1 + (uint64_t)blockIdx.x * kBlock, 1ull << L, (uint64_t)gridDim.x * kBlock, red,
-                   maxnode);
+    // Levels 0..L-2: fusion starts at L-2 at the latest.
+    node_max_range(C, sigma, L, 1 + (uint64_t)blockIdx.x * kBlock, 1ull << (L - 1), (uint64_t)gridDim.x * kBlock,
+                   red, maxnode);
 }
 
 __global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, uint64_t half, uint32_t *l0) {
@@ -486,6 +553,7 @@ __global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, 
 template <typename TIN0, typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void fused_pass(FusedArgs f, uint64_t nseg) {
     __shared__ LdsFused<T, kFusedBytes> s;
+    if (*f.l0 >= f.L) return;  // the plan found no level to fuse
     for (uint64_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
         fused_segment<TIN0, T, kFusedBytes>(f, seg, s);
         __syncthreads();
@@ -670,6 +738,7 @@ struct Plan {
     uint32_t L, in_bytes, mid_bytes;
     uint64_t W, T, rank_len, cap;
     uint64_t off_status, off_cnt, off_pre, off_D, off_part, off_E, off_M, off_S0, off_S1, total;
+    uint64_t off_lbs, LB;             // look-back state of the tile-prefix pass, words per level
     uint64_t off_PZ, off_NZ, off_CL;  // byte alphabets: piece counts, node zeros, node starts (wt_stats.hpp)
     uint64_t PS;                      // piece counts per level
     bool sparse;                      // node tables over the nonempty nodes only (wt_sparse.hpp)
@@ -718,6 +787,9 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
     const uint64_t Lt = p.L + (p.L & 1u);
     p.off_cnt = o;  // zeros per tile, per level (count-ahead), zeroed each build
     o = align_up(o + 4ull * Lt * p.T, 256);
+    p.LB = cdiv(p.T, kTpSpan) + 1;  // look-back words per level of the tile-prefix pass
+    p.off_lbs = o;                  // zeroed with the counts (it lies before off_pre)
+    o = align_up(o + 8ull * p.L * p.LB, 256);
     p.off_pre = o;  // exclusive zero prefix per tile, per level
     o = align_up(o + 8ull * Lt * p.T, 256);
     p.off_D = o;
@@ -764,6 +836,19 @@ static thread_local bool g_fuse = true;
 static thread_local bool g_slices = true;  // sliced LDS histogram for wide alphabets
 static thread_local bool g_pairs = false;  // two levels per pass for byte alphabets (measured slower: see wt_set_level_pairs)
 static thread_local int g_spin_limit = 8;
+
+// Tile prefixes of level l from the counts its predecessor left: one block
+// when they fit one, else the multi-block pass.
+static void tile_prefixes(const Plan &p, unsigned char *sc, uint32_t l, uint64_t Tl, hipStream_t s) {
+    const uint32_t *cnt = (const uint32_t *)(sc + p.off_cnt) + (uint64_t)l * p.T;
+    uint64_t *pre = (uint64_t *)(sc + p.off_pre) + (uint64_t)l * p.T;
+    if (Tl <= (uint64_t)kTpSpan) {
+        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt, pre, Tl);
+    } else {
+        uint64_t *state = (uint64_t *)(sc + p.off_lbs) + (uint64_t)l * p.LB;
+        tile_prefix_multi<<<(unsigned)cdiv(Tl, kTpSpan), kBlock, 0, s>>>(cnt, pre, Tl, state, g_spin_limit);
+    }
+}
 constexpr uint64_t kOffMaxNode = 8;   // in the status block: largest node per level (u64 x 30)
 constexpr uint64_t kOffFusedL0 = 248; // in the status block: first fused level (u32)
 
@@ -1118,7 +1203,7 @@ static int run_pairs(const void *d_seq, const Plan &p, const wt_outputs *out, un
                 buf ^= 1;
             }
         } else {
-            tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
+            tile_prefixes(p, sc, l, Tl, s);
             LevelArgs a;
             a.in = cur;
             a.out = nullptr;
@@ -1320,7 +1405,7 @@ static int run_sparse(const void *d_seq, const Plan &p, const wt_outputs *out, u
         if ((rc = sparse_tables(p, out, sc, l, s))) return rc;
         const bool scatter = l + 1 < p.L;
         void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
-        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
+        tile_prefixes(p, sc, l, Tl, s);
         LevelArgs a;
         a.in = cur;
         a.out = scatter ? dst : nullptr;
@@ -1443,7 +1528,7 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
         if (matrix) matrix_tables<<<1, kWave, 0, s>>>(D, p.L, Dm, d_zeros);
         if (fuse) {
             unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
-            const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << p.L, kBlock), 2048));
+            const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << (p.L - 1), kBlock), 2048));
             node_max_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(out->C, sigma, p.L, maxnode);
             fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), fused_l0);
         }
@@ -1510,7 +1595,7 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
         void *dst = (l % 2 == 0) ? (void *)(sc + p.off_S0) : (void *)(sc + p.off_S1);
         // Tile prefixes of this level from the counts its predecessor left.
         const uint64_t Tl = cdiv(n, 1ull << tile_shift_for(cur_w));
-        tile_prefix_scan<<<1, kScanThreads, 0, s>>>(cnt + (uint64_t)l * p.T, pre + (uint64_t)l * p.T, Tl);
+        tile_prefixes(p, sc, l, Tl, s);
         LevelArgs a;
         a.in = cur;
         a.out = scatter ? dst : nullptr;

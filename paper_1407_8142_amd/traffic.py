@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 PROBE = os.path.join(HERE, "bw_probe")
 LEVEL_PASS_SOURCES = [os.path.join(HERE, "csrc", f)
-                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp")]
+                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp", "wt_stats.hpp")]
 PROBE_MIB = 1024
 
 
@@ -68,7 +68,7 @@ def main():
     os.makedirs(args.out, exist_ok=True)
     probe_cmd = [PROBE, str(PROBE_MIB), "3"]
     bench_cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--workload", args.workload, "--steps", "2",
-                 "--warmup", "1", "--no-cpu-baseline", "--no-batch", "--no-serve", "--no-matrix"]
+                 "--warmup", "1", "--no-cpu-baseline", "--no-batch", "--no-serve", "--no-matrix", "--no-alphabets"]
     known = PROBE_MIB * 1024.0  # KiB read and written by one copy launch
     cf = run_pass("FETCH_SIZE", probe_cmd, args.out, "copy_fetch")
     cw = run_pass("WRITE_SIZE", probe_cmd, args.out, "copy_write")
@@ -80,7 +80,7 @@ def main():
     bw = run_pass("WRITE_SIZE", bench_cmd, args.out, "lp_write")
     kernels = {}
     for k in sorted(set(bf) | set(bw)):
-        if not is_level_pass(k) and "histogram" not in k:
+        if not is_level_pass(k) and not any(x in k for x in ("histogram", "stats_prep", "stats_scan", "level_dirs")):
             continue
         f = bf.get(k, [0.0])
         w = bw.get(k, [0.0])
