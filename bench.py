@@ -329,11 +329,13 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
     log(f"[batch] {b.layout.items} work items, scratch {b.layout.scratch_bytes / 2**30:.2f} GiB, "
         f"outputs {b.slab.numel() * 8 / 2**30:.2f} GiB; autotuning")
     if tune is None:
-        best, table = autotune.autotune(b)
+        best, table, fused = autotune.autotune(b)
     else:
-        best, table = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), []
-    log(f"[batch] best tune {best.as_dict()}: " + ", ".join(f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/"
-                                                           f"{r['tune']['chunk']}={r['ms']}" for r in table))
+        best, table, fused = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), [], True
+        wt.set_fused_levels(True)
+    log(f"[batch] best tune {best.as_dict()} fused={fused}: " + ", ".join(
+        f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/{r['tune']['chunk']}/{int(r['fused'])}={r['ms']}"
+        for r in table))
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -357,11 +359,12 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
     e1.record(cur)
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / steps
+    wt.set_fused_levels(True)  # the captured graph keeps the tuned setting; later builds take the default
     model = batch_model_bytes(jobs)
     if not per_seq_check:
         log(f"[batch] batched {batch_ms:.3f} ms ({best.as_dict()})")
         return {"ms_per_step": batch_ms, "value": sym_lvl / (batch_ms / 1e3), "unit": "symbols*levels/s",
-                "tune": best.as_dict(), "model_bytes": model,
+                "tune": best.as_dict(), "fused_tail_levels": fused, "model_bytes": model,
                 "model_frac_of_hbm_peak": model / (batch_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
     want = b.slab.clone()
 
@@ -403,7 +406,7 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
         "value": sym_lvl / (batch_ms / 1e3), "unit": "symbols*levels/s", "ms_per_step": batch_ms,
         "steps": steps, "launch": "wt_batch_run captured in one graph (" + (
             "one persistent work-queue launch" if best.mode == wt.BATCH_PERSISTENT else "one launch per phase")
-        + " + a clearing kernel)", "tune": best.as_dict(), "autotune": table,
+        + " + a clearing kernel)", "tune": best.as_dict(), "fused_tail_levels": fused, "autotune": table,
         "per_seq": {"value": sym_lvl / (per_seq_ms / 1e3), "ms_per_step": per_seq_ms,
                     "wall_ms_per_step": per_seq_wall_ms, "launch": "one wt_build per sequence on one stream"},
         "speedup_vs_per_seq": per_seq_ms / batch_ms, "bit_exact_vs_per_seq": identical,
