@@ -331,10 +331,10 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
     if tune is None:
         best, table, fused = autotune.autotune(b)
     else:
-        best, table, fused = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), [], True
-        wt.set_fused_levels(True)
+        best, table, fused = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), [], 1
+        wt.set_fused_levels(1)
     log(f"[batch] best tune {best.as_dict()} fused={fused}: " + ", ".join(
-        f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/{r['tune']['chunk']}/{int(r['fused'])}={r['ms']}"
+        f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/{r['tune']['chunk']}/f{int(r['fused'])}={r['ms']}"
         for r in table))
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
@@ -359,7 +359,7 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
     e1.record(cur)
     torch.cuda.synchronize()
     batch_ms = e0.elapsed_time(e1) / steps
-    wt.set_fused_levels(True)  # the captured graph keeps the tuned setting; later builds take the default
+    wt.set_fused_levels(1)  # the captured graph keeps the tuned setting; later builds take the default
     model = batch_model_bytes(jobs)
     if not per_seq_check:
         log(f"[batch] batched {batch_ms:.3f} ms ({best.as_dict()})")

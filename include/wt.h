@@ -452,12 +452,15 @@ int wt_query_multi(const wt_view *d_views, uint32_t ntrees, const uint32_t *d_tr
  * launches made from the thread that set it, and other threads keep their
  * own values (defaults as stated). */
 
-/* Fused tail levels (on by default).  Once every node of a level fits in one
- * block's LDS, wt_build and wt_batch_run run that level and all deeper ones
- * in LDS, one node-aligned segment per block (no sequence traffic for those
- * levels); outputs are identical either way.  0 turns it off for later
- * launches (for comparisons). */
-int wt_set_fused_levels(int enable);
+/* Fused tail levels (levels = 1 by default).  Once every node of a level
+ * fits one block's segment, wt_build and wt_batch_run run that level and all
+ * deeper ones on chip, one node-aligned segment per block (no sequence
+ * traffic for those levels); outputs are identical whatever the setting.
+ *   0       no fused levels;
+ *   1       from the first level whose nodes fit;
+ *   m >= 2  at most the last m levels (from level max(first fitting, L - m)).
+ * WT_ERR_ARG for a negative value. */
+int wt_set_fused_levels(int levels);
 
 /* Wide-alphabet histogram (on by default).  For sigma > 8192, wt_build counts
  * symbols in 2^16-symbol slices of packed 16-bit LDS counters, one row of

@@ -4,8 +4,8 @@ candidate wt_tune on the batch itself and keeps the fastest.
 The tunables are the launch form (one persistent launch over the whole
 queue, or one launch per phase), the resident blocks per CU of the work
 kernel, the work items taken per queue access, and the levels per LDS pass:
-each job's tail levels fused in LDS once its nodes fit a segment, or every
-level a pass of its own (`wt.set_fused_levels`).  The tile shape (16 KiB per
+each job's tail levels fused on chip once its nodes fit a segment, at most
+the last m of them, or every level a pass of its own (`wt.set_fused_levels`).  The tile shape (16 KiB per
 tile, 256 threads, so 16/8/4 symbols per thread at 1/2/4 bytes) is a
 compile-time constant of the kernels: their LDS layouts, register tiles and
 unrolled loops are sized by it.  Every candidate produces the same outputs
@@ -20,10 +20,11 @@ import torch
 
 from . import wt
 
-# (launch form, blocks per CU, chunk, fused tail levels)
-DEFAULT_CANDIDATES = ([(wt.BATCH_PERSISTENT, bpc, chunk, True) for bpc, chunk in ((0, 1), (4, 4))] +
-                      [(wt.BATCH_PER_PHASE, bpc, chunk, fused)
-                       for bpc in (0, 4) for chunk in (1, 4) for fused in (True, False)])
+# (launch form, blocks per CU, chunk, fused tail levels: 0 none, 1 all that
+# fit, m >= 2 at most the last m)
+DEFAULT_CANDIDATES = ([(wt.BATCH_PERSISTENT, bpc, chunk, 1) for bpc, chunk in ((0, 1), (4, 4))] +
+                      [(wt.BATCH_PER_PHASE, bpc, chunk, 1) for bpc, chunk in ((0, 4), (4, 4))] +
+                      [(wt.BATCH_PER_PHASE, bpc, 1, fused) for bpc in (0, 4) for fused in (1, 0, 8, 6, 4)])
 
 
 def time_run(batch: "wt.Batch", tune: "wt.Tune", reps: int = 3) -> float:
@@ -68,7 +69,7 @@ def autotune(batch: "wt.Batch", candidates=None, reps: int = 3, cache_path: str 
                 raise RuntimeError(f"batch failed under {t.as_dict()}: {wt.STATUS_NAMES.get(rc, rc)}")
             table.append({"tune": t.as_dict(), "fused": fused, "ms": round(ms, 4)})
     finally:
-        wt.set_fused_levels(True)
+        wt.set_fused_levels(1)
     best = min(table, key=lambda r: r["ms"])
     wt.set_fused_levels(best["fused"])
     if cache_path and key:

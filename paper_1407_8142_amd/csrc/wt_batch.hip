@@ -121,7 +121,7 @@ struct Args {
     uint32_t chunk;          // items taken per queue access
     uint32_t spin_limit;
     uint32_t fenced;         // items of one launch depend on each other's writes
-    uint32_t fuse;           // run the tail levels of a job fused in LDS once its nodes fit
+    uint32_t fuse;           // tail levels fused in LDS once a job's nodes fit: 0 none, 1 all, m >= 2 at most m
     // Per-phase launches: every level and fused launch takes its items from
     // a list of the live ones, (job, tile or segment), that the tables phase
     // (level 0, fused segments) and the level set-up launches (level l >= 1)
@@ -636,7 +636,7 @@ __device__ __forceinline__ void fused_segments(const JobDev &j, uint32_t l0, con
 // tails, level-0 tile prefixes and the first fused level of one job.  N:
 // values per thread in the block scans (more is faster, and costs registers).
 template <int N>
-__device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fuse, const Args &b) {
+__device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, uint32_t fuse, const Args &b) {
     BlockScanTmp &tmp = lp.scan;
     if (!__hip_atomic_load(j.ctl + kCtlCDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         const uint64_t total = block_scan_all<N>(
@@ -653,7 +653,7 @@ __device__ __forceinline__ void prep_item(const JobDev &j, LdsPrep &lp, bool fus
                  threadIdx.x, kBlock);
     tile_prefix_block(j.cnt, j.pre, j.T0, tmp);
     uint32_t l0 = j.L;
-    if (fuse && j.L >= 2 && j.n > 0) l0 = fused_from(lp.lmax, j.L, fused_half(j.mid_bytes));
+    if (fuse && j.L >= 2 && j.n > 0) l0 = fused_from(lp.lmax, j.L, fused_half(j.mid_bytes), fuse);
     if (threadIdx.x == 0) j.ctl[kCtlFusedL0] = l0;
     if (l0 < j.L) fused_segments(j, l0, b, lp);
     if (b.list && j.n > 0 && l0 > 0) {
@@ -788,8 +788,8 @@ __device__ __forceinline__ void run_item(const Args &b, uint32_t it, LDS &s, uin
     } else if (kind == kKindPrep) {
         if constexpr ((KINDS & kHasPrep) != 0) {
             wait_for(b, ctl + kCtlDone, j.hist_items, ctl + kCtlStatus);
-            if constexpr (KINDS == kHasAll) prep_item<4>(j, s.prep, b.fuse != 0, b);
-            else prep_item<4>(j, s, b.fuse != 0, b);
+            if constexpr (KINDS == kHasAll) prep_item<4>(j, s.prep, b.fuse, b);
+            else prep_item<4>(j, s, b.fuse, b);
             publish(b, ctl + kCtlReady);
         }
     } else if (kind == kKindFused) {
@@ -1187,7 +1187,7 @@ extern "C" int wt_batch_run(const wt_batch_layout *lay, const wt_tune *tune, voi
     a.chunk = chunk;
     a.spin_limit = spin;
     a.fenced = t.mode == WT_BATCH_PERSISTENT ? 1u : 0u;
-    a.fuse = fused_levels_enabled() ? 1u : 0u;
+    a.fuse = fused_levels_setting();
     const uint32_t last = lay->phases - 1;
     // Lists of live items (per-phase launches only).
     a.list = a.fenced ? nullptr : (uint2 *)(sc + lay->off_list);

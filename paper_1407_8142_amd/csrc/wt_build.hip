@@ -546,8 +546,9 @@ __global__ __launch_bounds__(kBlock) void node_max_kernel(const uint64_t *C, uin
                    red, maxnode);
 }
 
-__global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, uint64_t half, uint32_t *l0) {
-    if (threadIdx.x == 0) *l0 = fused_from(reinterpret_cast<const uint64_t *>(maxnode), L, half);
+__global__ void fuse_plan_kernel(const unsigned long long *maxnode, uint32_t L, uint64_t half, uint32_t most,
+                                 uint32_t *l0) {
+    if (threadIdx.x == 0) *l0 = fused_from(reinterpret_cast<const uint64_t *>(maxnode), L, half, most);
 }
 
 template <typename TIN0, typename T>
@@ -832,7 +833,7 @@ static int make_plan(uint64_t n, uint64_t sigma, int sym_bytes, Plan &p) {
 // caller that changes one for a comparison does not change the builds of
 // other threads.
 static thread_local bool g_timing = false;
-static thread_local bool g_fuse = true;
+static thread_local uint32_t g_fuse = 1;  // wt_set_fused_levels
 static thread_local bool g_slices = true;  // sliced LDS histogram for wide alphabets
 static thread_local bool g_pairs = false;  // two levels per pass for byte alphabets (measured slower: see wt_set_level_pairs)
 static thread_local int g_spin_limit = 8;
@@ -1107,7 +1108,7 @@ static PathChoice choose_path(const Plan &p, bool matrix, bool dirs) {
     // passes without the per-tile check of the fused level.
     c.lmin = 0;
     while (c.lmin < 63 && cdiv(n, 1ull << c.lmin) > fused_half(p.mid_bytes)) ++c.lmin;
-    c.fuse = g_fuse && !matrix && !p.sparse && dirs && p.L >= 2 && n > 0 && c.lmin + 2 <= p.L;
+    c.fuse = g_fuse != 0 && !matrix && !p.sparse && dirs && p.L >= 2 && n > 0 && c.lmin + 2 <= p.L;
     // Two levels per pass: byte symbols in and between levels, nothing fused
     // (inputs too small for that are the fused pass's), 32-bit positions.
     c.pairs = g_pairs && !matrix && !c.fuse && p.in_bytes == 1 && p.mid_bytes == 1 && p.L >= 2 && n > 0 &&
@@ -1530,7 +1531,7 @@ static int build_impl(const void *d_seq, uint64_t n, uint64_t sigma, int sym_byt
             unsigned long long *maxnode = (unsigned long long *)(sc + p.off_status + kOffMaxNode);
             const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>(cdiv(1ull << (p.L - 1), kBlock), 2048));
             node_max_kernel<<<(unsigned)blocks, kBlock, 0, s>>>(out->C, sigma, p.L, maxnode);
-            fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), fused_l0);
+            fuse_plan_kernel<<<1, kWave, 0, s>>>(maxnode, p.L, fused_half(p.mid_bytes), g_fuse, fused_l0);
         }
     };
     auto c_scan = [&]() {
@@ -1988,10 +1989,11 @@ extern "C" int wt_status_get(const void *d_scratch, void *stream) {
     return st == 0 ? WT_OK : (st == kStatusSymbol ? WT_ERR_SYMBOL : WT_ERR_HIP);
 }
 
-bool wt::fused_levels_enabled() { return g_fuse; }
+uint32_t wt::fused_levels_setting() { return g_fuse; }
 
-extern "C" int wt_set_fused_levels(int enable) {
-    g_fuse = enable != 0;
+extern "C" int wt_set_fused_levels(int levels) {
+    if (levels < 0) return WT_ERR_ARG;
+    g_fuse = (uint32_t)levels;
     return WT_OK;
 }
 

@@ -22,8 +22,9 @@ constexpr int kScanChunk = kBlock * kItems;  // elements per block in the generi
 
 constexpr uint32_t kStatusSymbol = 2u;
 
-// Host switch of the fused tail levels (wt_set_fused_levels).
-bool fused_levels_enabled();
+// Host switch of the fused tail levels (wt_set_fused_levels): 0 none, 1 from
+// the first level whose nodes fit, m >= 2 at most the last m levels.
+uint32_t fused_levels_setting();
 
 __host__ __device__ inline uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline uint64_t align_up(uint64_t a, uint64_t b) { return cdiv(a, b) * b; }
@@ -1234,9 +1235,14 @@ struct FusedArgs {
 // First fused level from the largest node of each level: the first level
 // whose nodes all fit in kHalf positions, if it leaves a split to do
 // (l0 <= L-2); L otherwise.
-__device__ __forceinline__ uint32_t fused_from(const uint64_t *maxnode, uint32_t L, uint64_t half) {
+__device__ __forceinline__ uint32_t fused_from(const uint64_t *maxnode, uint32_t L, uint64_t half,
+                                               uint32_t most = 1) {
     for (uint32_t l = 0; l + 2 <= L; ++l)
-        if (maxnode[l] <= half) return l;
+        if (maxnode[l] <= half) {
+            // at most the last `most` levels when most >= 2
+            const uint32_t from = most >= 2 && most < L && l < L - most ? L - most : l;
+            return from + 2 <= L ? from : L;
+        }
     return L;
 }
 

@@ -581,8 +581,10 @@ def build_rank_select(bits: torch.Tensor, n: int, L: int, stream=None) -> dict:
     return {"rank": rank, "sel1": sel1, "sel0": sel0, "sel_counts": counts, "_scratch": scratch}
 
 
-def set_fused_levels(on: bool):
-    _check(lib().wt_set_fused_levels(1 if on else 0), "wt_set_fused_levels")
+def set_fused_levels(levels):
+    """0/False: no fused levels; 1/True: from the first level whose nodes fit;
+    m >= 2: at most the last m levels (this host thread's later launches)."""
+    _check(lib().wt_set_fused_levels(int(levels)), "wt_set_fused_levels")
 
 
 def histogram_path(n: int, sigma: int, sym_bytes: int) -> int:

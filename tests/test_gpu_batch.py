@@ -214,3 +214,19 @@ def test_batch_empty_and_single(wtmod, oracle_mod):
     b.run(wtmod.Tune(mode=wtmod.BATCH_PER_PHASE))
     torch.cuda.synchronize()
     check_batch(wtmod, oracle_mod, b, [(S, 256)], "single text job")
+
+
+@pytest.mark.parametrize("levels", [0, 3, 1])
+def test_batch_fused_levels_setting(wtmod, oracle_mod, levels):
+    """No fused levels, at most the last three, or all that fit: the same
+    buffers as the oracle's in every case."""
+    jobs = mixed_jobs(seed=14)
+    say(f"[batch] fused levels setting {levels}")
+    b, _ = make_batch(wtmod, jobs)
+    try:
+        wtmod.set_fused_levels(levels)
+        b.run(wtmod.Tune(mode=wtmod.BATCH_PER_PHASE))
+        torch.cuda.synchronize()
+    finally:
+        wtmod.set_fused_levels(1)
+    check_batch(wtmod, oracle_mod, b, jobs, f"fused levels {levels}")

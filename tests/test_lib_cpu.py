@@ -136,7 +136,7 @@ def test_batch_plan_queue_shape():
     alphabet needs packed LDS bins (5120 <= sigma <= 2^16), one table item
     per job, then per level the byte-symbol tiles and the wider tiles of
     every job that has that level (16 KiB tiles), then one fused-segment item
-    per 8 KiB of positions at the job's narrowed width."""
+    per (8 KiB - 32 positions) at the job's narrowed width (the segment stride)."""
     spec = [(0, 4, 1), (1, 1, 1), (100000, 256, 1), (20000, 1 << 16, 2), (5000, 1 << 20, 4), (70000, 5, 1),
             (30000, 6000, 2), (9000, 200, 4)]
     lay = wt.batch_plan([_job(*s) for s in spec])
@@ -151,7 +151,7 @@ def test_batch_plan_queue_shape():
         for wide in (False, True):
             per_phase.append(sum(tiles(n, b if l == 0 else mid(L(s))) for n, s, b in spec
                                  if n and l < L(s) and ((b if l == 0 else mid(L(s))) > 1) == wide))
-    fused = sum(-(-n // (8192 // mid(L(s)))) for n, s, b in spec if n and L(s) >= 2)
+    fused = sum(-(-n // (8192 // mid(L(s)) - 32)) for n, s, b in spec if n and L(s) >= 2)
     assert lay.njobs == len(spec)
     assert lay.phases == 3 + len(per_phase) + 1
     assert lay.items == hist + jh + len(spec) + sum(per_phase) + fused
@@ -318,3 +318,18 @@ def test_sparse_tables_keep_scratch_small(n, sigma):
     dense_words = 2 << lay.L
     assert lay.scratch_bytes < 8 * dense_words or lay.L > 30
     assert lay.scratch_bytes <= 2 * 4 * n + 64 * n + (64 << 20)
+
+
+def test_fused_levels_setting():
+    """wt_set_fused_levels takes 0 (none), 1 (every level from the first whose
+    nodes fit) or m >= 2 (at most the last m levels); a negative value is an
+    argument error and leaves the setting alone."""
+    lib = wt.lib()
+    try:
+        for v in (0, 1, 2, 6, 40):
+            assert lib.wt_set_fused_levels(v) == wt.WT_OK
+        assert lib.wt_set_fused_levels(-1) == wt.WT_ERR_ARG
+        with pytest.raises(Exception):
+            wt.set_fused_levels(-3)
+    finally:
+        wt.set_fused_levels(1)
