@@ -62,10 +62,11 @@ constexpr int kFusedBytes = 16384;                                  // per LDS b
 constexpr uint32_t kJobHistMaxSigma = 65536;  // packed 16-bit LDS bins of one block (128 KiB)
 
 // Item kinds a kernel is built for: each phase of the per-phase launch gets
-// a kernel with only its own kind (its own LDS and registers); the
+// a kernel with only its own kind (its own LDS and registers; the whole-job
+// histograms, bit 2, have a kernel of their own, job_hist_kernel); the
 // persistent launch gets one with every kind.
-constexpr uint32_t kHasTileHist = 1, kHasJobHist = 2, kHasPrep = 4, kHasLevel8 = 8, kHasLevelWide = 16,
-                   kHasFused = 32, kHasAll = 63;
+constexpr uint32_t kHasTileHist = 1, kHasPrep = 4, kHasLevel8 = 8, kHasLevelWide = 16, kHasFused = 32,
+                   kHasAll = 63;
 constexpr uint32_t kHasLevel = kHasLevel8 | kHasLevelWide;
 
 // Tile variants of the level pass: input and output widths and whether it
