@@ -35,7 +35,7 @@ METRIC = "symbols*levels/s and % HBM peak; batched vs per-seq builds, bit-exact"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level_pass.json")
 LEVEL_PASS_SOURCES = [os.path.join(ROOT, "paper_1407_8142_amd", "csrc", f)
-                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp")]
+                      for f in ("wt_build.hip", "wt_kernels.hpp", "wt_device.hpp", "wt_pair.hpp", "wt_stats.hpp")]
 
 WORKLOADS = {
     "text256": ("text-like: n=2^28 uint8, sigma=256, Zipf(1.1) over a permuted byte alphabet, geometric runs "
