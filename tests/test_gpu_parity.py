@@ -119,6 +119,18 @@ def test_workloads_scaled(wtmod, oracle_mod, cfg, n):
     check_against_oracle(wtmod, oracle_mod, S, sigma, f"{cfg} n={n}")
 
 
+@pytest.mark.parametrize("n,sigma,dtype", [((4096 * 4096) + 4099, (1 << 17) + 3, np.uint32),
+                                           ((4096 * 8192) + 12289, (1 << 16), np.uint16)])
+def test_tile_prefixes_over_several_blocks(wtmod, oracle_mod, n, sigma, dtype):
+    """Levels of more than 4096 tiles take their tile prefixes from the
+    multi-block pass (a decoupled look-back between its blocks): 32-bit
+    levels of 4096 symbols per tile and 16-bit levels of 8192, a ragged last
+    tile and a ragged last block, against the oracle."""
+    rng = np.random.default_rng(n)
+    S = rng.integers(0, sigma, n).astype(dtype)
+    check_against_oracle(wtmod, oracle_mod, S, sigma, f"multi-block tile prefixes n={n} sigma={sigma}")
+
+
 def test_standalone_rank_select_matches(wtmod, oracle_mod):
     for n, sigma in [(0, 8), (1, 2), (4097, 5), (300001, 256), (70000, 1 << 20)]:
         rng = np.random.default_rng(n)
