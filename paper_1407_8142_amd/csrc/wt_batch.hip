@@ -12,23 +12,28 @@
 //                             by the block itself
 //   tables (job)              C (unless its histogram wrote it), the node
 //                             tables D_l, the directory tails, the tile
-//                             prefixes of level 0, the first fused level
+//                             prefixes of level 0, the first fused level and
+//                             the fused segments' starts
 //   level tile (job, l, t)    one tile of the level pass (bits, directories,
 //                             stable split and scatter, count-ahead of l+1);
 //                             byte-symbol and wider tiles are separate phases
-//   fused segment (job, s)    the job's tail levels in LDS on one
+//   fused segment (job, s)    the job's tail levels on chip on one
 //                             node-aligned segment, once every node fits
-// The block that finishes the last tile of a level scans the count-ahead
-// totals into the next level's tile prefixes and marks that level ready.
 //
 // Two launch forms, same items and outputs:
 //  * one launch per phase (the default): a kernel built for that phase's
-//    kind only, items assigned statically (chunk per block); kernel
-//    boundaries order the phases, so no wait ever spins and no cross-XCD
-//    write-back is needed between items;
+//    kind only (and, for a level phase whose tiles take one variant, for that
+//    variant only).  The tables phase lists the live items of level 0 and of
+//    the fused phase, and a set-up launch before each level l >= 1 scans the
+//    count-ahead totals into the level's tile prefixes and lists its live
+//    tiles; level and fused launches take their items from those lists.
+//    Kernel boundaries order the phases, so no wait ever spins and no
+//    cross-XCD write-back is needed between items;
 //  * one persistent launch over the whole queue: blocks take chunks of items
 //    from a global head counter and wait, with release/acquire fences, for
-//    the items their own depends on.  A block only waits on items that
+//    the items their own depends on (the block that finishes the last tile
+//    of a level scans the count-ahead totals into the next level's tile
+//    prefixes and marks that level ready).  A block only waits on items that
 //    precede its own in the queue, and items are handed out in queue order to
 //    blocks that are running, so every wait ends whatever the residency
 //    (induction on queue position).  A wait is still bounded: after
