@@ -84,9 +84,11 @@ constexpr bool var_has(uint32_t var, uint32_t code) { return var == 0 || var == 
 
 // Waves per SIMD each kernel is compiled for: the register budget that
 // keeps its code free of spills (the per-phase kernels inline several tile
-// variants, and the job records take many scalar registers).
+// variants, and the job records take many scalar registers), except for the
+// fused tail levels and the mixed wider tiles, which run faster at five
+// waves with a few spilled registers than at four without (measured).
 constexpr int waves_for(uint32_t kinds, uint32_t var = 0) {
-    return kinds == kHasPrep ? 2 : (var != 0 ? (var == vcode(1, 1, true) ? 4 : 5) : (kinds == kHasLevelWide ? 5 : 4));
+    return kinds == kHasPrep ? 2 : (var != 0 ? (var == vcode(1, 1, true) ? 4 : 5) : (kinds == kHasLevelWide || kinds == kHasFused ? 5 : 4));
 }
 
 // Control words of one job (cleared by every run): status, done counters
