@@ -95,9 +95,11 @@ def level_pass_bytes(n: int, L: int, in_bytes: int, mid_bytes: int, passes: int,
     return out
 
 
-def traffic_per_launch(workload: str):
+def traffic_per_launch(workload: str, dominant: bool = False):
     """Measured HBM bytes per level-pass launch from committed rocprofv3
-    counter runs, or None when absent or taken on different kernel sources."""
+    counter runs (averaged over every level-pass launch, or with `dominant`
+    those of the most-launched level-pass kernel), or None when absent or
+    taken on different kernel sources."""
     try:
         doc = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -105,7 +107,13 @@ def traffic_per_launch(workload: str):
     ent = doc.get(workload)
     if not ent or ent.get("source_sha256") != source_sha():
         return None
-    return ent.get("traffic_bytes_per_launch")
+    if not dominant:
+        return ent.get("traffic_bytes_per_launch")
+    lp = {k: v for k, v in ent.get("kernels", {}).items() if "level_pass" in k or "pair_pass" in k}
+    if not lp:
+        return None
+    dom = max(lp, key=lambda k: lp[k]["launches"])
+    return lp[dom]["fetch_bytes"] + lp[dom]["write_bytes"]
 
 
 def cpu_info():
@@ -571,9 +579,11 @@ def main():
     lastbits = passes == L and L >= 2 and wt.histogram_path(n, sigma, S.dtype.itemsize) == wt.HIST_LEVELS
     per_pass = level_pass_bytes(n, L, S.dtype.itemsize, mid, passes, lastbits)
     per_pass_ms = [sum(launches[i::passes]) / args.steps for i in range(passes)]
-    # The dominant kernel: the level passes (the last level's directory
-    # pass, when there is one, is a different and much lighter kernel).
-    npass = passes - 1 if lastbits else passes
+    # The dominant kernel: the level passes.  For byte alphabets that is the
+    # pass of levels 0..L-3; level L-2's pass (which also writes the last
+    # level's bits, and no sequence) and the last level's directory pass are
+    # other kernels, reported beside it.
+    npass = passes - 2 if lastbits and passes >= 3 else (passes - 1 if lastbits else passes)
     lp_ms = sum(per_pass_ms[:npass]) * args.steps
     lp_bytes = sum(per_pass[:npass]) * args.steps
     avg_launch_ms = lp_ms / (npass * args.steps)
@@ -581,7 +591,7 @@ def main():
     achieved = avg_bytes / (avg_launch_ms / 1e3) / 1e9
     log(f"[bench] {'levels per pass: 1' if passes == L else 'levels per pass: 2'}; ms per pass: "
         + " ".join(f"{x:.4f}" for x in per_pass_ms))
-    traffic = traffic_per_launch(args.workload if n == n_default else "")
+    traffic = traffic_per_launch(args.workload if n == n_default else "", dominant=lastbits and passes >= 3)
     probe = copy_probe()
     step_bytes = model_bytes(n, L, S.dtype.itemsize)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -589,13 +599,17 @@ def main():
             "achievable": probe, "frac_of_tile_copy": round(achieved / probe["copy_tile"], 4) if probe else None,
             "step_model_bytes": step_bytes,
             "step_frac": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "kernel": ("level_pass (levels 0..L-2; level L-2 also writes the last level's bits)" if lastbits
+            "kernel": ("level_pass_u8 (levels 0..L-3)" if lastbits and passes >= 3
                        else "level_pass (all levels)") if passes == L else
                       "pair_pass (two levels per launch; an odd last level by level_pass)",
             "passes_per_build": passes, "avg_launch_ms": round(avg_launch_ms, 5),
             "algorithmic_bytes_per_launch": round(avg_bytes), "level_pass_share_of_step":
                 round(lp_ms / args.steps / ms_per_step_timed, 3),
             "ms_per_launch": [round(x, 5) for x in per_pass_ms],
+            "level_L_minus_2": ({"kernel": "level_pass_u8 of level L-2 (also writes the last level's bits, "
+                                           "no sequence)", "ms": round(per_pass_ms[-2], 5), "bytes": per_pass[-2],
+                                 "GBps": round(per_pass[-2] / (per_pass_ms[-2] / 1e3) / 1e9, 1)}
+                                if lastbits and passes >= 3 else None),
             "last_level": ({"kernel": "level_dirs (directories over the last level's bits)",
                             "ms": round(per_pass_ms[-1], 5), "bytes": per_pass[-1]} if lastbits else None),
             "launch_timing": "K steps before the timed ones, each level-pass launch carrying its start and "

@@ -27,11 +27,26 @@ def hipcc_flags() -> list[str]:
 
 
 def build_library(verbose: bool = False) -> str:
+    """One object per source, compiled in parallel, then one link."""
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        flags = [f for f in hipcc_flags() if f != "-shared"]
+        cmd = [HIPCC, *flags, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+        objs.append(obj)
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *hipcc_flags(), "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
+    for obj in objs:
+        os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 
