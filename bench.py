@@ -339,8 +339,9 @@ def batch_leg(count: int, steps: int, tune=None, per_seq_check: bool = True):
     if tune is None:
         best, table, fused = autotune.autotune(b)
     else:
-        best, table, fused = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), [], 1
-        wt.set_fused_levels(1)
+        fused = tune[3] if len(tune) > 3 else 1
+        best, table = wt.Tune(mode=tune[0], blocks_per_cu=tune[1], chunk=tune[2], spin_limit=0), []
+        wt.set_fused_levels(fused)
     log(f"[batch] best tune {best.as_dict()} fused={fused}: " + ", ".join(
         f"{r['tune']['mode']}/{r['tune']['blocks_per_cu']}/{r['tune']['chunk']}/f{int(r['fused'])}={r['ms']}"
         for r in table))
@@ -495,7 +496,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched build (no per-sequence comparison) and print its object")
-    ap.add_argument("--batch-tune", default=None, help="MODE,BLOCKS_PER_CU,CHUNK instead of autotuning")
+    ap.add_argument("--batch-tune", default=None, help="MODE,BLOCKS_PER_CU,CHUNK[,FUSED_LEVELS] instead of autotuning "
+                    "(fused levels as wt_set_fused_levels takes them; default 1)")
     ap.add_argument("--no-alphabets", action="store_true",
                     help="skip the large-alphabet builds (n = 2^27 32-bit symbols, sigma 2^16 and 2^20)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
