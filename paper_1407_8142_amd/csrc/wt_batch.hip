@@ -998,11 +998,20 @@ static int make_batch_plan(const wt_job *jobs, uint32_t njobs, HostPlan &hp) {
     hp.phase_first.push_back(0);
     for (uint32_t i = 0; i < njobs; ++i)
         if (!hp.jobs[i].job_hist) add(i, kKindHist, hp.jobs[i].T0);
+    // The whole-job histograms and the tables run one block per job, so a
+    // large job started last would set the phase's end: their items go
+    // largest first (by n, resp. by sigma, then n).
+    std::vector<uint32_t> ord(njobs);
+    for (uint32_t i = 0; i < njobs; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) { return hp.jobs[x].n > hp.jobs[y].n; });
     hp.phase_first.push_back((uint32_t)items);
-    for (uint32_t i = 0; i < njobs; ++i)
+    for (uint32_t i : ord)
         if (hp.jobs[i].job_hist) add(i, kKindJobHist, 1);
     hp.phase_first.push_back((uint32_t)items);
-    for (uint32_t i = 0; i < njobs; ++i) add(i, kKindPrep, 1);
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+        return hp.jobs[x].sigma != hp.jobs[y].sigma ? hp.jobs[x].sigma > hp.jobs[y].sigma : hp.jobs[x].n > hp.jobs[y].n;
+    });
+    for (uint32_t i : ord) add(i, kKindPrep, 1);
     for (uint32_t l = 0; l < maxL; ++l) {
         for (int wide = 0; wide < 2; ++wide) {  // byte-symbol tiles, then wider ones
             hp.phase_first.push_back((uint32_t)items);
