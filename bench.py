@@ -501,7 +501,7 @@ def main():
     ap.add_argument("--no-alphabets", action="store_true",
                     help="skip the large-alphabet builds (n = 2^27 32-bit symbols, sigma 2^16 and 2^20)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-pool", type=int, default=1000, help="distinct payloads the trace cycles over")
     ap.add_argument("--serve-h2d-seconds", type=float, default=1.5)
