@@ -24,7 +24,7 @@ from . import wt
 # fit, m >= 2 at most the last m)
 DEFAULT_CANDIDATES = ([(wt.BATCH_PERSISTENT, bpc, chunk, 1) for bpc, chunk in ((0, 1), (4, 4))] +
                       [(wt.BATCH_PER_PHASE, bpc, chunk, 1) for bpc, chunk in ((0, 4), (4, 4))] +
-                      [(wt.BATCH_PER_PHASE, bpc, 1, fused) for bpc in (0, 4) for fused in (1, 0, 8, 6, 4)])
+                      [(wt.BATCH_PER_PHASE, bpc, 1, fused) for bpc in (0, 4) for fused in (1, 0, 12, 10, 8, 6, 4)])
 
 
 def time_run(batch: "wt.Batch", tune: "wt.Tune", reps: int = 3) -> float:
